@@ -1,0 +1,216 @@
+"""Seeded synthetic inputs for the block Helmholtz solver.
+
+This module is shared by the CPU oracle, the tests and the benchmark. It
+holds no arithmetic of the solver itself: it only draws velocity models,
+the absorbing-layer attenuation profile, the frequency for a points-per-
+wavelength rule, and point-source right-hand sides.
+
+Conventions (the grid of the paper's discretisation, section on the
+Helmholtz forward problem): a domain of ``n`` cells per axis has nodes
+0..n, of which 1..n-1 are unknowns (homogeneous Dirichlet outside).
+Arrays are C-ordered with axis 0 of the *solver* fastest, i.e. numpy shape
+``(nz, nx)`` in 2D and ``(nz, ny, nx)`` in 3D, z being depth. Depth index 0
+of the unknowns is the first row below the free surface.
+
+The paper's experiments use the SEG/EAGE salt model, which is not
+available here; the layered models below take its velocity range
+(1.5-4.5 km/s) and the points-per-wavelength rule of the multigrid
+experiments instead.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Problem", "gradient_model_2d", "layered_model", "layer_gamma",
+    "omega_for_ppw", "surface_sources", "random_rhs", "config",
+    "CONFIGS",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """A Helmholtz instance: model, attenuation, frequency and sources."""
+    dim: int
+    n: tuple            # cells per axis, solver order (x, [y,] z)
+    h: tuple            # spacing per axis, solver order
+    m: np.ndarray       # squared slowness, float64, numpy shape (nz,[ny,]nx)
+    gamma: np.ndarray   # dimensionless attenuation incl. absorbing layer
+    omega: float
+    Q: np.ndarray       # complex128 [nrhs][N], each RHS contiguous, x fastest
+    src: list           # source node indices (numpy order tuples)
+    shift: float = 0.2
+    levels: int = 3
+    nu_pre: int = 2
+    nu_post: int = 2
+    jacobi_weight: float = 0.8
+    restart: int = 5
+    tol: float = 1e-6
+    name: str = ""
+
+    @property
+    def N(self) -> int:
+        return int(np.prod([c - 1 for c in self.n]))
+
+    @property
+    def nrhs(self) -> int:
+        return int(self.Q.shape[0])
+
+
+def _axis_nodes(n: int) -> np.ndarray:
+    """Positions (in cells) of the unknown nodes 1..n-1 along one axis."""
+    return np.arange(1, n, dtype=np.float64)
+
+
+def gradient_model_2d(n: int, v0: float = 1.5, v1: float = 3.0) -> np.ndarray:
+    """Velocity rising linearly with depth from v0 (surface) to v1 (bottom)."""
+    z = _axis_nodes(n) / n
+    v = v0 + (v1 - v0) * z
+    return np.repeat(v[:, None], n - 1, axis=1)
+
+
+def _gaussian_smooth(a: np.ndarray, sigma: float, truncate: float = 4.0) -> np.ndarray:
+    """Separable Gaussian filter with reflecting edges (scipy-free)."""
+    r = int(truncate * sigma + 0.5)
+    x = np.arange(-r, r + 1, dtype=np.float64)
+    k = np.exp(-0.5 * (x / sigma) ** 2)
+    k /= k.sum()
+    out = a
+    for ax in range(a.ndim):
+        pad = [(0, 0)] * a.ndim
+        pad[ax] = (r, r)
+        p = np.pad(out, pad, mode="symmetric")
+        acc = np.zeros_like(out)
+        for j, w in enumerate(k):
+            sl = [slice(None)] * a.ndim
+            sl[ax] = slice(j, j + out.shape[ax])
+            acc += w * p[tuple(sl)]
+        out = acc
+    return out
+
+
+def layered_model(dim: int, n: int, seed: int, nlayers: int = 8,
+                  vmin: float = 1.5, vmax: float = 4.5, pert: float = 0.1,
+                  sigma: float = 5.0) -> np.ndarray:
+    """Random layered velocity (km/s) plus a smooth random perturbation.
+
+    ``nlayers`` layers with sorted uniform interfaces in depth and sorted
+    uniform velocities in [vmin, vmax]; multiplied by (1 + p) with p a
+    Gaussian-smoothed white noise rescaled to max|p| = ``pert``.
+    """
+    rng = np.random.default_rng(seed)
+    ifc = np.sort(rng.uniform(0.0, 1.0, nlayers - 1))
+    vel = np.sort(rng.uniform(vmin, vmax, nlayers))
+    z = _axis_nodes(n) / n
+    vz = vel[np.searchsorted(ifc, z)]
+    shape = (n - 1,) * dim
+    v = np.broadcast_to(vz.reshape((-1,) + (1,) * (dim - 1)), shape).copy()
+    if pert > 0:
+        p = _gaussian_smooth(rng.standard_normal(shape), sigma)
+        p *= pert / np.abs(p).max()
+        v *= 1.0 + p
+    return v
+
+
+def layer_gamma(dim: int, n: int, width: int, gmax: float = 0.3,
+                top: bool = False, gamma0: float = 0.0) -> np.ndarray:
+    """Absorbing layer: gamma = gmax * (depth into the layer / width)^2.
+
+    The depth is measured in cells from the layer's inner edge, so it is 1
+    on the (Dirichlet) boundary node itself. All faces are absorbing except
+    the top (z = 0) free surface unless ``top``. ``gamma0`` is a constant
+    interior attenuation added everywhere.
+    """
+    k = _axis_nodes(n)
+    lo = np.maximum(width - k, 0.0) / width
+    hi = np.maximum(k - (n - width), 0.0) / width
+    both = np.maximum(lo, hi)
+    zprof = both if top else hi
+    if dim == 2:
+        g = np.maximum(zprof[:, None], both[None, :])
+    else:
+        g = np.maximum(np.maximum(zprof[:, None, None], both[None, :, None]),
+                       both[None, None, :])
+    return gamma0 + gmax * g ** 2
+
+
+def omega_for_ppw(vmin: float, ppw: float, h: float) -> float:
+    """Angular frequency giving ``ppw`` grid points per shortest wavelength."""
+    return 2.0 * math.pi * vmin / (ppw * h)
+
+
+def _spread(count: int, n: int, width: int) -> list:
+    """``count`` node indices (0-based unknowns) evenly over the non-layer span."""
+    lo, hi = width, n - width
+    return [int(round(lo + (hi - lo) * (i + 0.5) / count)) - 1 for i in range(count)]
+
+
+def surface_sources(dim: int, n: int, grid: tuple, width: int, depth: int = 0):
+    """Point sources on the first unknown row below the surface.
+
+    ``grid`` = (count along x,) in 2D or (count along x, count along y) in
+    3D. Returns numpy-order index tuples.
+    """
+    if dim == 2:
+        return [(depth, x) for x in _spread(grid[0], n, width)]
+    return [(depth, y, x) for y in _spread(grid[1], n, width)
+            for x in _spread(grid[0], n, width)]
+
+
+def point_rhs(dim: int, n: int, h: float, src: list) -> np.ndarray:
+    """Finite-volume delta: amplitude h^-dim at one node per source."""
+    N = (n - 1) ** dim
+    Q = np.zeros((len(src), N), dtype=np.complex128)
+    shape = (n - 1,) * dim
+    for s, idx in enumerate(src):
+        Q[s, np.ravel_multi_index(idx, shape)] = h ** (-dim)
+    return Q
+
+
+def random_rhs(N: int, nrhs: int, seed: int) -> np.ndarray:
+    """Dense complex Gaussian right-hand sides [nrhs][N]."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((nrhs, N)) + 1j * rng.standard_normal((nrhs, N)))
+
+
+def _make(dim, n, v, width, ppw, srcgrid, name, levels, restart, top=False):
+    h = 1.0 / n
+    m = 1.0 / v ** 2
+    gamma = layer_gamma(dim, n, width, top=top)
+    omega = omega_for_ppw(float(v.min()), ppw, h)
+    src = surface_sources(dim, n, srcgrid, width)
+    Q = point_rhs(dim, n, h, src)
+    return Problem(dim=dim, n=(n,) * dim, h=(h,) * dim, m=m, gamma=gamma,
+                   omega=omega, Q=Q, src=src, levels=levels, restart=restart,
+                   name=name)
+
+
+def config(k: int, n: int | None = None, nsrc: tuple | None = None,
+           levels: int | None = None) -> Problem:
+    """The benchmark configurations (1-based), optionally resized.
+
+    1: 2D 128^2, linear gradient 1.5->3.0 km/s, 16-cell layer, 10 ppw,
+       4 sources, 3 levels, FGMRES(10).
+    2: 3D 128^3, seeded 8-layer model + 10% smooth perturbation, 12-cell
+       layer, 8 ppw, 32 sources (8x4), 4 levels, FGMRES(5). Seed 2.
+    3: as 2 at 192^3 with 64 sources (8x8). Seed 3.
+    """
+    if k == 1:
+        n = n or 128
+        g = nsrc or (4,)
+        return _make(2, n, gradient_model_2d(n), 16, 10.0, g, "cfg1", levels or 3, 10)
+    if k == 2:
+        n = n or 128
+        g = nsrc or (8, 4)
+        return _make(3, n, layered_model(3, n, 2), 12, 8.0, g, "cfg2", levels or 4, 5)
+    if k == 3:
+        n = n or 192
+        g = nsrc or (8, 8)
+        return _make(3, n, layered_model(3, n, 3), 12, 8.0, g, "cfg3", levels or 4, 5)
+    raise ValueError(k)
+
+
+CONFIGS = (1, 2, 3)
