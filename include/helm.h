@@ -1,0 +1,168 @@
+/*
+ * helm.h -- C ABI of the MI355X block shifted-Laplacian Helmholtz solver.
+ *
+ * Problem (Treister & Haber, "Full waveform inversion guided by travel time
+ * tomography", eq:helm and eq:LinearSystem): for many right-hand sides q_s
+ * solve H u_s = q_s with
+ *     H = -Lap_h - omega^2 diag(m (1 - i gamma)),
+ * the second-order 5-point (2D) / 7-point (3D) finite-difference Laplacian on
+ * a vertex-centred grid with homogeneous Dirichlet values outside. gamma is
+ * dimensionless (the paper's gamma/omega) and carries the absorbing layer;
+ * the paper's sign convention differs by negating q.
+ *
+ * Method (section "Solving the Helmholtz equation for multiple right hand
+ * sides" and section 5.3): block FGMRES(m) right-preconditioned by a
+ * multigrid cycle for the shifted operator M = H with gamma -> gamma + shift
+ * (the paper adds a positive constant to gamma; 0.2 in its experiments).
+ * The cycle uses damped Jacobi relaxation (weight 0.8, 2 pre + 2 post),
+ * full-weighting restriction R = 2^-d P^T, d-linear prolongation P, Galerkin
+ * coarse operators R M P (the two-grid cycle algorithm, recursively) and an
+ * LU-based solve of the coarsest grid for the whole block.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns helm_status; nothing throws across the ABI. On error
+ *    helm_last_error() returns a thread-local message.
+ *  - Complex numbers are interleaved (re, im) doubles.
+ *  - Blocks of right-hand sides / solutions are DEVICE arrays of complex128
+ *    laid out [nrhs][N]: each right-hand side contiguous, grid axis 0 fastest
+ *    (N = prod(n[a]-1)). The library converts to its own internal layout.
+ *  - Setup inputs (m, gamma) are HOST FP64 arrays of N entries, copied in.
+ *  - `stream` is a hipStream_t (NULL = default stream). All device work of a
+ *    call is ordered on that stream; calls that return host values
+ *    synchronise it.
+ *  - The caller owns Q, U and any workspace; the handle owns the hierarchy.
+ *  - One handle must not be used by two threads at once.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_MAX_LEVELS 8
+
+typedef struct helm_ctx* helm_handle;
+
+typedef enum {
+  HELM_OK = 0,
+  HELM_ERR_INVALID_ARG = 1,   /* bad shape, level count, pointer or option  */
+  HELM_ERR_OOM = 2,           /* device allocation failed                   */
+  HELM_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed */
+  HELM_ERR_NOT_CONVERGED = 4, /* U holds the last iterate, info is filled   */
+  HELM_ERR_BREAKDOWN = 5,     /* rank-deficient block that could not be handled */
+  HELM_ERR_NONFINITE = 6,     /* NaN/Inf in m, gamma or Q                    */
+  HELM_ERR_UNSUPPORTED = 7    /* valid request this build does not support  */
+} helm_status;
+
+enum { HELM_FP64 = 0, HELM_MIXED = 1 };
+/* Coarsest-grid solve: exact (dense inverse of the Galerkin operator, FP64
+ * Gauss-Jordan at setup, applied as one matrix product for the block),
+ * learned network, none (the coarsest level is only relaxed), or
+ * coarse_iters steps of GMRES from zero per column (an inexact iterative
+ * coarsest solve, which the paper discusses in section 5.3 for coarse grids
+ * too large to factor). */
+enum { HELM_COARSE_LU = 0, HELM_COARSE_LEARNED = 1, HELM_COARSE_NONE = 2, HELM_COARSE_GMRES = 3 };
+/* Cycle shape below the finest level: V (one recursive call) or W (two;
+ * the two-grid cycle text). K is reserved and rejected as unsupported. */
+enum { HELM_CYCLE_V = 0, HELM_CYCLE_W = 1, HELM_CYCLE_K = 2 };
+
+typedef struct {
+  int32_t dim;                 /* 2 or 3 */
+  int32_t n[3];                /* cells per axis, axis 0 fastest; unknowns n-1;
+                                  n[a] % 2^(levels-1) == 0; n[2] ignored in 2D */
+  double h[3];                 /* spacing per axis (> 0) */
+  const double* m;             /* HOST [N] squared slowness (> 0) */
+  const double* gamma;         /* HOST [N] dimensionless attenuation (>= 0) */
+  double omega;                /* angular frequency (> 0) */
+  double shift;                /* beta >= 0 added to gamma in the preconditioner */
+  int32_t levels;              /* 1..HELM_MAX_LEVELS; coarsest must have >= 1 unknown/axis */
+  int32_t nu_pre[HELM_MAX_LEVELS];      /* Jacobi sweeps before the coarse correction */
+  int32_t nu_post[HELM_MAX_LEVELS];     /* and after it */
+  double jacobi_weight[HELM_MAX_LEVELS];/* damping per level (paper: 0.8) */
+  int32_t precision;           /* HELM_FP64 or HELM_MIXED (FP32 cycle, BF16 fields at
+                                  levels >= 2, FP64 outer Krylov) */
+  int32_t coarse;              /* HELM_COARSE_* */
+  int32_t cycle;               /* HELM_CYCLE_* */
+  int32_t coarse_iters;        /* GMRES steps for HELM_COARSE_GMRES (1..48) */
+  const void* net;             /* HOST weights blob for HELM_COARSE_LEARNED (or NULL) */
+  size_t net_bytes;
+} helm_setup_desc;
+
+/* Fill `d` with the paper's defaults: shift 0.2, 2+2 sweeps at 0.8, V-cycle,
+ * FP64, LU coarsest (20 GMRES steps if HELM_COARSE_GMRES is chosen),
+ * 3 levels. Geometry, m, gamma and omega are left zero. */
+void helm_setup_desc_default(helm_setup_desc* d);
+
+typedef struct {
+  int32_t restart;     /* m of FGMRES(m) (paper: 5) */
+  int32_t max_cycles;  /* cap on preconditioner applications (Arnoldi steps) */
+  int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs) */
+  int32_t warm_start;  /* 1: U holds an initial guess */
+  int32_t reorth;      /* 1: second block Gram-Schmidt pass + second CholQR pass */
+} helm_solve_opts;
+
+typedef struct {
+  int32_t cycles;       /* Arnoldi steps = preconditioner applications (the paper's #Cyc) */
+  int32_t restarts;
+  int32_t converged_all;
+  int32_t fallback_used;/* learned coarse solve replaced by the exact one */
+  double t_solve_ms;    /* device time of the solve (hip events) */
+  double* relres;       /* HOST [nrhs] or NULL: final FP64 ||q_s - H u_s|| / ||q_s|| */
+  int32_t* converged;   /* HOST [nrhs] or NULL */
+} helm_solve_info;
+
+/* Build the hierarchy: fine coefficients, Galerkin operators per level
+ * (two-grid cycle text: A_c = P^T A P), and the coarsest solve (LU of the
+ * coarsest grid for a block of RHS). Synchronises `stream`. */
+helm_status helm_setup(const helm_setup_desc* desc, void* stream, helm_handle* out);
+void helm_destroy(helm_handle h);
+
+/* Bytes of device workspace helm_solve_block needs for `nrhs`, `restart`. */
+helm_status helm_workspace_size(helm_handle h, int32_t nrhs, int32_t restart, size_t* bytes);
+
+/* Solve H U = Q (block FGMRES, section 5.3) until every column satisfies
+ * ||q_s - H u_s|| / ||q_s|| <= tol in FP64 (a zero column is converged at 0).
+ * Q, U: DEVICE complex128 [nrhs][N]. workspace: DEVICE, >= helm_workspace_size
+ * bytes, or NULL to let the handle allocate and cache it. info: HOST, may be
+ * NULL. Returns HELM_ERR_NOT_CONVERGED (U = last iterate) if max_cycles is hit. */
+helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U, double tol,
+                             const helm_solve_opts* opts, void* workspace, size_t ws_bytes,
+                             helm_solve_info* info, void* stream);
+
+/* relres[s] = ||q_s - H u_s|| / ||q_s|| in FP64 (0 for a zero q_s).
+ * Q, U: DEVICE complex128 [nrhs][N]; relres: HOST [nrhs]. */
+helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void* U,
+                          double* relres, void* stream);
+
+/* Y = H X (op 0) or Y = M X (op 1, shifted), in FP64 (eq:LinearSystem).
+ * X, Y: DEVICE complex128 [nrhs][N]. */
+helm_status helm_apply(helm_handle h, int32_t op, int32_t nrhs, const void* X, void* Y,
+                       void* stream);
+
+/* Z = one multigrid cycle applied to R (the preconditioner, in the handle's
+ * precision). R, Z: DEVICE complex128 [nrhs][N]. */
+helm_status helm_precond(helm_handle h, int32_t nrhs, const void* R, void* Z, void* stream);
+
+/* Unknowns per axis of level l (0 = finest). */
+helm_status helm_level_dims(helm_handle h, int32_t level, int32_t nu[3]);
+
+/* Copy the operator of level l >= 1 to HOST `st` as FP64 complex
+ * [N_l][3^dim] (entry (ox+1) + 3(oy+1) [+ 9(oz+1)] couples node i to node
+ * i + offset), converted from the stored precision. */
+helm_status helm_level_stencil(helm_handle h, int32_t level, double* st);
+
+/* E = coarsest-grid solve applied to R (as used inside the cycle).
+ * R, E: DEVICE complex128 [nrhs][N_coarsest]. */
+helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* E, void* stream);
+
+const char* helm_status_string(helm_status s);
+const char* helm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

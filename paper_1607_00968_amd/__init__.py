@@ -1,0 +1,259 @@
+"""Python binding of libhelm.so, the MI355X block shifted-Laplacian Helmholtz solver.
+
+The binding only marshals arguments: every step of the solve runs in the
+library's HIP kernels. PyTorch provides device memory (complex128 CUDA
+tensors) and the current stream. The functions mirror ``include/helm.h``:
+
+    h = helm_setup(dim, n, h, m, gamma, omega, ...)
+    info = helm_solve_block(h, Q, U, tol, restart=5, ...)
+    relres = helm_residual(h, Q, U)
+
+``Q`` and ``U`` are complex128 tensors on the GPU, shaped ``[nrhs, N]``
+(each right-hand side contiguous, grid axis 0 fastest). If the shared library
+is missing the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "HelmError", "lib", "LIBPATH", "Handle", "helm_setup", "helm_solve_block",
+    "helm_residual", "helm_apply", "helm_precond", "helm_level_stencil",
+    "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "ABI_SYMBOLS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libhelm.so")
+MAX_LEVELS = 8
+
+HELM_OK, HELM_ERR_INVALID_ARG, HELM_ERR_OOM, HELM_ERR_DEVICE = 0, 1, 2, 3
+HELM_ERR_NOT_CONVERGED, HELM_ERR_BREAKDOWN, HELM_ERR_NONFINITE, HELM_ERR_UNSUPPORTED = 4, 5, 6, 7
+PRECISION = {"fp64": 0, "mixed": 1}
+COARSE = {"lu": 0, "learned": 1, "none": 2, "gmres": 3}
+CYCLE = {"V": 0, "W": 1, "K": 2}
+
+ABI_SYMBOLS = (
+    "helm_setup_desc_default", "helm_setup", "helm_destroy", "helm_workspace_size",
+    "helm_solve_block", "helm_residual", "helm_apply", "helm_precond",
+    "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
+    "helm_status_string", "helm_last_error",
+)
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"helm status {status}: {msg}")
+        self.status = status
+
+
+class SetupDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
+        ("m", C.c_void_p), ("gamma", C.c_void_p), ("omega", C.c_double),
+        ("shift", C.c_double), ("levels", C.c_int32),
+        ("nu_pre", C.c_int32 * MAX_LEVELS), ("nu_post", C.c_int32 * MAX_LEVELS),
+        ("jacobi_weight", C.c_double * MAX_LEVELS), ("precision", C.c_int32),
+        ("coarse", C.c_int32), ("cycle", C.c_int32), ("coarse_iters", C.c_int32),
+        ("net", C.c_void_p), ("net_bytes", C.c_size_t),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_cycles", C.c_int32), ("block_size", C.c_int32),
+                ("warm_start", C.c_int32), ("reorth", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("restarts", C.c_int32), ("converged_all", C.c_int32),
+                ("fallback_used", C.c_int32), ("t_solve_ms", C.c_double),
+                ("relres", C.c_void_p), ("converged", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhelm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with "
+                              "`python -m paper_1607_00968_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIBPATH)
+        P, I, D = C.c_void_p, C.c_int32, C.c_double
+        L.helm_setup_desc_default.argtypes = [C.POINTER(SetupDesc)]
+        L.helm_setup.argtypes = [C.POINTER(SetupDesc), P, C.POINTER(P)]
+        L.helm_destroy.argtypes = [P]
+        L.helm_workspace_size.argtypes = [P, I, I, C.POINTER(C.c_size_t)]
+        L.helm_solve_block.argtypes = [P, I, P, P, D, C.POINTER(SolveOpts), P, C.c_size_t,
+                                       C.POINTER(SolveInfo), P]
+        L.helm_residual.argtypes = [P, I, P, P, P, P]
+        L.helm_apply.argtypes = [P, I, I, P, P, P]
+        L.helm_precond.argtypes = [P, I, P, P, P]
+        L.helm_level_dims.argtypes = [P, I, P]
+        L.helm_level_stencil.argtypes = [P, I, P]
+        L.helm_coarse_solve.argtypes = [P, I, P, P, P]
+        L.helm_status_string.restype = C.c_char_p
+        L.helm_status_string.argtypes = [I]
+        L.helm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=()):
+    if st != HELM_OK and st not in allow:
+        raise HelmError(st, lib().helm_last_error().decode(errors="replace"))
+    return st
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_block(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.dim() == 2
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor [nrhs, N]")
+    return C.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns a helm_handle (the device hierarchy)."""
+
+    def __init__(self, ptr, dim, n, levels, precision):
+        self.ptr = ptr
+        self.dim = dim
+        self.n = tuple(n)
+        self.levels = levels
+        self.precision = precision
+        self.N = int(np.prod([c - 1 for c in self.n]))
+
+    def close(self):
+        if self.ptr:
+            lib().helm_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _per_level(v, levels, typ):
+    if np.isscalar(v):
+        v = [v] * levels
+    v = list(v) + [v[-1]] * (MAX_LEVELS - len(v))
+    return (typ * MAX_LEVELS)(*v[:MAX_LEVELS])
+
+
+def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_post=2,
+               jacobi_weight=0.8, precision="fp64", coarse="lu", cycle="V", coarse_iters=20,
+               net=None, stream=None) -> Handle:
+    """Build the hierarchy. m, gamma: host float64 arrays of N entries."""
+    d = SetupDesc()
+    lib().helm_setup_desc_default(C.byref(d))
+    d.dim = dim
+    nn = list(n) + [1] * (3 - len(n))
+    hh = list(h) + [1.0] * (3 - len(h))
+    for a in range(3):
+        d.n[a] = int(nn[a])
+        d.h[a] = float(hh[a])
+    m = np.ascontiguousarray(m, dtype=np.float64).ravel()
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64).ravel()
+    d.m = m.ctypes.data
+    d.gamma = gamma.ctypes.data
+    d.omega = float(omega)
+    d.shift = float(shift)
+    d.levels = int(levels)
+    d.nu_pre = _per_level(nu_pre, levels, C.c_int32)
+    d.nu_post = _per_level(nu_post, levels, C.c_int32)
+    d.jacobi_weight = _per_level(jacobi_weight, levels, C.c_double)
+    d.precision = PRECISION[precision]
+    d.coarse = COARSE[coarse]
+    d.cycle = CYCLE[cycle]
+    d.coarse_iters = int(coarse_iters)
+    blob = None
+    if net is not None:
+        blob = np.ascontiguousarray(np.frombuffer(net, dtype=np.uint8))
+        d.net = blob.ctypes.data
+        d.net_bytes = blob.nbytes
+    out = C.c_void_p()
+    _check(lib().helm_setup(C.byref(d), _stream(stream), C.byref(out)))
+    return Handle(out, dim, nn[:dim], levels, precision)
+
+
+def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:
+    b = C.c_size_t()
+    _check(lib().helm_workspace_size(hd.ptr, nrhs, restart, C.byref(b)))
+    return b.value
+
+
+def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
+                     warm_start=False, reorth=True, workspace=None, stream=None) -> dict:
+    """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ..."""
+    nrhs = Q.shape[0]
+    qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
+    if U.shape != Q.shape or Q.shape[1] != hd.N:
+        raise ValueError("Q and U must both be [nrhs, N]")
+    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(bool(reorth)))
+    rel = np.zeros(nrhs)
+    conv = np.zeros(nrhs, np.int32)
+    info = SolveInfo()
+    info.relres = rel.ctypes.data
+    info.converged = conv.ctypes.data
+    wp, wb = (None, 0) if workspace is None else (C.c_void_p(workspace.data_ptr()), workspace.numel()
+                                                   * workspace.element_size())
+    st = _check(lib().helm_solve_block(hd.ptr, nrhs, qp, up, float(tol), C.byref(o), wp, wb,
+                                       C.byref(info), _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
+    return {"status": st, "cycles": info.cycles, "restarts": info.restarts,
+            "converged_all": bool(info.converged_all), "fallback_used": bool(info.fallback_used),
+            "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool)}
+
+
+def helm_residual(hd: Handle, Q, U, stream=None) -> np.ndarray:
+    nrhs = Q.shape[0]
+    rel = np.zeros(nrhs)
+    _check(lib().helm_residual(hd.ptr, nrhs, _dev_block(Q, "Q"), _dev_block(U, "U"),
+                               rel.ctypes.data, _stream(stream)))
+    return rel
+
+
+def helm_apply(hd: Handle, X, Y, shifted=False, stream=None):
+    _check(lib().helm_apply(hd.ptr, 1 if shifted else 0, X.shape[0], _dev_block(X, "X"),
+                            _dev_block(Y, "Y"), _stream(stream)))
+    return Y
+
+
+def helm_precond(hd: Handle, R, Z, stream=None):
+    _check(lib().helm_precond(hd.ptr, R.shape[0], _dev_block(R, "R"), _dev_block(Z, "Z"),
+                              _stream(stream)))
+    return Z
+
+
+def helm_coarse_solve(hd: Handle, R, E, stream=None):
+    _check(lib().helm_coarse_solve(hd.ptr, R.shape[0], _dev_block(R, "R"), _dev_block(E, "E"),
+                                   _stream(stream)))
+    return E
+
+
+def helm_level_dims(hd: Handle, level: int):
+    nu = (C.c_int32 * 3)()
+    _check(lib().helm_level_dims(hd.ptr, level, nu))
+    return tuple(nu[a] for a in range(3))
+
+
+def helm_level_stencil(hd: Handle, level: int) -> np.ndarray:
+    """Stencil of level >= 1 as complex128 [N_l, 3^dim]."""
+    nu = helm_level_dims(hd, level)
+    ns = 27 if hd.dim == 3 else 9
+    st = np.zeros((int(np.prod(nu)), ns), np.complex128)
+    _check(lib().helm_level_stencil(hd.ptr, level, st.ctypes.data))
+    return st

@@ -1,0 +1,981 @@
+// helm.cpp -- host side of the solver: the C ABI of include/helm.h, the
+// multigrid hierarchy, the cycle scheduler and the block FGMRES driver.
+// Every arithmetic step runs in the HIP kernels of k_level / k_setup /
+// k_krylov; this file only sequences launches, owns device memory and
+// reads back the p per-column residual estimates once per Arnoldi step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "kernels.hpp"
+#include "learned.hpp"
+
+namespace helm {
+
+[[noreturn]] void fatal_combo(const char* where) {
+  std::fprintf(stderr, "helm: unsupported precision combination in %s\n", where);
+  std::abort();
+}
+
+static thread_local std::string g_err;
+
+static helm_status fail(helm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HCHECK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(e_ == hipErrorOutOfMemory ? HELM_ERR_OOM : HELM_ERR_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                              \
+  } while (0)
+
+static size_t psize(Prec p) { return p == P64 ? 16 : (p == P32 ? 8 : 4); }
+
+struct Level {
+  int nu[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  double ih[3] = {0, 0, 0};  // 1/h^2
+  int64_t npts = 0;
+  // coefficients: fine level uses diagonals, coarser levels stencils [N][NS]
+  c128* dH = nullptr;
+  c128* dM = nullptr;
+  c128* dw64 = nullptr;
+  c64* dM32 = nullptr;
+  c64* dw32 = nullptr;
+  c128* st64 = nullptr;
+  c64* st32 = nullptr;
+  // per-solve fields [N][P]
+  void* F = nullptr;
+  void* U0 = nullptr;
+  void* U1 = nullptr;
+  void* Rr = nullptr;
+  Prec pf = P64;  // field storage precision
+  Geo geo(int P) const {
+    Geo g;
+    g.nx = nu[0];
+    g.ny = nu[1];
+    g.nz = nu[2];
+    g.npts = npts;
+    g.P = P;
+    return g;
+  }
+};
+
+}  // namespace helm
+
+using namespace helm;
+
+struct helm_ctx {
+  int dim = 3;
+  int L = 0;
+  int precision = HELM_FP64;
+  int coarse = HELM_COARSE_LU;
+  int cycle = HELM_CYCLE_V;
+  int coarse_iters = 20;
+  // coarsest GMRES storage: basis, Hessenberg, coefficients
+  void* cg_mem = nullptr;
+  int cg_P = 0;
+  int nu_pre[HELM_MAX_LEVELS], nu_post[HELM_MAX_LEVELS];
+  double wj[HELM_MAX_LEVELS];
+  double omega = 0, shift = 0;
+  Level lv[HELM_MAX_LEVELS];
+  int64_t nc = 0;          // coarsest unknowns
+  c128* Minv64 = nullptr;  // dense coarsest inverse
+  c64* Minv32 = nullptr;
+  learned::Net* net = nullptr;
+  // cached per-solve field allocation
+  int fieldsP = 0;
+  void* fieldmem = nullptr;
+  // cached Krylov workspace
+  void* ws = nullptr;
+  size_t wsbytes = 0;
+  // K-cycle inner workspace (allocated with the fields)
+  std::vector<void*> kbuf;
+  double* hbuf = nullptr;  // pinned host scratch
+  size_t hbufn = 0;
+};
+
+namespace helm {
+
+static Prec field_prec(const helm_ctx* c, int l) {
+  if (c->precision == HELM_FP64) return P64;
+  if (l == 0) return P32;
+  if (l == c->L - 1) return P32;  // coarsest vectors stay FP32 (dense solve input)
+  return PBF;
+}
+static Prec comp_prec(const helm_ctx* c) { return c->precision == HELM_FP64 ? P64 : P32; }
+
+static const void* level_st(const helm_ctx* c, int l) {
+  return c->precision == HELM_FP64 ? (const void*)c->lv[l].st64 : (const void*)c->lv[l].st32;
+}
+static const void* level_dw(const helm_ctx* c, int l) {
+  return c->precision == HELM_FP64 ? (const void*)c->lv[l].dw64 : (const void*)c->lv[l].dw32;
+}
+
+__global__ void k_add_c128(int64_t n, const c128* __restrict__ x, c128* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = c128{y[i].re + x[i].re, y[i].im + x[i].im};
+}
+
+// One relaxation-family launch on level l (mode as launch_fine).
+static void level_op(helm_ctx* c, int l, int mode, int P, const void* u, const void* f, void* out, hipStream_t s) {
+  const Level& L = c->lv[l];
+  const Prec pf = field_prec(c, l), pt = comp_prec(c);
+  if (l == 0) {
+    const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+    launch_fine(mode, pf, pf, pf, pt, c->dim, L.geo(P), u, f, out, diag, level_dw(c, 0), L.ih, s);
+  } else {
+    launch_gal(mode, pf, pt, c->dim, L.geo(P), u, f, out, level_st(c, l), level_dw(c, l), s);
+  }
+}
+
+static void zero_field(helm_ctx* c, int l, int P, void* u, hipStream_t s) {
+  hipMemsetAsync(u, 0, psize(field_prec(c, l)) * c->lv[l].npts * P, s);
+}
+
+static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s);
+void field_axpy(helm_ctx* c, int l, int P, const void* x, void* y, hipStream_t s);
+
+// Multigrid cycle at level l for right-hand side f (level storage), result in
+// `out`; `tmp` is a second buffer of the same size (ping-pong for Jacobi).
+static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void* tmp, hipStream_t s) {
+  Level& L = c->lv[l];
+  if (l == c->L - 1) {
+    coarsest_solve(c, P, f, out, s);
+    return;
+  }
+  const int npre = c->nu_pre[l], npost = c->nu_post[l];
+  const int alternations = (npre >= 1 ? npre - 1 : 0) + npost;
+  void* a = (alternations % 2 == 0) ? out : tmp;
+  void* b = (a == out) ? tmp : out;
+  if (npre >= 1) {
+    level_op(c, l, 3, P, nullptr, f, a, s);
+    for (int k = 1; k < npre; ++k) {
+      level_op(c, l, 2, P, a, f, b, s);
+      std::swap(a, b);
+    }
+  } else {
+    zero_field(c, l, P, a, s);
+  }
+  level_op(c, l, 1, P, a, f, L.Rr, s);
+  Level& C = c->lv[l + 1];
+  const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
+  launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
+  cycle_rec(c, l + 1, P, C.F, C.U0, C.U1, s);
+  if (c->cycle == HELM_CYCLE_W && l + 1 < c->L - 1) {
+    // W-cycle: a second coarse cycle on the residual of the first result,
+    // e <- e + B(F - M e); F is free again and serves as ping-pong buffer.
+    level_op(c, l + 1, 1, P, C.U0, C.F, c->kbuf[l + 1], s);
+    cycle_rec(c, l + 1, P, c->kbuf[l + 1], C.U1, C.F, s);
+    field_axpy(c, l + 1, P, C.U1, C.U0, s);
+  }
+  launch_prolong_add(pc, pf, pt, c->dim, L.geo(P), C.geo(P), C.U0, a, s);
+  for (int k = 0; k < npost; ++k) {
+    level_op(c, l, 2, P, a, f, b, s);
+    std::swap(a, b);
+  }
+  (void)a;
+}
+
+// k steps of GMRES from zero on the coarsest grid, one independent GMRES per
+// column (classical Gram-Schmidt, applied twice), least squares by Givens
+// rotations. No host synchronisation: the step count is fixed.
+static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, hipStream_t s) {
+  const int l = c->L - 1;
+  const int k = c->coarse_iters;
+  const Level& L = c->lv[l];
+  const int64_t N = L.npts;
+  const Prec p = field_prec(c, l);
+  const size_t vb = (psize(p) * N * P + 255) / 256 * 256;
+  char* m = static_cast<char*>(c->cg_mem);
+  char* V = m;
+  c128* H = reinterpret_cast<c128*>(m + vb * (k + 1));
+  c128* Gc = H + (size_t)P * (k + 1) * k;
+  c128* G2 = Gc + (size_t)(k + 1) * P;
+  c128* Yc = G2 + (size_t)(k + 1) * P;
+  c128* part = Yc + (size_t)(k + 1) * P;
+  c128* Gs = part + gram_part_elems(P);
+  double* b2 = reinterpret_cast<double*>(Gs + 2 * P);
+  double* hn2 = b2 + P;
+  double* sc = hn2 + P;
+  auto vec = [&](int i) { return static_cast<void*>(V + vb * i); };
+  launch_colnorm2(p, N, P, P, f, part, Gs, b2, s);
+  launch_inv_sqrt(P, b2, sc, s);
+  launch_scale_cols(p, N, P, P, sc, f, vec(0), s);
+  PtrList vl{};
+  for (int j = 0; j < k; ++j) {
+    vl.p[j] = vec(j);
+    level_op(c, l, 0, P, vec(j), nullptr, vec(j + 1), s);
+    launch_gram(p, N, P, P, 1, j + 1, vl, vec(j + 1), part, Gc, s);
+    launch_block_update(0, p, p, N, P, P, 1, j + 1, vl, Gc, vec(j + 1), s);
+    launch_gram(p, N, P, P, 1, j + 1, vl, vec(j + 1), part, G2, s);
+    launch_block_update(0, p, p, N, P, P, 1, j + 1, vl, G2, vec(j + 1), s);
+    const int64_t ne = (int64_t)(j + 1) * P;
+    hipLaunchKernelGGL(k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G2, Gc);
+    launch_colnorm2(p, N, P, P, vec(j + 1), part, Gs, hn2, s);
+    launch_cg_hcol(P, j, k, Gc, hn2, H, sc, s);
+    launch_scale_cols(p, N, P, P, sc, vec(j + 1), vec(j + 1), s);
+  }
+  launch_cg_ls(P, k, H, b2, Yc, s);
+  launch_block_update(1, p, p, N, P, P, 1, k, vl, Yc, out, s);
+}
+
+static size_t coarse_gmres_bytes(const helm_ctx* c, int P) {
+  const int l = c->L - 1, k = c->coarse_iters;
+  const size_t vb = (psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256;
+  return vb * (k + 1) + 16 * ((size_t)P * (k + 1) * k + 3 * (size_t)(k + 1) * P + gram_part_elems(P) + 2 * P) +
+         8 * 3 * (size_t)P + 256;
+}
+
+static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s) {
+  const int l = c->L - 1;
+  if (c->coarse == HELM_COARSE_LU) {
+    if (c->precision == HELM_FP64)
+      launch_gemm(P64, c->nc, P, c->nc, c128{1, 0}, c->Minv64, c->nc, f, P, c128{0, 0}, out, P, s);
+    else
+      launch_gemm(P32, c->nc, P, c->nc, c128{1, 0}, c->Minv32, c->nc, f, P, c128{0, 0}, out, P, s);
+  } else if (c->coarse == HELM_COARSE_GMRES) {
+    coarse_gmres(c, P, f, out, s);
+  } else if (c->coarse == HELM_COARSE_LEARNED && c->net) {
+    learned::apply(c->net, c, l, P, f, out, s);
+  } else {
+    // relaxation only: nu_pre + nu_post damped Jacobi sweeps from zero
+    const int sweeps = std::max(1, c->nu_pre[l] + c->nu_post[l]);
+    void* tmp = c->lv[l].U1 == out ? c->lv[l].Rr : c->lv[l].U1;
+    void* a = (sweeps - 1) % 2 == 0 ? out : tmp;
+    void* b = a == out ? tmp : out;
+    level_op(c, l, 3, P, nullptr, f, a, s);
+    for (int k = 1; k < sweeps; ++k) {
+      level_op(c, l, 2, P, a, f, b, s);
+      std::swap(a, b);
+    }
+  }
+}
+
+}  // namespace helm
+
+// ---------------------------------------------------------------------------
+// Field allocation for a block of P columns.
+// ---------------------------------------------------------------------------
+static helm_status ensure_fields(helm_ctx* c, int P) {
+  if (c->fieldsP >= P && c->fieldmem) return HELM_OK;
+  if (c->fieldmem) {
+    hipFree(c->fieldmem);
+    c->fieldmem = nullptr;
+  }
+  size_t total = 0;
+  for (int l = 0; l < c->L; ++l) total += 5 * ((psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256);
+  HCHECK(hipMalloc(&c->fieldmem, total));
+  char* p = static_cast<char*>(c->fieldmem);
+  c->kbuf.assign(c->L, nullptr);
+  for (int l = 0; l < c->L; ++l) {
+    const size_t b = (psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256;
+    c->lv[l].F = p;
+    c->lv[l].U0 = p + b;
+    c->lv[l].U1 = p + 2 * b;
+    c->lv[l].Rr = p + 3 * b;
+    c->kbuf[l] = p + 4 * b;
+    p += 5 * b;
+  }
+  if (c->coarse == HELM_COARSE_GMRES) {
+    hipFree(c->cg_mem);
+    c->cg_mem = nullptr;
+    HCHECK(hipMalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
+  }
+  c->fieldsP = P;
+  return HELM_OK;
+}
+
+namespace helm {
+
+__global__ void k_field_axpy_c128(int64_t n, const c128* x, c128* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = c128{y[i].re + x[i].re, y[i].im + x[i].im};
+}
+__global__ void k_field_axpy_c64(int64_t n, const c64* x, c64* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = c64{y[i].re + x[i].re, y[i].im + x[i].im};
+}
+__global__ void k_field_axpy_cbf(int64_t n, const cbf* x, cbf* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n)
+    y[i] = cbf{f2bf(bf2f(y[i].re) + bf2f(x[i].re)), f2bf(bf2f(y[i].im) + bf2f(x[i].im))};
+}
+
+void field_axpy(helm_ctx* c, int l, int P, const void* x, void* y, hipStream_t s) {
+  const int64_t n = c->lv[l].npts * P;
+  const dim3 gr((unsigned)((n + 255) / 256));
+  switch (field_prec(c, l)) {
+    case P64: hipLaunchKernelGGL(k_field_axpy_c128, gr, dim3(256), 0, s, n, (const c128*)x, (c128*)y); break;
+    case P32: hipLaunchKernelGGL(k_field_axpy_c64, gr, dim3(256), 0, s, n, (const c64*)x, (c64*)y); break;
+    default: hipLaunchKernelGGL(k_field_axpy_cbf, gr, dim3(256), 0, s, n, (const cbf*)x, (cbf*)y); break;
+  }
+}
+
+}  // namespace helm
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void helm_setup_desc_default(helm_setup_desc* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->dim = 3;
+  d->shift = 0.2;
+  d->levels = 3;
+  for (int l = 0; l < HELM_MAX_LEVELS; ++l) {
+    d->nu_pre[l] = 2;
+    d->nu_post[l] = 2;
+    d->jacobi_weight[l] = 0.8;
+  }
+  d->precision = HELM_FP64;
+  d->coarse = HELM_COARSE_LU;
+  d->cycle = HELM_CYCLE_V;
+  d->coarse_iters = 20;
+}
+
+const char* helm_status_string(helm_status s) {
+  switch (s) {
+    case HELM_OK: return "ok";
+    case HELM_ERR_INVALID_ARG: return "invalid argument";
+    case HELM_ERR_OOM: return "out of device memory";
+    case HELM_ERR_DEVICE: return "device error";
+    case HELM_ERR_NOT_CONVERGED: return "not converged";
+    case HELM_ERR_BREAKDOWN: return "block breakdown";
+    case HELM_ERR_NONFINITE: return "non-finite input";
+    case HELM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown";
+}
+
+const char* helm_last_error(void) { return g_err.c_str(); }
+
+static void free_ctx(helm_ctx* c) {
+  if (!c) return;
+  for (int l = 0; l < c->L; ++l) {
+    Level& L = c->lv[l];
+    hipFree(L.dH);
+    hipFree(L.dM);
+    hipFree(L.dw64);
+    hipFree(L.dM32);
+    hipFree(L.dw32);
+    hipFree(L.st64);
+    hipFree(L.st32);
+  }
+  hipFree(c->Minv64);
+  hipFree(c->Minv32);
+  hipFree(c->fieldmem);
+  hipFree(c->cg_mem);
+  hipFree(c->ws);
+  if (c->hbuf) hipHostFree(c->hbuf);
+  if (c->net) learned::destroy(c->net);
+  delete c;
+}
+
+void helm_destroy(helm_handle h) { free_ctx(h); }
+
+helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out) {
+  if (!d || !out) return fail(HELM_ERR_INVALID_ARG, "null descriptor or output");
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return fail(HELM_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (d->levels < 2 || d->levels > HELM_MAX_LEVELS) return fail(HELM_ERR_INVALID_ARG, "levels must be 2..%d", HELM_MAX_LEVELS);
+  if (!(d->omega > 0) || !(d->shift >= 0) || !std::isfinite(d->omega) || !std::isfinite(d->shift))
+    return fail(HELM_ERR_INVALID_ARG, "omega must be > 0 and shift >= 0");
+  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED) return fail(HELM_ERR_INVALID_ARG, "bad precision");
+  if (d->coarse < HELM_COARSE_LU || d->coarse > HELM_COARSE_GMRES) return fail(HELM_ERR_INVALID_ARG, "bad coarse kind");
+  if (d->coarse == HELM_COARSE_GMRES && (d->coarse_iters < 1 || d->coarse_iters > 48))
+    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 1..48");
+  if (d->cycle < HELM_CYCLE_V || d->cycle > HELM_CYCLE_K) return fail(HELM_ERR_INVALID_ARG, "bad cycle kind");
+  if (d->cycle == HELM_CYCLE_K) return fail(HELM_ERR_UNSUPPORTED, "the K-cycle is not built in this library version");
+  const int f = 1 << (d->levels - 1);
+  int64_t N = 1;
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->n[a] < 2 * f || d->n[a] % f != 0)
+      return fail(HELM_ERR_INVALID_ARG, "n[%d]=%d must be a multiple of 2^(levels-1)=%d with >= 1 coarsest unknown", a,
+                  d->n[a], f);
+    if (!(d->h[a] > 0)) return fail(HELM_ERR_INVALID_ARG, "h[%d] must be > 0", a);
+    N *= d->n[a] - 1;
+  }
+  for (int l = 0; l < d->levels; ++l)
+    if (d->nu_pre[l] < 0 || d->nu_post[l] < 0 || !std::isfinite(d->jacobi_weight[l]))
+      return fail(HELM_ERR_INVALID_ARG, "bad relaxation parameters at level %d", l);
+  if (!d->m || !d->gamma) return fail(HELM_ERR_INVALID_ARG, "m and gamma are required");
+  for (int64_t i = 0; i < N; ++i) {
+    if (!std::isfinite(d->m[i]) || !std::isfinite(d->gamma[i]))
+      return fail(HELM_ERR_NONFINITE, "non-finite m or gamma at %lld", (long long)i);
+    if (!(d->m[i] > 0) || d->gamma[i] < 0) return fail(HELM_ERR_INVALID_ARG, "m must be > 0 and gamma >= 0");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  helm_ctx* c = new helm_ctx();
+  c->dim = d->dim;
+  c->L = d->levels;
+  c->precision = d->precision;
+  c->coarse = d->coarse;
+  c->cycle = d->cycle;
+  c->coarse_iters = d->coarse_iters;
+  c->omega = d->omega;
+  c->shift = d->shift;
+  for (int l = 0; l < HELM_MAX_LEVELS; ++l) {
+    c->nu_pre[l] = d->nu_pre[l];
+    c->nu_post[l] = d->nu_post[l];
+    c->wj[l] = d->jacobi_weight[l];
+  }
+  helm_status st = HELM_OK;
+  auto bail = [&](helm_status e) {
+    free_ctx(c);
+    return e;
+  };
+  // geometry per level
+  for (int l = 0; l < c->L; ++l) {
+    Level& L = c->lv[l];
+    L.npts = 1;
+    for (int a = 0; a < 3; ++a) {
+      if (a < c->dim) {
+        const int cells = d->n[a] >> l;
+        L.nu[a] = cells - 1;
+        L.h[a] = d->h[a] * (double)(1 << l);
+        L.ih[a] = 1.0 / (L.h[a] * L.h[a]);
+      } else {
+        L.nu[a] = 1;
+        L.h[a] = 1.0;
+        L.ih[a] = 0.0;
+      }
+      L.npts *= L.nu[a];
+    }
+    L.pf = field_prec(c, l);
+  }
+  const int NS = c->dim == 3 ? 27 : 9;
+  // fine coefficients
+  {
+    Level& L = c->lv[0];
+    double *dm = nullptr, *dg = nullptr;
+    if (hipMalloc(&dm, 8 * N) != hipSuccess || hipMalloc(&dg, 8 * N) != hipSuccess ||
+        hipMalloc(&L.dH, 16 * N) != hipSuccess || hipMalloc(&L.dM, 16 * N) != hipSuccess ||
+        hipMalloc(&L.dw64, 16 * N) != hipSuccess) {
+      hipFree(dm);
+      hipFree(dg);
+      return bail(fail(HELM_ERR_OOM, "setup: fine coefficients"));
+    }
+    hipMemcpyAsync(dm, d->m, 8 * N, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dg, d->gamma, 8 * N, hipMemcpyHostToDevice, s);
+    launch_fine_coef(c->dim, N, dm, dg, c->omega, c->shift, c->wj[0], L.ih, L.dH, L.dM, L.dw64, s);
+    hipStreamSynchronize(s);
+    hipFree(dm);
+    hipFree(dg);
+    if (c->precision == HELM_MIXED) {
+      if (hipMalloc(&L.dM32, 8 * N) != hipSuccess || hipMalloc(&L.dw32, 8 * N) != hipSuccess)
+        return bail(fail(HELM_ERR_OOM, "setup: fine FP32 coefficients"));
+      launch_narrow(N, L.dM, L.dM32, s);
+      launch_narrow(N, L.dw64, L.dw32, s);
+    }
+  }
+  // Galerkin levels
+  for (int l = 1; l < c->L; ++l) {
+    Level& L = c->lv[l];
+    Level& F = c->lv[l - 1];
+    if (hipMalloc(&L.st64, 16 * L.npts * NS) != hipSuccess || hipMalloc(&L.dw64, 16 * L.npts) != hipSuccess)
+      return bail(fail(HELM_ERR_OOM, "setup: level %d stencil", l));
+    if (l == 1)
+      launch_galerkin_from_fine(c->dim, F.geo(4), L.geo(4), F.dM, F.ih, L.st64, s);
+    else
+      launch_galerkin_from_gal(c->dim, F.geo(4), L.geo(4), F.st64, L.st64, s);
+    launch_gal_dw(c->dim, L.npts, L.st64, c->wj[l], L.dw64, s);
+    if (c->precision == HELM_MIXED) {
+      if (hipMalloc(&L.st32, 8 * L.npts * NS) != hipSuccess || hipMalloc(&L.dw32, 8 * L.npts) != hipSuccess)
+        return bail(fail(HELM_ERR_OOM, "setup: level %d FP32 stencil", l));
+      launch_narrow(L.npts * NS, L.st64, L.st32, s);
+      launch_narrow(L.npts, L.dw64, L.dw32, s);
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
+    return bail(fail(HELM_ERR_DEVICE, "setup: hierarchy kernels failed"));
+  // coarsest dense inverse
+  c->nc = c->lv[c->L - 1].npts;
+  if (c->coarse == HELM_COARSE_LU) {
+    const int64_t n = c->nc;
+    if (n > 24000) return bail(fail(HELM_ERR_UNSUPPORTED, "coarsest grid has %lld unknowns (> 24000)", (long long)n));
+    const int nb = 32;  // pivot block held in LDS by one workgroup
+    c128* work = nullptr;
+    if (hipMalloc(&c->Minv64, 16 * n * n) != hipSuccess ||
+        hipMalloc(&work, 16 * (2 * n * nb + nb * nb + 1)) != hipSuccess) {
+      hipFree(work);
+      return bail(fail(HELM_ERR_OOM, "setup: coarsest inverse (%lld unknowns)", (long long)n));
+    }
+    launch_assemble_dense(c->dim, c->lv[c->L - 1].geo(4), c->lv[c->L - 1].st64, c->Minv64, s);
+    const int rc = gauss_jordan_inverse(n, c->Minv64, nb, work, s);
+    hipFree(work);
+    if (rc != 0) return bail(fail(HELM_ERR_DEVICE, "setup: coarsest inversion failed (%d)", rc));
+    if (c->precision == HELM_MIXED) {
+      if (hipMalloc(&c->Minv32, 8 * n * n) != hipSuccess) return bail(fail(HELM_ERR_OOM, "setup: FP32 coarsest inverse"));
+      launch_narrow(n * n, c->Minv64, c->Minv32, s);
+      hipStreamSynchronize(s);
+      hipFree(c->Minv64);
+      c->Minv64 = nullptr;
+    }
+  } else if (c->coarse == HELM_COARSE_LEARNED) {
+    st = learned::create(c, d->net, d->net_bytes, &c->net, s);
+    if (st != HELM_OK) return bail(st);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
+    return bail(fail(HELM_ERR_DEVICE, "setup: device error"));
+  *out = c;
+  return HELM_OK;
+}
+
+helm_status helm_level_dims(helm_handle h, int32_t level, int32_t nu[3]) {
+  if (!h || !nu || level < 0 || level >= h->L) return fail(HELM_ERR_INVALID_ARG, "bad level");
+  for (int a = 0; a < 3; ++a) nu[a] = h->lv[level].nu[a];
+  return HELM_OK;
+}
+
+helm_status helm_level_stencil(helm_handle h, int32_t level, double* st) {
+  if (!h || !st || level < 1 || level >= h->L) return fail(HELM_ERR_INVALID_ARG, "bad level");
+  const int NS = h->dim == 3 ? 27 : 9;
+  HCHECK(hipDeviceSynchronize());
+  HCHECK(hipMemcpy(st, h->lv[level].st64, 16 * h->lv[level].npts * NS, hipMemcpyDeviceToHost));
+  return HELM_OK;
+}
+
+static int padP(int nrhs) { return (nrhs + 3) / 4 * 4; }
+
+static helm_status check_block(helm_handle h, int32_t nrhs, const void* a, const void* b) {
+  if (!h) return fail(HELM_ERR_INVALID_ARG, "null handle");
+  if (nrhs < 1 || nrhs > 256) return fail(HELM_ERR_INVALID_ARG, "nrhs must be 1..256");
+  if (!a || !b) return fail(HELM_ERR_INVALID_ARG, "null device pointer");
+  return HELM_OK;
+}
+
+// Scratch for the ABI helpers: internal copies of two blocks.
+static helm_status tmp_blocks(helm_ctx* c, int P, int64_t N, c128** A, c128** B) {
+  HCHECK(hipMalloc(A, 16 * N * P));
+  if (hipMalloc(B, 16 * N * P) != hipSuccess) {
+    hipFree(*A);
+    return fail(HELM_ERR_OOM, "temporary block");
+  }
+  (void)c;
+  return HELM_OK;
+}
+
+helm_status helm_apply(helm_handle h, int32_t op, int32_t nrhs, const void* X, void* Y, void* stream) {
+  helm_status st = check_block(h, nrhs, X, Y);
+  if (st != HELM_OK) return st;
+  if (op != 0 && op != 1) return fail(HELM_ERR_INVALID_ARG, "op must be 0 (H) or 1 (M)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = padP(nrhs);
+  const Level& L = h->lv[0];
+  c128 *A, *B;
+  if ((st = tmp_blocks(h, P, L.npts, &A, &B)) != HELM_OK) return st;
+  launch_to_internal(P64, L.npts, nrhs, P, X, A, s);
+  launch_fine(0, P64, P64, P64, P64, h->dim, L.geo(P), A, nullptr, B, op == 0 ? L.dH : L.dM, nullptr, L.ih, s);
+  launch_to_abi(P64, L.npts, nrhs, P, B, Y, s);
+  hipError_t e = hipStreamSynchronize(s);
+  hipFree(A);
+  hipFree(B);
+  HCHECK(e);
+  HCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+helm_status helm_precond(helm_handle h, int32_t nrhs, const void* R, void* Z, void* stream) {
+  helm_status st = check_block(h, nrhs, R, Z);
+  if (st != HELM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = padP(nrhs);
+  if ((st = ensure_fields(h, P)) != HELM_OK) return st;
+  Level& L = h->lv[0];
+  const Prec pf = field_prec(h, 0);
+  c128 *A, *B;
+  if ((st = tmp_blocks(h, P, L.npts, &A, &B)) != HELM_OK) return st;
+  launch_to_internal(pf, L.npts, nrhs, P, R, L.F, s);
+  cycle_rec(h, 0, P, L.F, A, B, s);
+  launch_to_abi(pf, L.npts, nrhs, P, A, Z, s);
+  hipError_t e = hipStreamSynchronize(s);
+  hipFree(A);
+  hipFree(B);
+  HCHECK(e);
+  HCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* E, void* stream) {
+  helm_status st = check_block(h, nrhs, R, E);
+  if (st != HELM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = padP(nrhs);
+  if ((st = ensure_fields(h, P)) != HELM_OK) return st;
+  const int l = h->L - 1;
+  Level& L = h->lv[l];
+  const Prec pf = field_prec(h, l);
+  launch_to_internal(pf, L.npts, nrhs, P, R, L.F, s);
+  coarsest_solve(h, P, L.F, L.U0, s);
+  launch_to_abi(pf, L.npts, nrhs, P, L.U0, E, s);
+  HCHECK(hipStreamSynchronize(s));
+  HCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov workspace layout (bytes, 256-aligned).
+// ---------------------------------------------------------------------------
+struct WsLayout {
+  size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, flag, act, ls, end;
+};
+
+static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
+  const int64_t N = c->lv[0].npts;
+  const size_t blk = 16 * (size_t)N * P;
+  const size_t zblk = (c->precision == HELM_FP64 ? 16 : 8) * (size_t)N * P;
+  const int ng = P / pb;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  WsLayout w{};
+  size_t o = 0;
+  w.Qi = o; o += al(blk);
+  w.X = o; o += al(blk);
+  w.W = o; o += al(blk);
+  w.V = o; o += al(blk) * (m + 1);
+  w.Z = o; o += al(zblk) * m;
+  w.part = o; o += al(16 * gram_part_elems(P));
+  w.G = o; o += al(16 * (size_t)MAXPTR * P * pb);
+  w.Gc = o; o += al(16 * (size_t)MAXPTR * P * pb);
+  const size_t ldh = (size_t)(m + 1) * pb;
+  w.Hb = o; o += al(16 * ldh * m * pb * ng);
+  w.S = o; o += al(16 * (size_t)ng * pb * pb);
+  w.R = o; o += al(16 * (size_t)ng * pb * pb);
+  w.Rinv = o; o += al(16 * (size_t)ng * pb * pb);
+  w.Y = o; o += al(16 * (size_t)m * P * pb);
+  w.est = o; o += al(8 * (size_t)P);
+  w.qn2 = o; o += al(8 * (size_t)P);
+  w.rn2 = o; o += al(8 * (size_t)P);
+  w.flag = o; o += al(4 * (size_t)ng);
+  w.act = o; o += al(4 * (size_t)ng);
+  w.ls = o; o += al(16 * (size_t)ng * (m + 1) * pb * (m + 1) * pb);
+  w.end = o;
+  return w;
+}
+
+helm_status helm_workspace_size(helm_handle h, int32_t nrhs, int32_t restart, size_t* bytes) {
+  if (!h || !bytes || nrhs < 1 || nrhs > 256 || restart < 1 || restart >= MAXPTR)
+    return fail(HELM_ERR_INVALID_ARG, "bad workspace query");
+  const int P = padP(nrhs);
+  *bytes = ws_layout(h, P, restart, 1).end + ws_layout(h, P, restart, P).end;
+  return HELM_OK;
+}
+
+__global__ void k_hscatter(int pb, int j, int P, const c128* __restrict__ Gc, const c128* __restrict__ R,
+                           c128* __restrict__ Hb, int ldh, int64_t hstride) {
+  // block column j of Hbar for group g = blockIdx.x
+  const int g = blockIdx.x;
+  c128* H = Hb + (int64_t)g * hstride;
+  const int rows = (j + 2) * pb;
+  for (int e = threadIdx.x; e < rows * pb; e += blockDim.x) {
+    const int row = e % rows, b = e / rows;
+    const int i = row / pb, a = row % pb;
+    c128 v;
+    if (i <= j)
+      v = Gc[((int64_t)i * P + g * pb + b) * pb + a];
+    else
+      v = R[((int64_t)g * pb + a) * pb + b];
+    H[(int64_t)(j * pb + b) * ldh + row] = v;
+  }
+}
+
+
+__global__ void k_set_active(int ng, int pb, double tol2, const double* __restrict__ rn2,
+                             const double* __restrict__ qn2, int* __restrict__ act) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  int a = 0;
+  for (int b = 0; b < pb; ++b) {
+    const int c = g * pb + b;
+    if (qn2[c] > 0.0 && rn2[c] > tol2 * qn2[c]) a = 1;
+  }
+  act[g] = a;
+}
+
+// Zero the update coefficients of inactive groups (their columns stay put).
+__global__ void k_zero_inactive(int ng, int pb, int P, int k, const int* __restrict__ act, c128* __restrict__ C) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)k * P * pb) return;
+  const int c = (int)((t / pb) % P);
+  if (!act[c / pb]) C[t] = c128{0.0, 0.0};
+}
+
+helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U, double tol,
+                             const helm_solve_opts* opts, void* workspace, size_t ws_bytes, helm_solve_info* info,
+                             void* stream) {
+  helm_status st = check_block(h, nrhs, Q, U);
+  if (st != HELM_OK) return st;
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(HELM_ERR_INVALID_ARG, "tol must be > 0");
+  helm_solve_opts o{5, 1000, 0, 0, 1};
+  if (opts) o = *opts;
+  const int m = o.restart;
+  if (m < 1 || m >= MAXPTR) return fail(HELM_ERR_INVALID_ARG, "restart must be 1..%d", MAXPTR - 1);
+  const int pb = o.block_size <= 0 ? nrhs : o.block_size;
+  if (pb < 1 || nrhs % pb != 0 || pb > 32) return fail(HELM_ERR_INVALID_ARG, "block_size must divide nrhs and be <= 32");
+  if (o.max_cycles < 1) return fail(HELM_ERR_INVALID_ARG, "max_cycles must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  helm_ctx* c = h;
+  const int P = padP(nrhs);
+  const int Pa = nrhs;  // active (real) columns
+  const int ng = Pa / pb;
+  const int64_t N = c->lv[0].npts;
+  const Level& L0 = c->lv[0];
+  const Prec pz = c->precision == HELM_FP64 ? P64 : P32;
+  if ((st = ensure_fields(c, P)) != HELM_OK) return st;
+  const WsLayout w = ws_layout(c, P, m, pb);
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    if (c->wsbytes < w.end) {
+      hipFree(c->ws);
+      c->ws = nullptr;
+      c->wsbytes = 0;
+      HCHECK(hipMalloc(&c->ws, w.end));
+      c->wsbytes = w.end;
+    }
+    base = static_cast<char*>(c->ws);
+  } else if (ws_bytes < w.end) {
+    return fail(HELM_ERR_INVALID_ARG, "workspace too small (%zu < %zu)", ws_bytes, w.end);
+  }
+  if (c->hbufn < (size_t)4 * P) {
+    if (c->hbuf) hipHostFree(c->hbuf);
+    HCHECK(hipHostMalloc(&c->hbuf, sizeof(double) * 4 * P));
+    c->hbufn = 4 * P;
+  }
+  double* hq = c->hbuf;          // ||q||^2
+  double* hr = c->hbuf + P;      // ||r||^2
+  double* hest = c->hbuf + 2 * P;
+  int* hflag = reinterpret_cast<int*>(c->hbuf + 3 * P);
+  const size_t blk = 16 * (size_t)N * P;
+  c128* Qi = (c128*)(base + w.Qi);
+  c128* X = (c128*)(base + w.X);
+  c128* W = (c128*)(base + w.W);
+  std::vector<c128*> V(m + 1);
+  std::vector<void*> Z(m);
+  const size_t vstride = (blk + 255) / 256 * 256;
+  const size_t zstride = ((pz == P64 ? 16 : 8) * (size_t)N * P + 255) / 256 * 256;
+  for (int j = 0; j <= m; ++j) V[j] = (c128*)(base + w.V + j * vstride);
+  for (int j = 0; j < m; ++j) Z[j] = base + w.Z + j * zstride;
+  c128* part = (c128*)(base + w.part);
+  c128* G = (c128*)(base + w.G);
+  c128* Gc = (c128*)(base + w.Gc);
+  c128* Hb = (c128*)(base + w.Hb);
+  c128* S = (c128*)(base + w.S);
+  c128* Rm = (c128*)(base + w.R);
+  c128* Rinv = (c128*)(base + w.Rinv);
+  c128* Yc = (c128*)(base + w.Y);
+  double* dest = (double*)(base + w.est);
+  double* dq = (double*)(base + w.qn2);
+  double* dr = (double*)(base + w.rn2);
+  int* dflag = (int*)(base + w.flag);
+  int* dact = (int*)(base + w.act);
+  c128* lsw = (c128*)(base + w.ls);
+  const int ldh = (m + 1) * pb;
+  const int64_t hstride = (int64_t)ldh * m * pb;
+  const Geo g0 = L0.geo(P);
+  const double chol_tol = 1e-26;
+
+  hipEvent_t e0, e1;
+  HCHECK(hipEventCreate(&e0));
+  HCHECK(hipEventCreate(&e1));
+  HCHECK(hipEventRecord(e0, s));
+  launch_to_internal(P64, N, nrhs, P, Q, Qi, s);
+  if (o.warm_start)
+    launch_to_internal(P64, N, nrhs, P, U, X, s);
+  else
+    hipMemsetAsync(X, 0, blk, s);
+  launch_colnorm2(P64, N, P, Pa, Qi, part, G, dq, s);
+  HCHECK(hipMemcpyAsync(hq, dq, 8 * Pa, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  for (int cidx = 0; cidx < Pa; ++cidx)
+    if (!std::isfinite(hq[cidx])) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(HELM_ERR_NONFINITE, "non-finite right-hand side column %d", cidx);
+    }
+  int cycles = 0, restarts = 0;
+  bool converged = false, breakdown = false;
+  std::vector<double> relres(Pa, 0.0);
+  std::vector<int> hact(ng, 1);
+  const double tol2 = tol * tol;
+  for (;;) {
+    // true FP64 residual R = Q - H X into V0
+    launch_fine(1, P64, P64, P64, P64, c->dim, g0, X, Qi, V[0], L0.dH, nullptr, L0.ih, s);
+    launch_colnorm2(P64, N, P, Pa, V[0], part, G, dr, s);
+    HCHECK(hipMemcpyAsync(hr, dr, 8 * Pa, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    HCHECK(hipGetLastError());
+    bool all = true;
+    for (int cidx = 0; cidx < Pa; ++cidx) {
+      relres[cidx] = hq[cidx] > 0 ? std::sqrt(hr[cidx] / hq[cidx]) : 0.0;
+      if (!std::isfinite(relres[cidx])) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return fail(HELM_ERR_NONFINITE, "non-finite residual in column %d", cidx);
+      }
+      if (relres[cidx] > tol) all = false;
+    }
+    if (all) {
+      converged = true;
+      break;
+    }
+    if (cycles >= o.max_cycles || breakdown) break;
+    restarts += cycles > 0;
+    hipLaunchKernelGGL(k_set_active, dim3((ng + 255) / 256), dim3(256), 0, s, ng, pb, tol2, dr, dq, dact);
+    // V0 S = R (CholQR)
+    {
+      PtrList xl{};
+      xl.p[0] = V[0];
+      launch_gram(P64, N, P, Pa, pb, 1, xl, V[0], part, G, s);
+      launch_cholqr_small(ng, pb, G, S, Rinv, dflag, chol_tol, s);
+      hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+      launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s);
+      std::swap(V[0], W);
+      HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
+      HCHECK(hipMemsetAsync(Hb, 0, 16 * (size_t)hstride * ng, s));
+      HCHECK(hipStreamSynchronize(s));
+      HCHECK(hipMemcpy(hact.data(), dact, 4 * ng, hipMemcpyDeviceToHost));
+      for (int gg = 0; gg < ng; ++gg)
+        if (hact[gg] && hflag[gg]) {
+          hipEventDestroy(e0);
+          hipEventDestroy(e1);
+          return fail(HELM_ERR_BREAKDOWN,
+                      "rank-deficient residual block in group %d (duplicate or dependent right-hand sides); "
+                      "use block_size 1",
+                      gg);
+        }
+    }
+    int jlast = -1;
+    for (int j = 0; j < m; ++j) {
+      // Z_j = cycle(V_j)
+      const Level& Lz = c->lv[0];
+      if (pz == P64) {
+        cycle_rec(c, 0, P, V[j], Z[j], Lz.U1, s);
+      } else {
+        launch_convert(P64, P32, N * P, V[j], Lz.F, s);
+        cycle_rec(c, 0, P, Lz.F, Z[j], Lz.U1, s);
+      }
+      ++cycles;
+      // W = H Z_j (FP64)
+      launch_fine(0, pz, P64, P64, P64, c->dim, g0, Z[j], nullptr, W, L0.dH, nullptr, L0.ih, s);
+      // block classical Gram-Schmidt against V_0..V_j (twice if reorth)
+      PtrList vl{};
+      for (int i = 0; i <= j; ++i) vl.p[i] = V[i];
+      launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, Gc, s);
+      launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, Gc, W, s);
+      if (o.reorth) {
+        launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, G, s);
+        launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, G, W, s);
+        const int64_t ne = (int64_t)(j + 1) * Pa * pb;
+        hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
+      }
+      // W = V_{j+1} R (CholQR)
+      PtrList wl{};
+      wl.p[0] = W;
+      launch_gram(P64, N, P, Pa, pb, 1, wl, W, part, G, s);
+      launch_cholqr_small(ng, pb, G, Rm, Rinv, dflag, chol_tol, s);
+      hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+      launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s);
+      hipLaunchKernelGGL(k_hscatter, dim3(ng), dim3(256), 0, s, pb, j, Pa, Gc, Rm, Hb, ldh, hstride);
+      launch_block_ls(ng, pb, j, Hb, ldh, hstride, S, Yc, 0, dest, lsw, dact, s);
+      HCHECK(hipMemcpyAsync(hest, dest, 8 * Pa, hipMemcpyDeviceToHost, s));
+      HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      HCHECK(hipGetLastError());
+      bool conv = true;
+      for (int cidx = 0; cidx < Pa; ++cidx)
+        if (hq[cidx] > 0 && hest[cidx] > tol * std::sqrt(hq[cidx])) conv = false;
+      bool brk = false;
+      for (int gg = 0; gg < ng; ++gg) brk = brk || (hact[gg] && hflag[gg]);
+      jlast = j;
+      if (conv || brk || j == m - 1 || cycles >= o.max_cycles) break;
+    }
+    // X += sum_j Z_j Y_j
+    hipLaunchKernelGGL(k_zero_inactive, dim3((unsigned)(((jlast + 1) * P * pb + 255) / 256)), dim3(256), 0, s, ng,
+                       pb, Pa, jlast + 1, dact, Yc);
+    PtrList zl{};
+    for (int i = 0; i <= jlast; ++i) zl.p[i] = Z[i];
+    launch_block_update(2, pz, P64, N, P, Pa, pb, jlast + 1, zl, Yc, X, s);
+  }
+  launch_to_abi(P64, N, nrhs, P, X, U, s);
+  HCHECK(hipEventRecord(e1, s));
+  HCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HCHECK(hipGetLastError());
+  if (info) {
+    info->cycles = cycles;
+    info->restarts = restarts;
+    info->converged_all = converged ? 1 : 0;
+    info->fallback_used = c->net ? learned::fallback_used(c->net) : 0;
+    info->t_solve_ms = ms;
+    for (int cidx = 0; cidx < nrhs; ++cidx) {
+      if (info->relres) info->relres[cidx] = relres[cidx];
+      if (info->converged) info->converged[cidx] = relres[cidx] <= tol;
+    }
+  }
+  if (!converged) return fail(HELM_ERR_NOT_CONVERGED, "not converged after %d cycles", cycles);
+  return HELM_OK;
+}
+
+helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void* U, double* relres, void* stream) {
+  helm_status st = check_block(h, nrhs, Q, U);
+  if (st != HELM_OK) return st;
+  if (!relres) return fail(HELM_ERR_INVALID_ARG, "relres is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = padP(nrhs);
+  const Level& L = h->lv[0];
+  const int64_t N = L.npts;
+  c128 *A, *B;
+  if ((st = tmp_blocks(h, P, N, &A, &B)) != HELM_OK) return st;
+  c128* R = nullptr;
+  c128* part = nullptr;
+  double* d = nullptr;
+  hipError_t e = hipMalloc(&R, 16 * N * P);
+  if (e == hipSuccess) e = hipMalloc(&part, 16 * (gram_part_elems(P) + 2 * P));
+  if (e == hipSuccess) e = hipMalloc(&d, 16 * P);
+  if (e != hipSuccess) {
+    hipFree(A);
+    hipFree(B);
+    hipFree(R);
+    hipFree(part);
+    return fail(HELM_ERR_OOM, "helm_residual scratch");
+  }
+  launch_to_internal(P64, N, nrhs, P, Q, A, s);
+  launch_to_internal(P64, N, nrhs, P, U, B, s);
+  launch_fine(1, P64, P64, P64, P64, h->dim, L.geo(P), B, A, R, L.dH, nullptr, L.ih, s);
+  c128* G = part + gram_part_elems(P);
+  launch_colnorm2(P64, N, P, nrhs, R, part, G, d, s);
+  launch_colnorm2(P64, N, P, nrhs, A, part, G, d + P, s);
+  std::vector<double> hd(2 * P);
+  e = hipMemcpyAsync(hd.data(), d, 16 * P, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(A);
+  hipFree(B);
+  hipFree(R);
+  hipFree(part);
+  hipFree(d);
+  HCHECK(e);
+  HCHECK(hipGetLastError());
+  for (int c = 0; c < nrhs; ++c) relres[c] = hd[P + c] > 0 ? std::sqrt(hd[c] / hd[P + c]) : 0.0;
+  return HELM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,466 @@
+// k_krylov.hip -- FP64 kernels of block FGMRES (section 5.3, "block FGMRES(5)").
+//
+// A block of P right-hand sides is split into groups of pb columns; each
+// group is an independent block-Krylov solve and all groups share every
+// launch. Vectors are point-major c128 blocks [N][ld].
+//
+//  - block Gram products V_i^H W: lanes own one column, loop over a grid
+//    stride of points, reduce across lanes through LDS, then a second pass
+//    sums the per-workgroup partials in a fixed order (deterministic);
+//  - block updates W -= sum_i V_i H_i, V = W R^-1 and X += sum_j Z_j Y_j:
+//    lanes own one (point, column) entry; the pb values of the group at
+//    that point are read once per lane group (broadcast through L1);
+//  - Cholesky of the pb x pb Gram matrix (CholQR) and the small block
+//    least-squares problem (Householder) run in one workgroup per group.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace helm {
+
+__device__ inline cx<double> tcx(c128 v) { return {v.re, v.im}; }
+__device__ inline c128 fcx(cx<double> v) { return {v.re, v.im}; }
+
+constexpr int GRAM_MAXACC = 16;
+constexpr int GRAM_BLOCKS = 1024;
+
+// part[blk][i][c][a] for i < k, c < P, a < na (a offset by a0 in the group).
+template <class S>
+__global__ __launch_bounds__(256) void k_gram_part(int64_t N, int ld, int P, int pb, int k, int a0, int na,
+                                                   PtrList X, const S* __restrict__ Y,
+                                                   c128* __restrict__ part) {
+  extern __shared__ cx<double> red[];  // [256][k*na]
+  const int tid = threadIdx.x;
+  const int PT = 256 / P;
+  const int c = tid % P, r = tid / P;
+  const int kn = k * na;
+  cx<double> acc[GRAM_MAXACC];
+#pragma unroll
+  for (int e = 0; e < GRAM_MAXACC; ++e) acc[e] = {0.0, 0.0};
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t nb0 = (int64_t)blockIdx.x * chunk;
+  const int64_t nb1 = nb0 + chunk < N ? nb0 + chunk : N;
+  if (r < PT) {
+    const int cb = (c / pb) * pb + a0;
+    for (int64_t n = nb0 + r; n < nb1; n += PT) {
+      const S yv = Y[n * ld + c];
+      const cx<double> y = {(double)yv.re, (double)yv.im};
+#pragma unroll
+      for (int e = 0; e < GRAM_MAXACC; ++e) {
+        if (e < kn) {
+          const int i = e / na, a = e - i * na;
+          const S xv = static_cast<const S*>(X.p[i])[n * ld + cb + a];
+          const cx<double> x = {(double)xv.re, (double)xv.im};
+          cfmac(acc[e], x, y);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < GRAM_MAXACC; ++e)
+    if (e < kn) red[tid * kn + e] = acc[e];
+  __syncthreads();
+  for (int o = tid; o < P * kn; o += 256) {
+    const int cc = o / kn, e = o - cc * kn;
+    cx<double> s = {0.0, 0.0};
+    for (int rr = 0; rr < PT; ++rr) s = s + red[(rr * P + cc) * kn + e];
+    const int i = e / na, a = e - i * na;
+    part[(((int64_t)blockIdx.x * k + i) * P + cc) * na + a] = fcx(s);
+  }
+}
+
+// G[i][c][a0+a] = sum over blocks of part (fixed order).
+__global__ void k_gram_final(int nblk, int P, int pb, int k, int i0, int a0, int na, const c128* __restrict__ part,
+                             c128* __restrict__ G) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= k * P * na) return;
+  const int a = o % na, c = (o / na) % P, i = o / (na * P);
+  cx<double> s = {0.0, 0.0};
+  for (int b = 0; b < nblk; ++b) s = s + tcx(part[(int64_t)b * k * P * na + o]);
+  G[((int64_t)(i0 + i) * P + c) * pb + a0 + a] = fcx(s);
+}
+
+int64_t gram_part_elems(int P) { return (int64_t)GRAM_BLOCKS * GRAM_MAXACC * P; }
+
+void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList& X, const void* Y, c128* part,
+                 c128* G, hipStream_t s) {
+  if (p != P64 && p != P32) fatal_combo("launch_gram");
+  if (P > 256 || P % pb != 0) fatal_combo("launch_gram");
+  int nblk = GRAM_BLOCKS;
+  const int64_t minpts = (256 / P) * 4;
+  if (N < (int64_t)nblk * minpts) nblk = (int)((N + minpts - 1) / minpts);
+  if (nblk < 1) nblk = 1;
+  const int na = pb < GRAM_MAXACC ? pb : GRAM_MAXACC;
+  const int kk = GRAM_MAXACC / na;
+  for (int i0 = 0; i0 < k; i0 += kk) {
+    const int kc = (k - i0) < kk ? (k - i0) : kk;
+    for (int a0 = 0; a0 < pb; a0 += na) {
+      const size_t shm = sizeof(cx<double>) * 256 * kc * na;
+      PtrList sub{};
+      for (int i = 0; i < kc; ++i) sub.p[i] = X.p[i0 + i];
+      if (p == P64)
+        hipLaunchKernelGGL((k_gram_part<c128>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, kc, a0, na, sub,
+                           (const c128*)Y, part);
+      else
+        hipLaunchKernelGGL((k_gram_part<c64>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, kc, a0, na, sub,
+                           (const c64*)Y, part);
+      const int outs = kc * P * na;
+      hipLaunchKernelGGL(k_gram_final, dim3((outs + 255) / 256), dim3(256), 0, s, nblk, P, pb, kc, i0, a0, na, part,
+                         G);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <class SX, class SY>
+__global__ __launch_bounds__(256) void k_block_update(int mode, int64_t N, int ld, int P, int pb, int k,
+                                                      PtrList X, const c128* __restrict__ C,
+                                                      SY* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int64_t n = t / P;
+  const int c = (int)(t - n * P);
+  const int cb = (c / pb) * pb;
+  cx<double> acc = {0.0, 0.0};
+  for (int i = 0; i < k; ++i) {
+    const SX* xi = static_cast<const SX*>(X.p[i]) + n * ld + cb;
+    const c128* ci = C + ((int64_t)i * P + c) * pb;
+    for (int a = 0; a < pb; ++a) {
+      const SX xv = xi[a];
+      cfma(acc, cx<double>{(double)xv.re, (double)xv.im}, tcx(ci[a]));
+    }
+  }
+  SY* yp = Y + n * ld + c;
+  cx<double> r = acc;
+  if (mode != 1) {
+    const SY yv = *yp;
+    const cx<double> y = {(double)yv.re, (double)yv.im};
+    r = mode == 0 ? y - acc : y + acc;
+  }
+  using E = decltype(yp->re);
+  *yp = SY{(E)r.re, (E)r.im};
+}
+
+void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, int pb, int k, const PtrList& X,
+                         const c128* C, void* Y, hipStream_t s) {
+  const dim3 gr((unsigned)((N * P + 255) / 256));
+  if (k > MAXPTR) fatal_combo("launch_block_update");
+  if (px == P64 && py == P64)
+    hipLaunchKernelGGL((k_block_update<c128, c128>), gr, dim3(256), 0, s, mode, N, ld, P, pb, k, X, C, (c128*)Y);
+  else if (px == P32 && py == P64)
+    hipLaunchKernelGGL((k_block_update<c64, c128>), gr, dim3(256), 0, s, mode, N, ld, P, pb, k, X, C, (c128*)Y);
+  else if (px == P32 && py == P32)
+    hipLaunchKernelGGL((k_block_update<c64, c64>), gr, dim3(256), 0, s, mode, N, ld, P, pb, k, X, C, (c64*)Y);
+  else
+    fatal_combo("launch_block_update");
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky G = R^H R per group (one workgroup each), R upper, and R^-1.
+// G layout: Gm[a][b] = G[(g*pb + b)*pb + a]. Outputs: R[g][a][b] row-major,
+// RinvC in update layout: RinvC[(g*pb + b)*pb + a] = Rinv[a][b].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __restrict__ G, c128* __restrict__ R,
+                                                      c128* __restrict__ RinvC, int* __restrict__ flag, double tol) {
+  extern __shared__ cx<double> sm[];
+  cx<double>* A = sm;             // pb x pb working copy (upper part becomes R)
+  cx<double>* Ri = sm + pb * pb;  // pb x pb inverse
+  __shared__ double dmax;
+  __shared__ int bad;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < pb * pb; e += blockDim.x) {
+    const int a = e / pb, b = e % pb;
+    A[e] = tcx(G[((int64_t)g * pb + b) * pb + a]);
+  }
+  if (tid == 0) {
+    bad = 0;
+    dmax = 0.0;
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (int a = 0; a < pb; ++a) dmax = fmax(dmax, A[a * pb + a].re);
+  __syncthreads();
+  for (int j = 0; j < pb; ++j) {
+    // A[j][j] <- sqrt(A[j][j]) (already reduced by previous rows)
+    if (tid == 0) {
+      const double d = A[j * pb + j].re;
+      if (!(d > tol * dmax) || !(dmax > 0.0)) bad = 1;
+      A[j * pb + j] = {sqrt(fmax(d, 0.0)), 0.0};
+    }
+    __syncthreads();
+    if (bad) break;
+    const double inv = 1.0 / A[j * pb + j].re;
+    for (int b = j + 1 + tid; b < pb; b += blockDim.x) A[j * pb + b] = inv * A[j * pb + b];
+    __syncthreads();
+    // trailing update A[a][b] -= conj(R[j][a]) R[j][b] for j < a <= b
+    for (int e = tid; e < pb * pb; e += blockDim.x) {
+      const int a = e / pb, b = e % pb;
+      if (a > j && b >= a) {
+        const cx<double> ra = A[j * pb + a], rb = A[j * pb + b];
+        cfmac(A[e], cx<double>{-ra.re, -ra.im}, rb);
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) flag[g] = 1;
+    for (int e = tid; e < pb * pb; e += blockDim.x) {
+      R[(int64_t)g * pb * pb + e] = c128{0.0, 0.0};
+      RinvC[(int64_t)g * pb * pb + e] = c128{0.0, 0.0};
+    }
+    return;
+  }
+  if (tid == 0) flag[g] = 0;
+  // Ri = R^-1 by back substitution, one column per lane
+  for (int b = tid; b < pb; b += blockDim.x) {
+    for (int a = pb - 1; a >= 0; --a) {
+      cx<double> s = {a == b ? 1.0 : 0.0, 0.0};
+      for (int l = a + 1; l <= b; ++l) s = s - A[a * pb + l] * Ri[l * pb + b];
+      const double inv = 1.0 / A[a * pb + a].re;
+      Ri[a * pb + b] = a > b ? cx<double>{0.0, 0.0} : inv * s;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < pb * pb; e += blockDim.x) {
+    const int a = e / pb, b = e % pb;
+    R[(int64_t)g * pb * pb + e] = a <= b ? fcx(A[e]) : c128{0.0, 0.0};
+    RinvC[((int64_t)g * pb + b) * pb + a] = fcx(Ri[e]);
+  }
+}
+
+void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, hipStream_t s) {
+  const size_t shm = sizeof(cx<double>) * 2 * pb * pb;
+  hipLaunchKernelGGL(k_cholqr_small, dim3(ng), dim3(256), shm, s, pb, G, R, Rinv, flag, tol);
+}
+
+// ---------------------------------------------------------------------------
+// Block least squares per group: min ||[S; 0] - Hbar Y||_F by Householder.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_block_ls(int pb, int j, int P, const c128* __restrict__ Hb, int ldh,
+                                                  int64_t hstride, const c128* __restrict__ S, c128* __restrict__ Yc,
+                                                  double* __restrict__ est, c128* __restrict__ scratch,
+                                                  const int* __restrict__ active) {
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int r = (j + 2) * pb, cc = (j + 1) * pb;
+  const int ncol = cc + pb;
+  cx<double>* M = reinterpret_cast<cx<double>*>(scratch) + (int64_t)g * r * ncol;  // col-major r x ncol
+  __shared__ double sred[256];
+  __shared__ cx<double> salpha;
+  __shared__ double svn2;
+  __shared__ int skip;
+  if (active && !active[g]) {
+    for (int e = tid; e < (j + 1) * pb * pb; e += blockDim.x) {
+      const int jj = e / (pb * pb), rem = e % (pb * pb), b = rem / pb, a = rem % pb;
+      Yc[((int64_t)jj * P + g * pb + b) * pb + a] = c128{0.0, 0.0};
+    }
+    for (int b = tid; b < pb; b += blockDim.x) est[g * pb + b] = 0.0;
+    return;
+  }
+  const c128* H = Hb + (int64_t)g * hstride;
+  for (int e = tid; e < r * cc; e += blockDim.x) {
+    const int col = e / r, row = e % r;
+    M[e] = tcx(H[(int64_t)col * ldh + row]);
+  }
+  for (int e = tid; e < r * pb; e += blockDim.x) {
+    const int b = e / r, row = e % r;
+    M[(int64_t)(cc + b) * r + row] = row < pb ? tcx(S[((int64_t)g * pb + row) * pb + b]) : cx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int q = 0; q < cc; ++q) {
+    double part = 0.0;
+    for (int i = q + tid; i < r; i += blockDim.x) {
+      const cx<double> v = M[(int64_t)q * r + i];
+      part += v.re * v.re + v.im * v.im;
+    }
+    sred[tid] = part;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) sred[tid] += sred[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double nrm = sqrt(sred[0]);
+      const cx<double> x0 = M[(int64_t)q * r + q];
+      const double ax = sqrt(x0.re * x0.re + x0.im * x0.im);
+      skip = nrm == 0.0;
+      const cx<double> ph = ax > 0.0 ? cx<double>{x0.re / ax, x0.im / ax} : cx<double>{1.0, 0.0};
+      salpha = {-ph.re * nrm, -ph.im * nrm};
+      const cx<double> v0 = x0 - salpha;
+      svn2 = sred[0] - ax * ax + (v0.re * v0.re + v0.im * v0.im);
+      M[(int64_t)q * r + q] = v0;  // reflector v stored in column q (rows q..r-1)
+    }
+    __syncthreads();
+    if (!skip) {
+      const double f = 2.0 / svn2;
+      for (int col = q + 1 + tid; col < ncol; col += blockDim.x) {
+        cx<double> d = {0.0, 0.0};
+        for (int i = q; i < r; ++i) cfmac(d, M[(int64_t)q * r + i], M[(int64_t)col * r + i]);
+        d = f * d;
+        for (int i = q; i < r; ++i) {
+          const cx<double> v = M[(int64_t)q * r + i];
+          M[(int64_t)col * r + i] = M[(int64_t)col * r + i] - v * d;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) M[(int64_t)q * r + q] = salpha;  // diagonal of R
+    __syncthreads();
+  }
+  // back substitution per right-hand-side column; R = upper part of M[:, :cc]
+  for (int b = tid; b < pb; b += blockDim.x) {
+    cx<double>* rhs = M + (int64_t)(cc + b) * r;
+    double e2 = 0.0;
+    for (int i = cc; i < r; ++i) e2 += rhs[i].re * rhs[i].re + rhs[i].im * rhs[i].im;
+    est[g * pb + b] = sqrt(e2);
+    for (int i = cc - 1; i >= 0; --i) {
+      cx<double> s = rhs[i];
+      for (int l = i + 1; l < cc; ++l) s = s - M[(int64_t)l * r + i] * rhs[l];
+      const cx<double> d = M[(int64_t)i * r + i];
+      const double dd = d.re * d.re + d.im * d.im;
+      rhs[i] = dd > 0.0 ? cx<double>{(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd}
+                        : cx<double>{0.0, 0.0};
+    }
+    for (int i = 0; i < cc; ++i) {
+      const int jj = i / pb, a = i % pb;
+      Yc[((int64_t)jj * P + g * pb + b) * pb + a] = fcx(rhs[i]);
+    }
+  }
+}
+
+void launch_block_ls(int ng, int pb, int j, const c128* Hb, int ldh, int64_t hstride, const c128* S, c128* Y,
+                     int64_t ystride, double* est, c128* scratch, const int* active, hipStream_t s) {
+  (void)ystride;
+  hipLaunchKernelGGL(k_block_ls, dim3(ng), dim3(256), 0, s, pb, j, ng * pb, Hb, ldh, hstride, S, Y, est, scratch,
+                     active);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_diag_real(int P, const c128* __restrict__ G, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < P) out[c] = G[c].re;
+}
+
+void launch_colnorm2(Prec p, int64_t N, int ld, int P, const void* X, c128* part, c128* G, double* out,
+                     hipStream_t s) {
+  PtrList xl{};
+  xl.p[0] = X;
+  launch_gram(p, N, ld, P, 1, 1, xl, X, part, G, s);
+  hipLaunchKernelGGL(k_diag_real, dim3((P + 255) / 256), dim3(256), 0, s, P, G, out);
+}
+
+__global__ void k_mask_cols(int64_t N, int ld, int P, int pb, const int* __restrict__ active, c128* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int64_t n = t / P;
+  const int c = (int)(t - n * P);
+  if (!active[c / pb]) Y[n * ld + c] = c128{0.0, 0.0};
+}
+void launch_mask_cols(int64_t N, int ld, int P, int pb, const int* active, c128* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_cols, dim3((unsigned)((N * P + 255) / 256)), dim3(256), 0, s, N, ld, P, pb, active, Y);
+}
+
+template <class S>
+__global__ void k_scale_cols(int64_t N, int ld, int P, const double* __restrict__ sc, const S* __restrict__ X,
+                             S* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int64_t n = t / P;
+  const int c = (int)(t - n * P);
+  const S v = X[n * ld + c];
+  using E = decltype(v.re);
+  Y[n * ld + c] = S{(E)(sc[c] * v.re), (E)(sc[c] * v.im)};
+}
+void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const void* X, void* Y, hipStream_t s) {
+  const dim3 gr((unsigned)((N * P + 255) / 256));
+  if (p == P64)
+    hipLaunchKernelGGL((k_scale_cols<c128>), gr, dim3(256), 0, s, N, ld, P, sc, (const c128*)X, (c128*)Y);
+  else if (p == P32)
+    hipLaunchKernelGGL((k_scale_cols<c64>), gr, dim3(256), 0, s, N, ld, P, sc, (const c64*)X, (c64*)Y);
+  else
+    fatal_combo("launch_scale_cols");
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-step GMRES of the coarsest grid (one independent GMRES per column).
+// ---------------------------------------------------------------------------
+// Column j of every column's Hessenberg matrix H[c] ((k+1) x k, column-major)
+// from the Gram coefficients Gc[i][c] (i <= j) and ||w||^2; sc[c] = 1/||w||.
+__global__ void k_cg_hcol(int P, int j, int k, const c128* __restrict__ Gc, const double* __restrict__ hn2,
+                          c128* __restrict__ H, double* __restrict__ sc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  c128* h = H + (int64_t)c * (k + 1) * k + (int64_t)j * (k + 1);
+  for (int i = 0; i <= j; ++i) h[i] = Gc[(int64_t)i * P + c];
+  const double nrm = sqrt(fmax(hn2[c], 0.0));
+  h[j + 1] = c128{nrm, 0.0};
+  sc[c] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+}
+void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_hcol, dim3((P + 63) / 64), dim3(64), 0, s, P, j, k, Gc, hn2, H, sc);
+}
+// sc[c] = 1/sqrt(b2[c]) (0 for a zero column)
+__global__ void k_inv_sqrt(int P, const double* __restrict__ b2, double* __restrict__ sc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < P) sc[c] = b2[c] > 0.0 ? 1.0 / sqrt(b2[c]) : 0.0;
+}
+void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_sqrt, dim3((P + 63) / 64), dim3(64), 0, s, P, b2, sc);
+}
+// Least squares min || beta e1 - H y || per column by Givens rotations;
+// y written in update layout Y[i][c] (pb = 1).
+__global__ void k_cg_ls(int P, int k, const c128* __restrict__ Hm, const double* __restrict__ b2,
+                        c128* __restrict__ Y) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  constexpr int KMAX = 48;
+  cx<double> h[KMAX + 1], g[KMAX + 1], cs[KMAX], sn[KMAX];
+  cx<double> R[KMAX * (KMAX + 1) / 2];  // packed upper triangle, column by column
+  const c128* H = Hm + (int64_t)c * (k + 1) * k;
+  const double beta = sqrt(fmax(b2[c], 0.0));
+  for (int i = 0; i <= k; ++i) g[i] = {0.0, 0.0};
+  g[0] = {beta, 0.0};
+  int steps = k;
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i <= j + 1; ++i) h[i] = tcx(H[(int64_t)j * (k + 1) + i]);
+    for (int i = 0; i < j; ++i) {  // previous rotations
+      const cx<double> a = h[i], b = h[i + 1];
+      // [c s; -conj(s) c] with c real
+      h[i] = cs[i] * a + sn[i] * b;
+      h[i + 1] = cx<double>{-sn[i].re, sn[i].im} * a + cs[i] * b;
+    }
+    const cx<double> a = h[j], b = h[j + 1];
+    const double na = sqrt(a.re * a.re + a.im * a.im), nb = sqrt(b.re * b.re + b.im * b.im);
+    const double r = sqrt(na * na + nb * nb);
+    if (r == 0.0) {
+      steps = j;
+      break;
+    }
+    const cx<double> ph = na > 0.0 ? cx<double>{a.re / na, a.im / na} : cx<double>{1.0, 0.0};
+    cs[j] = {na / r, 0.0};
+    // s = ph * conj(b) / r so that the rotated entry below vanishes
+    sn[j] = {(ph.re * b.re + ph.im * b.im) / r, (ph.im * b.re - ph.re * b.im) / r};
+    h[j] = {ph.re * r, ph.im * r};
+    const cx<double> gj = g[j];
+    g[j] = cs[j] * gj;
+    g[j + 1] = cx<double>{-sn[j].re, sn[j].im} * gj;
+    for (int i = 0; i <= j; ++i) R[j * (j + 1) / 2 + i] = h[i];
+    if (nb == 0.0) {  // happy breakdown: exact in this space
+      steps = j + 1;
+      break;
+    }
+  }
+  cx<double> y[KMAX];
+  for (int i = steps - 1; i >= 0; --i) {
+    cx<double> s = g[i];
+    for (int l = i + 1; l < steps; ++l) s = s - R[l * (l + 1) / 2 + i] * y[l];
+    const cx<double> d = R[i * (i + 1) / 2 + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    y[i] = {(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd};
+  }
+  for (int i = 0; i < k; ++i) Y[(int64_t)i * P + c] = i < steps ? fcx(y[i]) : c128{0.0, 0.0};
+}
+void launch_cg_ls(int P, int k, const c128* H, const double* b2, c128* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_ls, dim3((P + 63) / 64), dim3(64), 0, s, P, k, H, b2, Y);
+}
+
+}  // namespace helm

@@ -1,0 +1,488 @@
+// k_level.hip -- per-level kernels of the block multigrid cycle.
+//
+// Every kernel works on point-major blocks [N][P] (see common.hpp) and lets
+// each lane own K consecutive right-hand sides of one grid point, so a
+// wavefront reads contiguous runs for the centre and each neighbour.
+//
+//  - fine level: the 5-point (2D) / 7-point (3D) operator of eq:LinearSystem
+//    with a per-point complex diagonal (H or the shifted M) and constant
+//    off-diagonals -1/h_a^2;
+//  - coarse levels: 9-point / 27-point Galerkin stencils [N][3^d];
+//  - damped Jacobi (section 5.3), residual, full-weighting restriction and
+//    d-linear prolongation (section "Solving the Helmholtz equation for
+//    multiple right hand sides").
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace helm {
+
+template <class A, class B, class C> constexpr int kmax3() {
+  return St<A>::R > St<B>::R ? (St<A>::R > St<C>::R ? St<A>::R : St<C>::R)
+                             : (St<B>::R > St<C>::R ? St<B>::R : St<C>::R);
+}
+__device__ inline void put1(c128* p, c128 v) { *p = v; }
+__device__ inline void put1(c64* p, c128 v) { *p = c64{(float)v.re, (float)v.im}; }
+__device__ inline void put1(cbf* p, c128 v) { *p = cbf{f2bf((float)v.re), f2bf((float)v.im)}; }
+__device__ inline c128 get1(const c128* p) { return *p; }
+__device__ inline c128 get1(const c64* p) { return c128{(double)p->re, (double)p->im}; }
+__device__ inline c128 get1(const cbf* p) { return c128{(double)bf2f(p->re), (double)bf2f(p->im)}; }
+
+template <int K, class S, class T> __device__ inline void ldK(const S* p, cx<T>* o) {
+#pragma unroll
+  for (int k = 0; k < K; k += St<S>::R) ld16<T>(p + k, o + k);
+}
+template <int K, class S, class T> __device__ inline void ldKz(const S* p, bool ok, cx<T>* o) {
+  if (ok) {
+    ldK<K, S, T>(p, o);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = {(T)0, (T)0};
+  }
+}
+template <int K, class S, class T> __device__ inline void stK(S* p, const cx<T>* o) {
+#pragma unroll
+  for (int k = 0; k < K; k += St<S>::R) st16<T>(p + k, o + k);
+}
+
+// ---------------------------------------------------------------------------
+// Fine-level operator family.
+//   APPLY : out = A u
+//   RESID : out = f - A u
+//   JAC   : out = u + w D^-1 (f - A u)      (dw = w / diag)
+//   JAC0  : out = w D^-1 f                  (first sweep from u = 0)
+// ---------------------------------------------------------------------------
+template <int DIM, class SU, class SF, class SO, class T, int MODE>
+__global__ __launch_bounds__(256) void k_fine(Geo g, const SU* __restrict__ u, const SF* __restrict__ f,
+                                              SO* __restrict__ out, const cx<T>* __restrict__ dg,
+                                              const cx<T>* __restrict__ dw, T ihx, T ihy, T ihz) {
+  constexpr int K = kmax3<SU, SF, SO>();
+  const int Pc = g.P / K;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.npts * Pc) return;
+  const int64_t i = t / Pc;
+  const int c = (int)(t - i * Pc) * K;
+  const int64_t base = i * g.P + c;
+  cx<T> res[K];
+  if (MODE == 3) {
+    cx<T> fv[K];
+    ldK<K, SF, T>(f + base, fv);
+    cx<T> w = dw[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = w * fv[k];
+    stK<K, SO, T>(out + base, res);
+    return;
+  }
+  int x, y, z;
+  coords(g, i, x, y, z);
+  cx<T> uc[K], nb[K], acc[K];
+  ldK<K, SU, T>(u + base, uc);
+  const cx<T> d = dg[i];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = d * uc[k];
+  const int64_t sx = g.P, sy = (int64_t)g.nx * g.P, sz = (int64_t)g.nx * g.ny * g.P;
+  // -1/h^2 couplings to the 2*DIM face neighbours (zero outside the grid)
+  cx<T> sum[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) sum[k] = {(T)0, (T)0};
+  ldKz<K, SU, T>(u + base - sx, x > 0, nb);
+#pragma unroll
+  for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
+  ldKz<K, SU, T>(u + base + sx, x < g.nx - 1, nb);
+#pragma unroll
+  for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
+  ldKz<K, SU, T>(u + base - sy, y > 0, nb);
+#pragma unroll
+  for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihy * nb[k];
+  ldKz<K, SU, T>(u + base + sy, y < g.ny - 1, nb);
+#pragma unroll
+  for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihy * nb[k];
+  if (DIM == 3) {
+    ldKz<K, SU, T>(u + base - sz, z > 0, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihz * nb[k];
+    ldKz<K, SU, T>(u + base + sz, z < g.nz - 1, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihz * nb[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = acc[k] - sum[k];
+  if (MODE == 0) {
+    stK<K, SO, T>(out + base, acc);
+    return;
+  }
+  cx<T> fv[K];
+  ldK<K, SF, T>(f + base, fv);
+  if (MODE == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
+  } else {
+    const cx<T> w = dw[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
+  }
+  stK<K, SO, T>(out + base, res);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin-level operator family (same modes), stencil [N][NS], NS = 3^DIM.
+// ---------------------------------------------------------------------------
+template <int DIM, class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, const S* __restrict__ f,
+                                             S* __restrict__ out, const cx<T>* __restrict__ st,
+                                             const cx<T>* __restrict__ dw) {
+  constexpr int K = St<S>::R;
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  const int Pc = g.P / K;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.npts * Pc) return;
+  const int64_t i = t / Pc;
+  const int c = (int)(t - i * Pc) * K;
+  const int64_t base = i * g.P + c;
+  cx<T> res[K];
+  if (MODE == 3) {
+    cx<T> fv[K];
+    ldK<K, S, T>(f + base, fv);
+    const cx<T> w = dw[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = w * fv[k];
+    stK<K, S, T>(out + base, res);
+    return;
+  }
+  int x, y, z;
+  coords(g, i, x, y, z);
+  cx<T> acc[K], nb[K], uc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = {(T)0, (T)0};
+  const cx<T>* sp = st + i * NS;
+  const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+#pragma unroll
+  for (int oz = zlo; oz <= zhi; ++oz) {
+    const bool okz = (z + oz >= 0) && (z + oz < g.nz);
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+      const bool oky = okz && (y + oy >= 0) && (y + oy < g.ny);
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const bool ok = oky && (x + ox >= 0) && (x + ox < g.nx);
+        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+        const int64_t off = (((int64_t)oz * g.ny + oy) * g.nx + ox) * g.P;
+        ldKz<K, S, T>(u + base + off, ok, nb);
+        if (ox == 0 && oy == 0 && oz == 0) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) uc[k] = nb[k];
+        }
+        const cx<T> a = sp[o];
+#pragma unroll
+        for (int k = 0; k < K; ++k) cfma(acc[k], a, nb[k]);
+      }
+    }
+  }
+  if (MODE == 0) {
+    stK<K, S, T>(out + base, acc);
+    return;
+  }
+  cx<T> fv[K];
+  ldK<K, S, T>(f + base, fv);
+  if (MODE == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
+  } else {
+    const cx<T> w = dw[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
+  }
+  stK<K, S, T>(out + base, res);
+}
+
+// ---------------------------------------------------------------------------
+// Full weighting: rc[I] = 2^-d sum_delta w(delta) rf[2I+1+delta],
+// w = prod over axes of (1 if delta_a == 0 else 1/2).
+// ---------------------------------------------------------------------------
+template <int DIM, class SI, class SO, class T>
+__global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const SI* __restrict__ rf, SO* __restrict__ rc) {
+  constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
+  const int Pc = gc.P / K;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.npts * Pc) return;
+  const int64_t I = t / Pc;
+  const int c = (int)(t - I * Pc) * K;
+  int X, Y, Z;
+  coords(gc, I, X, Y, Z);
+  cx<T> acc[K], v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = {(T)0, (T)0};
+  const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+#pragma unroll
+  for (int dz = zlo; dz <= zhi; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int fx = 2 * X + 1 + dx, fy = 2 * Y + 1 + dy, fz = DIM == 3 ? 2 * Z + 1 + dz : 0;
+        const T w = (dx ? (T)0.5 : (T)1) * (dy ? (T)0.5 : (T)1) * (dz ? (T)0.5 : (T)1);
+        const int64_t fi = ((int64_t)fz * gf.ny + fy) * gf.nx + fx;
+        ldK<K, SI, T>(rf + fi * gf.P + c, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * v[k];
+      }
+  const T s = DIM == 3 ? (T)0.125 : (T)0.25;
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = s * acc[k];
+  stK<K, SO, T>(rc + I * gc.P + c, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation and correction: uf += P ec. A fine index i has the coarse
+// parent (i-1)/2 with weight 1 when i is odd, else the parents i/2-1 and i/2
+// (those inside the coarse grid) with weight 1/2.
+// ---------------------------------------------------------------------------
+__device__ inline int parents(int i, int nc, int* p, float* w) {
+  if (i & 1) {
+    p[0] = (i - 1) >> 1;
+    w[0] = 1.f;
+    return 1;
+  }
+  int k = 0;
+  if (i / 2 - 1 >= 0) {
+    p[k] = i / 2 - 1;
+    w[k++] = 0.5f;
+  }
+  if (i / 2 < nc) {
+    p[k] = i / 2;
+    w[k++] = 0.5f;
+  }
+  return k;
+}
+
+template <int DIM, class SC, class SF, class T>
+__global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const SC* __restrict__ ec, SF* __restrict__ uf) {
+  constexpr int K = St<SC>::R > St<SF>::R ? St<SC>::R : St<SF>::R;
+  const int Pc = gf.P / K;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gf.npts * Pc) return;
+  const int64_t i = t / Pc;
+  const int c = (int)(t - i * Pc) * K;
+  int x, y, z;
+  coords(gf, i, x, y, z);
+  int px[2], py[2], pz[2] = {0, 0};
+  float wx[2], wy[2], wz[2] = {1.f, 1.f};
+  const int nx = parents(x, gc.nx, px, wx);
+  const int ny = parents(y, gc.ny, py, wy);
+  const int nz = DIM == 3 ? parents(z, gc.nz, pz, wz) : 1;
+  cx<T> acc[K], v[K];
+  ldK<K, SF, T>(uf + i * gf.P + c, acc);
+  for (int a = 0; a < nz; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int e = 0; e < nx; ++e) {
+        const T w = (T)(wx[e] * wy[b] * wz[a]);
+        const int64_t ci = ((int64_t)pz[a] * gc.ny + py[b]) * gc.nx + px[e];
+        ldK<K, SC, T>(ec + ci * gc.P + c, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * v[k];
+      }
+  stK<K, SF, T>(uf + i * gf.P + c, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Layout and precision conversion.
+// ---------------------------------------------------------------------------
+template <class SI, class SO, class T>
+__global__ __launch_bounds__(256) void k_convert(int64_t nvec, const SI* __restrict__ a, SO* __restrict__ b) {
+  constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t * K >= nvec) return;
+  cx<T> v[K];
+  ldK<K, SI, T>(a + t * K, v);
+  stK<K, SO, T>(b + t * K, v);
+}
+
+// ABI [nrhs][N] complex128 -> internal [N][P] (columns >= nrhs zeroed).
+template <class SO>
+__global__ __launch_bounds__(256) void k_to_internal(int64_t N, int nrhs, int P, const c128* __restrict__ src,
+                                                     SO* __restrict__ dst) {
+  __shared__ c128 tile[32][33];
+  const int64_t n0 = (int64_t)blockIdx.x * 32;
+  const int s0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int s = s0 + r;
+    const int64_t n = n0 + tx;
+    tile[r][tx] = (s < nrhs && n < N) ? src[(int64_t)s * N + n] : c128{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t n = n0 + r;
+    const int s = s0 + tx;
+    if (n < N && s < P) put1(dst + n * P + s, tile[tx][r]);
+  }
+}
+
+// internal [N][P] -> ABI [nrhs][N] complex128.
+template <class SI>
+__global__ __launch_bounds__(256) void k_to_abi(int64_t N, int nrhs, int P, const SI* __restrict__ src,
+                                                c128* __restrict__ dst) {
+  __shared__ c128 tile[32][33];
+  const int64_t n0 = (int64_t)blockIdx.x * 32;
+  const int s0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t n = n0 + r;
+    const int s = s0 + tx;
+    c128 v{0.0, 0.0};
+    if (n < N && s < P) v = get1(src + n * P + s);
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int s = s0 + r;
+    const int64_t n = n0 + tx;
+    if (s < nrhs && n < N) dst[(int64_t)s * N + n] = tile[tx][r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 255) / 256)); }
+
+template <class SU, class SF, class SO, class T, int MODE>
+static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, void* out, const void* dg,
+                          const void* dw, const double ih[3], hipStream_t s) {
+  constexpr int K = kmax3<SU, SF, SO>();
+  const int64_t thr = g.npts * (g.P / K);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_fine<3, SU, SF, SO, T, MODE>), grid1(thr), dim3(256), 0, s, g, (const SU*)u, (const SF*)f,
+                       (SO*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0], (T)ih[1], (T)ih[2]);
+  else
+    hipLaunchKernelGGL((k_fine<2, SU, SF, SO, T, MODE>), grid1(thr), dim3(256), 0, s, g, (const SU*)u, (const SF*)f,
+                       (SO*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0], (T)ih[1], (T)ih[2]);
+}
+
+template <class SU, class SF, class SO, class T>
+static void fine_mode(int mode, int dim, const Geo& g, const void* u, const void* f, void* out, const void* dg,
+                      const void* dw, const double ih[3], hipStream_t s) {
+  switch (mode) {
+    case 0: fine_dispatch<SU, SF, SO, T, 0>(dim, g, u, f, out, dg, dw, ih, s); break;
+    case 1: fine_dispatch<SU, SF, SO, T, 1>(dim, g, u, f, out, dg, dw, ih, s); break;
+    case 2: fine_dispatch<SU, SF, SO, T, 2>(dim, g, u, f, out, dg, dw, ih, s); break;
+    default: fine_dispatch<SU, SF, SO, T, 3>(dim, g, u, f, out, dg, dw, ih, s); break;
+  }
+}
+
+void launch_fine(int mode, Prec pu, Prec pf, Prec po, Prec pt, int dim, const Geo& g, const void* u, const void* f,
+                 void* out, const void* dg, const void* dw, const double ih[3], hipStream_t s) {
+  // Supported combinations: FP64 cycle / outer (c128 everywhere, double),
+  // mixed cycle (c64 everywhere, float), outer apply of a c64 field into a
+  // c128 result in double.
+  if (pt == P64) {
+    if (pu == P64 && pf == P64 && po == P64) return fine_mode<c128, c128, c128, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
+    if (pu == P32 && pf == P64 && po == P64) return fine_mode<c64, c128, c128, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
+  } else {
+    if (pu == P32 && pf == P32 && po == P32) return fine_mode<c64, c64, c64, float>(mode, dim, g, u, f, out, dg, dw, ih, s);
+    if (pu == P32 && pf == P64 && po == P32) return fine_mode<c64, c128, c64, float>(mode, dim, g, u, f, out, dg, dw, ih, s);
+  }
+  fatal_combo("launch_fine");
+}
+
+template <class S, class T, int MODE>
+static void gal_dispatch(int dim, const Geo& g, const void* u, const void* f, void* out, const void* st,
+                         const void* dw, hipStream_t s) {
+  const int64_t thr = g.npts * (g.P / St<S>::R);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_gal<3, S, T, MODE>), grid1(thr), dim3(256), 0, s, g, (const S*)u, (const S*)f, (S*)out,
+                       (const cx<T>*)st, (const cx<T>*)dw);
+  else
+    hipLaunchKernelGGL((k_gal<2, S, T, MODE>), grid1(thr), dim3(256), 0, s, g, (const S*)u, (const S*)f, (S*)out,
+                       (const cx<T>*)st, (const cx<T>*)dw);
+}
+
+template <class S, class T>
+static void gal_mode(int mode, int dim, const Geo& g, const void* u, const void* f, void* out, const void* st,
+                     const void* dw, hipStream_t s) {
+  switch (mode) {
+    case 0: gal_dispatch<S, T, 0>(dim, g, u, f, out, st, dw, s); break;
+    case 1: gal_dispatch<S, T, 1>(dim, g, u, f, out, st, dw, s); break;
+    case 2: gal_dispatch<S, T, 2>(dim, g, u, f, out, st, dw, s); break;
+    default: gal_dispatch<S, T, 3>(dim, g, u, f, out, st, dw, s); break;
+  }
+}
+
+void launch_gal(int mode, Prec ps, Prec pt, int dim, const Geo& g, const void* u, const void* f, void* out,
+                const void* st, const void* dw, hipStream_t s) {
+  if (ps == P64 && pt == P64) return gal_mode<c128, double>(mode, dim, g, u, f, out, st, dw, s);
+  if (ps == P32 && pt == P32) return gal_mode<c64, float>(mode, dim, g, u, f, out, st, dw, s);
+  if (ps == PBF && pt == P32) return gal_mode<cbf, float>(mode, dim, g, u, f, out, st, dw, s);
+  fatal_combo("launch_gal");
+}
+
+template <class SI, class SO, class T>
+static void restrict_t(int dim, const Geo& gf, const Geo& gc, const void* rf, void* rc, hipStream_t s) {
+  constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
+  const int64_t thr = gc.npts * (gc.P / K);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_restrict<3, SI, SO, T>), grid1(thr), dim3(256), 0, s, gf, gc, (const SI*)rf, (SO*)rc);
+  else
+    hipLaunchKernelGGL((k_restrict<2, SI, SO, T>), grid1(thr), dim3(256), 0, s, gf, gc, (const SI*)rf, (SO*)rc);
+}
+
+void launch_restrict(Prec pi, Prec po, Prec pt, int dim, const Geo& gf, const Geo& gc, const void* rf, void* rc,
+                     hipStream_t s) {
+  if (pi == P64 && po == P64 && pt == P64) return restrict_t<c128, c128, double>(dim, gf, gc, rf, rc, s);
+  if (pi == P32 && po == P32 && pt == P32) return restrict_t<c64, c64, float>(dim, gf, gc, rf, rc, s);
+  if (pi == P32 && po == PBF && pt == P32) return restrict_t<c64, cbf, float>(dim, gf, gc, rf, rc, s);
+  if (pi == PBF && po == PBF && pt == P32) return restrict_t<cbf, cbf, float>(dim, gf, gc, rf, rc, s);
+  if (pi == PBF && po == P32 && pt == P32) return restrict_t<cbf, c64, float>(dim, gf, gc, rf, rc, s);
+  fatal_combo("launch_restrict");
+}
+
+template <class SC, class SF, class T>
+static void prolong_t(int dim, const Geo& gf, const Geo& gc, const void* ec, void* uf, hipStream_t s) {
+  constexpr int K = St<SC>::R > St<SF>::R ? St<SC>::R : St<SF>::R;
+  const int64_t thr = gf.npts * (gf.P / K);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_prolong_add<3, SC, SF, T>), grid1(thr), dim3(256), 0, s, gf, gc, (const SC*)ec, (SF*)uf);
+  else
+    hipLaunchKernelGGL((k_prolong_add<2, SC, SF, T>), grid1(thr), dim3(256), 0, s, gf, gc, (const SC*)ec, (SF*)uf);
+}
+
+void launch_prolong_add(Prec pc, Prec pf, Prec pt, int dim, const Geo& gf, const Geo& gc, const void* ec, void* uf,
+                        hipStream_t s) {
+  if (pc == P64 && pf == P64 && pt == P64) return prolong_t<c128, c128, double>(dim, gf, gc, ec, uf, s);
+  if (pc == P32 && pf == P32 && pt == P32) return prolong_t<c64, c64, float>(dim, gf, gc, ec, uf, s);
+  if (pc == PBF && pf == P32 && pt == P32) return prolong_t<cbf, c64, float>(dim, gf, gc, ec, uf, s);
+  if (pc == PBF && pf == PBF && pt == P32) return prolong_t<cbf, cbf, float>(dim, gf, gc, ec, uf, s);
+  if (pc == P32 && pf == PBF && pt == P32) return prolong_t<c64, cbf, float>(dim, gf, gc, ec, uf, s);
+  fatal_combo("launch_prolong_add");
+}
+
+void launch_convert(Prec pi, Prec po, int64_t nvals, const void* a, void* b, hipStream_t s) {
+  if (pi == P64 && po == P32)
+    { hipLaunchKernelGGL((k_convert<c128, c64, double>), grid1(nvals / 2), dim3(256), 0, s, nvals, (const c128*)a, (c64*)b); return; }
+  if (pi == P32 && po == P64)
+    { hipLaunchKernelGGL((k_convert<c64, c128, double>), grid1(nvals / 2), dim3(256), 0, s, nvals, (const c64*)a, (c128*)b); return; }
+  if (pi == P32 && po == PBF)
+    { hipLaunchKernelGGL((k_convert<c64, cbf, float>), grid1(nvals / 4), dim3(256), 0, s, nvals, (const c64*)a, (cbf*)b); return; }
+  if (pi == PBF && po == P32)
+    { hipLaunchKernelGGL((k_convert<cbf, c64, float>), grid1(nvals / 4), dim3(256), 0, s, nvals, (const cbf*)a, (c64*)b); return; }
+  if (pi == P64 && po == PBF)
+    { hipLaunchKernelGGL((k_convert<c128, cbf, double>), grid1(nvals / 4), dim3(256), 0, s, nvals, (const c128*)a, (cbf*)b); return; }
+  if (pi == PBF && po == P64)
+    { hipLaunchKernelGGL((k_convert<cbf, c128, double>), grid1(nvals / 4), dim3(256), 0, s, nvals, (const cbf*)a, (c128*)b); return; }
+  fatal_combo("launch_convert");
+}
+
+void launch_to_internal(Prec po, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s) {
+  dim3 gr((unsigned)((N + 31) / 32), (unsigned)((P + 31) / 32));
+  if (po == P64) { hipLaunchKernelGGL((k_to_internal<c128>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (c128*)dst); return; }
+  if (po == P32) { hipLaunchKernelGGL((k_to_internal<c64>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (c64*)dst); return; }
+  { hipLaunchKernelGGL((k_to_internal<cbf>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (cbf*)dst); return; }
+}
+
+void launch_to_abi(Prec pi, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s) {
+  dim3 gr((unsigned)((N + 31) / 32), (unsigned)((P + 31) / 32));
+  if (pi == P64) { hipLaunchKernelGGL((k_to_abi<c128>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (c128*)dst); return; }
+  if (pi == P32) { hipLaunchKernelGGL((k_to_abi<c64>), gr, dim3(256), 0, s, N, nrhs, P, (const c64*)src, (c128*)dst); return; }
+  { hipLaunchKernelGGL((k_to_abi<cbf>), gr, dim3(256), 0, s, N, nrhs, P, (const cbf*)src, (c128*)dst); return; }
+}
+
+}  // namespace helm

@@ -1,0 +1,99 @@
+// kernels.hpp -- host-side launchers of the solver's HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace helm {
+
+enum Prec { P64 = 0, P32 = 1, PBF = 2 };
+
+// Up to MAXPTR device pointers passed by value as a kernel argument.
+constexpr int MAXPTR = 32;
+struct PtrList {
+  const void* p[MAXPTR];
+};
+
+[[noreturn]] void fatal_combo(const char* where);
+
+// ---- k_level.hip ------------------------------------------------------------
+// mode: 0 apply (out = A u), 1 residual (out = f - A u),
+//       2 Jacobi (out = u + dw (f - A u)), 3 zero-guess Jacobi (out = dw f).
+void launch_fine(int mode, Prec pu, Prec pf, Prec po, Prec pt, int dim, const Geo& g, const void* u, const void* f,
+                 void* out, const void* diag, const void* dw, const double ih[3], hipStream_t s);
+void launch_gal(int mode, Prec ps, Prec pt, int dim, const Geo& g, const void* u, const void* f, void* out,
+                const void* st, const void* dw, hipStream_t s);
+void launch_restrict(Prec pi, Prec po, Prec pt, int dim, const Geo& gf, const Geo& gc, const void* rf, void* rc,
+                     hipStream_t s);
+void launch_prolong_add(Prec pc, Prec pf, Prec pt, int dim, const Geo& gf, const Geo& gc, const void* ec, void* uf,
+                        hipStream_t s);
+void launch_convert(Prec pi, Prec po, int64_t nvals, const void* a, void* b, hipStream_t s);
+void launch_to_internal(Prec po, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
+void launch_to_abi(Prec pi, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
+
+// ---- k_setup.hip ------------------------------------------------------------
+// Fine-level diagonals from (m, gamma): dH, dM (shifted) and dw = wjac / dM.
+void launch_fine_coef(int dim, int64_t N, const double* m, const double* gamma, double omega, double beta,
+                      double wjac, const double ih[3], c128* dH, c128* dM, c128* dw, hipStream_t s);
+// Galerkin stencil of the level below the fine one (from the 5/7-point M).
+void launch_galerkin_from_fine(int dim, const Geo& gf, const Geo& gc, const c128* dM, const double ih[3], c128* stc,
+                               hipStream_t s);
+// Galerkin stencil from a 9/27-point level.
+void launch_galerkin_from_gal(int dim, const Geo& gf, const Geo& gc, const c128* stf, c128* stc, hipStream_t s);
+// dw[i] = wjac / st[i][centre].
+void launch_gal_dw(int dim, int64_t N, const c128* st, double wjac, c128* dw, hipStream_t s);
+// Dense row-major matrix of a stencil operator (n x n, n = npts).
+void launch_assemble_dense(int dim, const Geo& g, const c128* st, c128* A, hipStream_t s);
+// FP64 complex -> FP32 complex, elementwise (any length).
+void launch_narrow(int64_t n, const c128* a, c64* b, hipStream_t s);
+// In-place Gauss-Jordan inverse of a dense n x n matrix with block size nb,
+// without pivoting (the shifted operators have a positive definite
+// Hermitian part after multiplication by -i, so every pivot block is
+// nonsingular). Workspace: n*nb*2 + nb*nb complex. Returns 0 or an error.
+int gauss_jordan_inverse(int64_t n, c128* A, int nb, c128* work, hipStream_t s);
+// C = alpha A B + beta C, row-major, complex (T = double or float storage
+// c128 / c64). lda/ldb/ldc in elements.
+void launch_gemm(Prec p, int64_t M, int64_t N, int64_t K, c128 alpha, const void* A, int64_t lda, const void* B,
+                 int64_t ldb, c128 beta, void* C, int64_t ldc, hipStream_t s);
+
+// ---- k_krylov.hip -----------------------------------------------------------
+// Block Gram products per group of pb columns:
+//   G[i][c][a] = sum_n conj(X_i[n][g*pb+a]) Y[n][c],  g = c / pb, c < P,
+// for k <= MAXPTR matrices X_0..X_{k-1}, FP64 c128 [N][ld].
+// `part` is scratch (>= gram_part_elems complex); G has k * P * pb entries.
+// Storage p = P64 (c128) or P32 (c64); accumulation is FP64.
+int64_t gram_part_elems(int P);
+void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList& X, const void* Y, c128* part,
+                 c128* G, hipStream_t s);
+// Y[n][c] (+/-)= sum_i sum_a X_i[n][g*pb+a] C_i[c][a]  (C layout as G).
+//   mode 0: Y -= ..., mode 1: Y = ... (overwrite), mode 2: Y += ...
+// X may be c128 or c64 (px), Y c128 or c64 (py); arithmetic in FP64.
+void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, int pb, int k, const PtrList& X,
+                         const c128* C, void* Y, hipStream_t s);
+// Per group g < ng: Cholesky G_g = R^H R (pb x pb, G layout [c][a] of one X),
+// R and Rinv written [g][pb][pb] row-major (row a, col b). flag[g] = 1 on
+// breakdown (pivot <= tol * max diagonal).
+void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, hipStream_t s);
+// Block FGMRES least squares per group: Hbar_g is ((j+2)pb x (j+1)pb),
+// column-major with leading dimension ldh, stored at Hb + g*hstride; S_g the
+// pb x pb first block (row-major). Writes Y_g ((j+1)pb x pb, column-major
+// ld (j+1)pb... stored at Y + g*ystride) and est[g*pb+b] = residual norm of
+// column b. scratch: per group (j+2)pb*((j+1)pb + pb) complex.
+void launch_block_ls(int ng, int pb, int j, const c128* Hb, int ldh, int64_t hstride, const c128* S, c128* Y,
+                     int64_t ystride, double* est, c128* scratch, const int* active, hipStream_t s);
+// Column norms^2 of a block (P columns of [N][ld]) -> out[P] (double).
+// G: scratch of P complex.
+void launch_colnorm2(Prec p, int64_t N, int ld, int P, const void* X, c128* part, c128* G, double* out,
+                     hipStream_t s);
+// Columns with active[g]==0 are zeroed in Y (inactive groups of the block).
+void launch_mask_cols(int64_t N, int ld, int P, int pb, const int* active, c128* Y, hipStream_t s);
+// Scale columns: Y[n][c] = s[c] * X[n][c] (in place allowed).
+void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const void* X, void* Y, hipStream_t s);
+// Fixed-step per-column GMRES helpers for the coarsest grid.
+void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s);
+void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);
+void launch_cg_ls(int P, int k, const c128* H, const double* b2, c128* Y, hipStream_t s);
+
+}  // namespace helm

@@ -143,8 +143,11 @@ def omega_for_ppw(vmin: float, ppw: float, h: float) -> float:
 
 
 def _spread(count: int, n: int, width: int) -> list:
-    """``count`` node indices (0-based unknowns) evenly over the non-layer span."""
+    """``count`` node indices (0-based unknowns) evenly over the non-layer span
+    (over the whole axis when the layer leaves fewer than ``count`` cells)."""
     lo, hi = width, n - width
+    if hi - lo < count:
+        lo, hi = 0, n
     return [int(round(lo + (hi - lo) * (i + 0.5) / count)) - 1 for i in range(count)]
 
 
