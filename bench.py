@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Benchmark: right-hand sides solved per second to 1e-6 relative residual.
+
+Workload (one "step" = one full block solve, setup excluded as in the
+paper's timings): the 3D Helmholtz equation on a 192^3-cell grid (191^3
+unknowns) with 64 point sources on the top surface, a seeded 8-layer
+velocity model (1.5-4.5 km/s) with a smooth random perturbation, a 12-cell
+absorbing layer, 8 points per wavelength; block FGMRES(5) preconditioned by
+a 3-level shifted-Laplacian V(2,2) cycle (shift 0.2, damped Jacobi 0.8,
+Galerkin coarse operators, 20 GMRES steps on the coarsest grid). Inputs are
+synthetic (no dataset) and resident in device memory when timing starts.
+
+Prints one JSON line. Options select the precision and the block size.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic bytes per point and right-hand side of one launch
+STORE = {"fp64": 16, "mixed": 8}
+
+
+def fine_sweep_bytes(prec, N, P, n_jac0, n_jac):
+    """Damped-Jacobi sweeps on the finest level: the zero-guess sweep reads f
+    and writes u (2 fields), a full sweep reads u and f and writes u (3);
+    per point the diagonal (full sweep) and w/D (both) are read once."""
+    s = STORE[prec]
+    coef = 16 if prec == "fp64" else 8
+    return n_jac0 * N * (2 * s * P + coef) + n_jac * N * (3 * s * P + 2 * coef)
+
+
+def cpu_baseline(p, gpu_cycles, iters):
+    """The oracle (plain FP64 C, OpenMP on this host's cores) on a bounded
+    sample: `iters` preconditioned FGMRES iterations for one right-hand side
+    of the same 192^3 workload; RHS/s = 1 / (time per iteration * cycles the
+    GPU solve needed)."""
+    import oracle
+    g = oracle.grid(p.dim, p.n, p.h)
+    H = oracle.Hierarchy(g, p.m, p.gamma, p.omega, p.shift, 3, coarse="gmres", coarse_iters=20)
+    t0 = time.perf_counter()
+    H.fgmres(p.Q[:1], tol=1e-30, restart=5, maxit=iters)
+    dt = (time.perf_counter() - t0) / iters
+    return {"value": 1.0 / (dt * gpu_cycles), "unit": "RHS/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{iters} FGMRES(5) iterations (V-cycle + outer step) for 1 RHS of the same 192^3 workload, "
+                      f"{dt:.2f} s/iteration, scaled by the {gpu_cycles} cycles of the GPU block solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--n", type=int, default=192)
+    ap.add_argument("--block-size", type=int, default=1)
+    ap.add_argument("--restart", type=int, default=5)
+    ap.add_argument("--coarse-iters", type=int, default=20)
+    ap.add_argument("--reorth", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the workload is one GPU's share); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1607_00968_amd as pk
+
+    p = synth.config(3, n=args.n)
+    t0 = time.perf_counter()
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                       precision=args.precision, coarse="gmres", coarse_iters=args.coarse_iters)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    Q = torch.from_numpy(p.Q).cuda()
+    U = torch.zeros_like(Q)
+
+    def step():
+        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=2000,
+                                   block_size=args.block_size, reorth=args.reorth)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pk.helm_profile_enable(hd, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = pk.helm_profile_read(hd)
+    pk.helm_profile_enable(hd, False)
+
+    dt = t1 - t0
+    cycles = [i["cycles"] for i in infos]
+    ok = all(i["converged_all"] for i in infos)
+    relres = max(float(i["relres"].max()) for i in infos)
+    value = p.nrhs * args.steps / dt if ok else 0.0
+
+    # roofline of the dominant stencil kernel: the finest-level Jacobi sweep
+    N = p.N
+    P = (p.nrhs + 3) // 4 * 4
+    ncyc = sum(cycles)
+    n_jac0, n_jac = ncyc, 3 * ncyc  # V(2,2): one zero-guess sweep + three full sweeps per cycle
+    launches, ms = stats["fine_sweep"]
+    byts = fine_sweep_bytes(args.precision, N, P, n_jac0, n_jac) / max(launches, 1)
+    avg_s = ms / 1e3 / max(launches, 1)
+    achieved = byts / avg_s / 1e9
+    roof = {"kernel": "finest-level damped-Jacobi sweep", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+            "bytes_per_launch": int(byts), "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches}
+    per_step = {k: round(v[1] / args.steps, 2) for k, v in stats.items()}
+
+    out = {
+        "metric": "RHS solved/sec to 1e-6 rel. residual, 3D 192^3 x 64 src",
+        "value": round(value, 4), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64/bf16 cycle + f64 Krylov" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Helmholtz {args.n}^3 cells x {p.nrhs} point sources, 8 ppw, "
+                               f"block FGMRES({args.restart}) + 3-level shifted-Laplacian V(2,2), "
+                               f"GMRES({args.coarse_iters}) coarsest",
+                   "precision": args.precision, "block_size": args.block_size, "reorth": args.reorth,
+                   "cycles_per_step": cycles, "max_relres": relres, "converged": ok,
+                   "setup_s": round(t_setup, 2), "kernel_ms_per_step": per_step},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, cycles[0], args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -102,7 +102,8 @@ typedef struct {
   int32_t max_cycles;  /* cap on preconditioner applications (Arnoldi steps) */
   int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs) */
   int32_t warm_start;  /* 1: U holds an initial guess */
-  int32_t reorth;      /* 1: second block Gram-Schmidt pass + second CholQR pass */
+  int32_t reorth;      /* 0: one block Gram-Schmidt pass; 1: always two; 2: a second
+                          pass only where the norm fell below half (block size 1) */
 } helm_solve_opts;
 
 typedef struct {
@@ -158,6 +159,28 @@ helm_status helm_level_stencil(helm_handle h, int32_t level, double* st);
 /* E = coarsest-grid solve applied to R (as used inside the cycle).
  * R, E: DEVICE complex128 [nrhs][N_coarsest]. */
 helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* E, void* stream);
+
+/* Per-class kernel timing with HIP events recorded on the solve's stream
+ * around every launch of the class (for roofline accounting). */
+enum {
+  HELM_K_FINE_SWEEP = 0, /* damped-Jacobi sweeps on the finest level */
+  HELM_K_FINE_RESID,     /* residual of the cycle on the finest level */
+  HELM_K_OUTER_APPLY,    /* W = H Z and R = Q - H X of the outer Krylov (FP64) */
+  HELM_K_TRANSFER,       /* restriction and prolongation, all levels */
+  HELM_K_COARSE_SWEEP,   /* relaxation / residual on Galerkin levels */
+  HELM_K_COARSEST,       /* the whole coarsest-grid solve */
+  HELM_K_GRAM,           /* block Gram products and column norms */
+  HELM_K_UPDATE,         /* block updates W -= V H, V = W R^-1, X += Z Y */
+  HELM_K_NCLASS
+};
+typedef struct {
+  int32_t launches;
+  double total_ms;
+} helm_kernel_stat;
+/* enable != 0 starts timing (counters reset); 0 stops it. */
+helm_status helm_profile_enable(helm_handle h, int32_t enable);
+/* Fill stats[HELM_K_NCLASS]; synchronises the device. */
+helm_status helm_profile_read(helm_handle h, helm_kernel_stat* stats);
 
 const char* helm_status_string(helm_status s);
 const char* helm_last_error(void);

@@ -21,6 +21,7 @@ import numpy as np
 
 __all__ = [
     "HelmError", "lib", "LIBPATH", "Handle", "helm_setup", "helm_solve_block",
+    "helm_profile_enable", "helm_profile_read", "KERNEL_CLASSES",
     "helm_residual", "helm_apply", "helm_precond", "helm_level_stencil",
     "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "ABI_SYMBOLS",
 ]
@@ -39,8 +40,10 @@ ABI_SYMBOLS = (
     "helm_setup_desc_default", "helm_setup", "helm_destroy", "helm_workspace_size",
     "helm_solve_block", "helm_residual", "helm_apply", "helm_precond",
     "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
-    "helm_status_string", "helm_last_error",
+    "helm_profile_enable", "helm_profile_read", "helm_status_string", "helm_last_error",
 )
+KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
+                  "coarsest", "gram", "update")
 
 
 class HelmError(RuntimeError):
@@ -96,6 +99,8 @@ def lib():
         L.helm_level_dims.argtypes = [P, I, P]
         L.helm_level_stencil.argtypes = [P, I, P]
         L.helm_coarse_solve.argtypes = [P, I, P, P, P]
+        L.helm_profile_enable.argtypes = [P, I]
+        L.helm_profile_read.argtypes = [P, P]
         L.helm_status_string.restype = C.c_char_p
         L.helm_status_string.argtypes = [I]
         L.helm_last_error.restype = C.c_char_p
@@ -257,3 +262,19 @@ def helm_level_stencil(hd: Handle, level: int) -> np.ndarray:
     st = np.zeros((int(np.prod(nu)), ns), np.complex128)
     _check(lib().helm_level_stencil(hd.ptr, level, st.ctypes.data))
     return st
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int32), ("total_ms", C.c_double)]
+
+
+def helm_profile_enable(hd: Handle, enable: bool = True):
+    """Start (counters reset) or stop per-class kernel timing with HIP events."""
+    _check(lib().helm_profile_enable(hd.ptr, 1 if enable else 0))
+
+
+def helm_profile_read(hd: Handle) -> dict:
+    """{class: (launches, total_ms)} for every kernel class."""
+    arr = (KernelStat * len(KERNEL_CLASSES))()
+    _check(lib().helm_profile_read(hd.ptr, C.cast(arr, C.c_void_p)))
+    return {name: (arr[i].launches, arr[i].total_ms) for i, name in enumerate(KERNEL_CLASSES)}

@@ -108,9 +108,42 @@ struct helm_ctx {
   std::vector<void*> kbuf;
   double* hbuf = nullptr;  // pinned host scratch
   size_t hbufn = 0;
+  // per-class kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  std::vector<int> evcls;
+  size_t evused = 0;
 };
 
 namespace helm {
+
+// Records a HIP event pair around the launches in its scope when timing is on.
+struct Prof {
+  helm_ctx* c;
+  hipStream_t s;
+  size_t idx = 0;
+  bool on;
+  Prof(helm_ctx* c_, int cls, hipStream_t s_) : c(c_), s(s_), on(c_->prof) {
+    if (!on) return;
+    if (c->evused + 2 > c->evpool.size()) {
+      for (int k = 0; k < 256; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        c->evpool.push_back(e);
+      }
+    }
+    idx = c->evused;
+    c->evused += 2;
+    c->evcls.push_back(cls);
+    hipEventRecord(c->evpool[idx], s);
+  }
+  ~Prof() {
+    if (on) hipEventRecord(c->evpool[idx + 1], s);
+  }
+};
 
 static Prec field_prec(const helm_ctx* c, int l) {
   if (c->precision == HELM_FP64) return P64;
@@ -134,6 +167,7 @@ __global__ void k_add_c128(int64_t n, const c128* __restrict__ x, c128* __restri
 
 // One relaxation-family launch on level l (mode as launch_fine).
 static void level_op(helm_ctx* c, int l, int mode, int P, const void* u, const void* f, void* out, hipStream_t s) {
+  Prof pr(c, l == 0 ? (mode == 1 ? HELM_K_FINE_RESID : HELM_K_FINE_SWEEP) : HELM_K_COARSE_SWEEP, s);
   const Level& L = c->lv[l];
   const Prec pf = field_prec(c, l), pt = comp_prec(c);
   if (l == 0) {
@@ -156,7 +190,13 @@ void field_axpy(helm_ctx* c, int l, int P, const void* x, void* y, hipStream_t s
 static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void* tmp, hipStream_t s) {
   Level& L = c->lv[l];
   if (l == c->L - 1) {
-    coarsest_solve(c, P, f, out, s);
+    const bool was = c->prof;
+    {
+      Prof pr(c, HELM_K_COARSEST, s);
+      c->prof = false;  // time the coarsest solve as one unit
+      coarsest_solve(c, P, f, out, s);
+      c->prof = was;
+    }
     return;
   }
   const int npre = c->nu_pre[l], npost = c->nu_post[l];
@@ -175,7 +215,10 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   level_op(c, l, 1, P, a, f, L.Rr, s);
   Level& C = c->lv[l + 1];
   const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
-  launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
+  {
+    Prof pr(c, HELM_K_TRANSFER, s);
+    launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
+  }
   cycle_rec(c, l + 1, P, C.F, C.U0, C.U1, s);
   if (c->cycle == HELM_CYCLE_W && l + 1 < c->L - 1) {
     // W-cycle: a second coarse cycle on the residual of the first result,
@@ -184,7 +227,10 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
     cycle_rec(c, l + 1, P, c->kbuf[l + 1], C.U1, C.F, s);
     field_axpy(c, l + 1, P, C.U1, C.U0, s);
   }
-  launch_prolong_add(pc, pf, pt, c->dim, L.geo(P), C.geo(P), C.U0, a, s);
+  {
+    Prof pr(c, HELM_K_TRANSFER, s);
+    launch_prolong_add(pc, pf, pt, c->dim, L.geo(P), C.geo(P), C.U0, a, s);
+  }
   for (int k = 0; k < npost; ++k) {
     level_op(c, l, 2, P, a, f, b, s);
     std::swap(a, b);
@@ -206,8 +252,7 @@ static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, hipStream
   char* V = m;
   c128* H = reinterpret_cast<c128*>(m + vb * (k + 1));
   c128* Gc = H + (size_t)P * (k + 1) * k;
-  c128* G2 = Gc + (size_t)(k + 1) * P;
-  c128* Yc = G2 + (size_t)(k + 1) * P;
+  c128* Yc = Gc + (size_t)2 * (k + 1) * P;
   c128* part = Yc + (size_t)(k + 1) * P;
   c128* Gs = part + gram_part_elems(P);
   double* b2 = reinterpret_cast<double*>(Gs + 2 * P);
@@ -221,13 +266,9 @@ static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, hipStream
   for (int j = 0; j < k; ++j) {
     vl.p[j] = vec(j);
     level_op(c, l, 0, P, vec(j), nullptr, vec(j + 1), s);
+    // one classical Gram-Schmidt pass; the update also yields ||w||^2
     launch_gram(p, N, P, P, 1, j + 1, vl, vec(j + 1), part, Gc, s);
-    launch_block_update(0, p, p, N, P, P, 1, j + 1, vl, Gc, vec(j + 1), s);
-    launch_gram(p, N, P, P, 1, j + 1, vl, vec(j + 1), part, G2, s);
-    launch_block_update(0, p, p, N, P, P, 1, j + 1, vl, G2, vec(j + 1), s);
-    const int64_t ne = (int64_t)(j + 1) * P;
-    hipLaunchKernelGGL(k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G2, Gc);
-    launch_colnorm2(p, N, P, P, vec(j + 1), part, Gs, hn2, s);
+    launch_update_norm(p, N, P, P, j + 1, vl, Gc, vec(j + 1), part, Gs, hn2, s);
     launch_cg_hcol(P, j, k, Gc, hn2, H, sc, s);
     launch_scale_cols(p, N, P, P, sc, vec(j + 1), vec(j + 1), s);
   }
@@ -385,6 +426,7 @@ static void free_ctx(helm_ctx* c) {
   hipFree(c->ws);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->net) learned::destroy(c->net);
+  for (hipEvent_t e : c->evpool) hipEventDestroy(e);
   delete c;
 }
 
@@ -538,6 +580,33 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   return HELM_OK;
 }
 
+helm_status helm_profile_enable(helm_handle h, int32_t enable) {
+  if (!h) return fail(HELM_ERR_INVALID_ARG, "null handle");
+  HCHECK(hipDeviceSynchronize());
+  h->prof = enable != 0;
+  if (h->prof) {
+    h->evused = 0;
+    h->evcls.clear();
+  }
+  return HELM_OK;
+}
+
+helm_status helm_profile_read(helm_handle h, helm_kernel_stat* stats) {
+  if (!h || !stats) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  HCHECK(hipDeviceSynchronize());
+  for (int k = 0; k < HELM_K_NCLASS; ++k) stats[k] = helm_kernel_stat{0, 0.0};
+  for (size_t p = 0; p < h->evcls.size(); ++p) {
+    float ms = 0.f;
+    HCHECK(hipEventElapsedTime(&ms, h->evpool[2 * p], h->evpool[2 * p + 1]));
+    const int cls = h->evcls[p];
+    if (cls >= 0 && cls < HELM_K_NCLASS) {
+      stats[cls].launches += 1;
+      stats[cls].total_ms += ms;
+    }
+  }
+  return HELM_OK;
+}
+
 helm_status helm_level_dims(helm_handle h, int32_t level, int32_t nu[3]) {
   if (!h || !nu || level < 0 || level >= h->L) return fail(HELM_ERR_INVALID_ARG, "bad level");
   for (int a = 0; a < 3; ++a) nu[a] = h->lv[level].nu[a];
@@ -634,7 +703,7 @@ helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* 
 // Krylov workspace layout (bytes, 256-aligned).
 // ---------------------------------------------------------------------------
 struct WsLayout {
-  size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, flag, act, ls, end;
+  size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, w2, hn2, flag, act, ls, end;
 };
 
 static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
@@ -662,6 +731,8 @@ static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
   w.est = o; o += al(8 * (size_t)P);
   w.qn2 = o; o += al(8 * (size_t)P);
   w.rn2 = o; o += al(8 * (size_t)P);
+  w.w2 = o; o += al(8 * (size_t)P);
+  w.hn2 = o; o += al(8 * (size_t)P);
   w.flag = o; o += al(4 * (size_t)ng);
   w.act = o; o += al(4 * (size_t)ng);
   w.ls = o; o += al(16 * (size_t)ng * (m + 1) * pb * (m + 1) * pb);
@@ -722,7 +793,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   helm_status st = check_block(h, nrhs, Q, U);
   if (st != HELM_OK) return st;
   if (!(tol > 0) || !std::isfinite(tol)) return fail(HELM_ERR_INVALID_ARG, "tol must be > 0");
-  helm_solve_opts o{5, 1000, 0, 0, 1};
+  helm_solve_opts o{5, 1000, 0, 0, 2};
   if (opts) o = *opts;
   const int m = o.restart;
   if (m < 1 || m >= MAXPTR) return fail(HELM_ERR_INVALID_ARG, "restart must be 1..%d", MAXPTR - 1);
@@ -782,6 +853,8 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   double* dest = (double*)(base + w.est);
   double* dq = (double*)(base + w.qn2);
   double* dr = (double*)(base + w.rn2);
+  double* dw2 = (double*)(base + w.w2);
+  double* dhn2 = (double*)(base + w.hn2);
   int* dflag = (int*)(base + w.flag);
   int* dact = (int*)(base + w.act);
   c128* lsw = (c128*)(base + w.ls);
@@ -799,7 +872,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     launch_to_internal(P64, N, nrhs, P, U, X, s);
   else
     hipMemsetAsync(X, 0, blk, s);
-  launch_colnorm2(P64, N, P, Pa, Qi, part, G, dq, s);
+  { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, Qi, part, G, dq, s); }
   HCHECK(hipMemcpyAsync(hq, dq, 8 * Pa, hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
   for (int cidx = 0; cidx < Pa; ++cidx)
@@ -816,7 +889,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   for (;;) {
     // true FP64 residual R = Q - H X into V0
     launch_fine(1, P64, P64, P64, P64, c->dim, g0, X, Qi, V[0], L0.dH, nullptr, L0.ih, s);
-    launch_colnorm2(P64, N, P, Pa, V[0], part, G, dr, s);
+    { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, V[0], part, G, dr, s); }
     HCHECK(hipMemcpyAsync(hr, dr, 8 * Pa, hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
     HCHECK(hipGetLastError());
@@ -837,14 +910,18 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     if (cycles >= o.max_cycles || breakdown) break;
     restarts += cycles > 0;
     hipLaunchKernelGGL(k_set_active, dim3((ng + 255) / 256), dim3(256), 0, s, ng, pb, tol2, dr, dq, dact);
-    // V0 S = R (CholQR)
+    // V0 S = R: CholQR, or plain normalisation for block size 1
     {
       PtrList xl{};
       xl.p[0] = V[0];
-      launch_gram(P64, N, P, Pa, pb, 1, xl, V[0], part, G, s);
-      launch_cholqr_small(ng, pb, G, S, Rinv, dflag, chol_tol, s);
+      if (pb == 1) {
+        launch_norm_to_r(Pa, dr, nullptr, 0.0, S, Rinv, dflag, s);
+      } else {
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, xl, V[0], part, G, s); }
+        launch_cholqr_small(ng, pb, G, S, Rinv, dflag, chol_tol, s);
+      }
       hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-      launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s);
+      { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s); }
       std::swap(V[0], W);
       HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
       HCHECK(hipMemsetAsync(Hb, 0, 16 * (size_t)hstride * ng, s));
@@ -872,25 +949,58 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       }
       ++cycles;
       // W = H Z_j (FP64)
-      launch_fine(0, pz, P64, P64, P64, c->dim, g0, Z[j], nullptr, W, L0.dH, nullptr, L0.ih, s);
-      // block classical Gram-Schmidt against V_0..V_j (twice if reorth)
+      {
+        Prof pr(c, HELM_K_OUTER_APPLY, s);
+        launch_fine(0, pz, P64, P64, P64, c->dim, g0, Z[j], nullptr, W, L0.dH, nullptr, L0.ih, s);
+      }
+      // block classical Gram-Schmidt against V_0..V_j, then W = V_{j+1} R
       PtrList vl{};
       for (int i = 0; i <= j; ++i) vl.p[i] = V[i];
-      launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, Gc, s);
-      launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, Gc, W, s);
-      if (o.reorth) {
-        launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, G, s);
-        launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, G, W, s);
-        const int64_t ne = (int64_t)(j + 1) * Pa * pb;
-        hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
+      if (pb == 1) {
+        // one pass computes V^H W and ||W||^2; the update returns ||W'||^2;
+        // a second pass runs when asked (reorth 1) or when the norm dropped
+        // below half (reorth 2, the "twice is enough" test)
+        PtrList vw = vl;
+        vw.p[j + 1] = W;
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 2, vw, W, part, Gc, s); }
+        launch_diag_real(Pa, Gc + (size_t)(j + 1) * Pa, dw2, s);
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G, dhn2, s); }
+        bool again = o.reorth == 1;
+        if (o.reorth == 2) {
+          std::vector<double> a(Pa), b(Pa);
+          HCHECK(hipMemcpyAsync(a.data(), dw2, 8 * Pa, hipMemcpyDeviceToHost, s));
+          HCHECK(hipMemcpyAsync(b.data(), dhn2, 8 * Pa, hipMemcpyDeviceToHost, s));
+          HCHECK(hipStreamSynchronize(s));
+          for (int cidx = 0; cidx < Pa; ++cidx)
+            if (hact[cidx] && b[cidx] < 0.25 * a[cidx]) again = true;
+        }
+        if (again) {
+          { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 1, vl, W, part, G, s); }
+          { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, G, W, part, G + (size_t)(j + 1) * Pa, dhn2, s); }
+          const int64_t ne = (int64_t)(j + 1) * Pa;
+          hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
+        }
+        launch_norm_to_r(Pa, dhn2, dw2, 1e-28, Rm, Rinv, dflag, s);
+        hipLaunchKernelGGL(k_zero_inactive, dim3((P + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+        PtrList wl{};
+        wl.p[0] = W;
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s); }
+      } else {
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, Gc, s); }
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, Gc, W, s); }
+        if (o.reorth) {
+          { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, G, s); }
+          { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, G, W, s); }
+          const int64_t ne = (int64_t)(j + 1) * Pa * pb;
+          hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
+        }
+        PtrList wl{};
+        wl.p[0] = W;
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, wl, W, part, G, s); }
+        launch_cholqr_small(ng, pb, G, Rm, Rinv, dflag, chol_tol, s);
+        hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s); }
       }
-      // W = V_{j+1} R (CholQR)
-      PtrList wl{};
-      wl.p[0] = W;
-      launch_gram(P64, N, P, Pa, pb, 1, wl, W, part, G, s);
-      launch_cholqr_small(ng, pb, G, Rm, Rinv, dflag, chol_tol, s);
-      hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-      launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s);
       hipLaunchKernelGGL(k_hscatter, dim3(ng), dim3(256), 0, s, pb, j, Pa, Gc, Rm, Hb, ldh, hstride);
       launch_block_ls(ng, pb, j, Hb, ldh, hstride, S, Yc, 0, dest, lsw, dact, s);
       HCHECK(hipMemcpyAsync(hest, dest, 8 * Pa, hipMemcpyDeviceToHost, s));
@@ -910,7 +1020,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
                        pb, Pa, jlast + 1, dact, Yc);
     PtrList zl{};
     for (int i = 0; i <= jlast; ++i) zl.p[i] = Z[i];
-    launch_block_update(2, pz, P64, N, P, Pa, pb, jlast + 1, zl, Yc, X, s);
+    { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(2, pz, P64, N, P, Pa, pb, jlast + 1, zl, Yc, X, s); }
   }
   launch_to_abi(P64, N, nrhs, P, X, U, s);
   HCHECK(hipEventRecord(e1, s));

@@ -68,15 +68,37 @@ __global__ __launch_bounds__(256) void k_gram_part(int64_t N, int ld, int P, int
   }
 }
 
-// G[i][c][a0+a] = sum over blocks of part (fixed order).
-__global__ void k_gram_final(int nblk, int P, int pb, int k, int i0, int a0, int na, const c128* __restrict__ part,
-                             c128* __restrict__ G) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= k * P * na) return;
-  const int a = o % na, c = (o / na) % P, i = o / (na * P);
-  cx<double> s = {0.0, 0.0};
-  for (int b = 0; b < nblk; ++b) s = s + tcx(part[(int64_t)b * k * P * na + o]);
-  G[((int64_t)(i0 + i) * P + c) * pb + a0 + a] = fcx(s);
+// G[i][c][a0+a] = sum over blocks of part, in a fixed order: each
+// workgroup owns 64 consecutive outputs; its four waves sum interleaved
+// quarters of the partials (eight independent accumulators per lane) and
+// the quarters are added through LDS.
+__global__ __launch_bounds__(256) void k_gram_final(int nblk, int P, int pb, int k, int i0, int a0, int na,
+                                                    const c128* __restrict__ part, c128* __restrict__ G) {
+  __shared__ cx<double> red[4][64];
+  const int nout = k * P * na;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + lane;
+  cx<double> acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = {0.0, 0.0};
+  if (o < nout) {
+    int b = q;
+    for (; b + 28 < nblk; b += 32) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = acc[u] + tcx(part[(int64_t)(b + 4 * u) * nout + o]);
+    }
+    for (; b < nblk; b += 4) acc[0] = acc[0] + tcx(part[(int64_t)b * nout + o]);
+  }
+  cx<double> s = acc[0];
+#pragma unroll
+  for (int u = 1; u < 8; ++u) s = s + acc[u];
+  red[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && o < nout) {
+    s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    const int a = o % na, c = (o / na) % P, i = o / (na * P);
+    G[((int64_t)(i0 + i) * P + c) * pb + a0 + a] = fcx(s);
+  }
 }
 
 int64_t gram_part_elems(int P) { return (int64_t)GRAM_BLOCKS * GRAM_MAXACC * P; }
@@ -104,8 +126,7 @@ void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList&
         hipLaunchKernelGGL((k_gram_part<c64>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, kc, a0, na, sub,
                            (const c64*)Y, part);
       const int outs = kc * P * na;
-      hipLaunchKernelGGL(k_gram_final, dim3((outs + 255) / 256), dim3(256), 0, s, nblk, P, pb, kc, i0, a0, na, part,
-                         G);
+      hipLaunchKernelGGL(k_gram_final, dim3((outs + 63) / 64), dim3(256), 0, s, nblk, P, pb, kc, i0, a0, na, part, G);
     }
   }
 }
@@ -340,6 +361,10 @@ __global__ void k_diag_real(int P, const c128* __restrict__ G, double* __restric
   if (c < P) out[c] = G[c].re;
 }
 
+void launch_diag_real(int P, const c128* G, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_real, dim3((P + 255) / 256), dim3(256), 0, s, P, G, out);
+}
+
 void launch_colnorm2(Prec p, int64_t N, int ld, int P, const void* X, c128* part, c128* G, double* out,
                      hipStream_t s) {
   PtrList xl{};
@@ -378,6 +403,84 @@ void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const
     hipLaunchKernelGGL((k_scale_cols<c64>), gr, dim3(256), 0, s, N, ld, P, sc, (const c64*)X, (c64*)Y);
   else
     fatal_combo("launch_scale_cols");
+}
+
+// ---------------------------------------------------------------------------
+// Block size 1: Y[n][c] -= sum_i X_i[n][c] C[i][c], and the new ||Y_c||^2 as
+// per-workgroup partials (same lane layout as the Gram kernel, so the final
+// reduction is k_gram_final with k = na = pb = 1).
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int P, int k, PtrList X,
+                                                          const c128* __restrict__ C, S* __restrict__ Y,
+                                                          c128* __restrict__ part) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int PT = 256 / P;
+  const int c = tid % P, r = tid / P;
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t nb0 = (int64_t)blockIdx.x * chunk;
+  const int64_t nb1 = nb0 + chunk < N ? nb0 + chunk : N;
+  double nrm = 0.0;
+  using E = decltype(Y->re);
+  if (r < PT) {
+    cx<double> coef[MAXPTR];
+    for (int i = 0; i < k; ++i) coef[i] = tcx(C[(int64_t)i * P + c]);
+    for (int64_t n = nb0 + r; n < nb1; n += PT) {
+      const int64_t e = n * ld + c;
+      const S yv = Y[e];
+      cx<double> y = {(double)yv.re, (double)yv.im};
+      for (int i = 0; i < k; ++i) {
+        const S xv = static_cast<const S*>(X.p[i])[e];
+        cfma(y, cx<double>{-(double)xv.re, -(double)xv.im}, coef[i]);
+      }
+      const S out = S{(E)y.re, (E)y.im};
+      Y[e] = out;
+      nrm += (double)out.re * (double)out.re + (double)out.im * (double)out.im;
+    }
+  }
+  red[tid] = nrm;
+  __syncthreads();
+  for (int cc = tid; cc < P; cc += 256) {
+    double s = 0.0;
+    for (int rr = 0; rr < PT; ++rr) s += red[rr * P + cc];
+    part[(int64_t)blockIdx.x * P + cc] = c128{s, 0.0};
+  }
+}
+
+void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& X, const c128* C, void* Y,
+                        c128* part, c128* G, double* nrm2, hipStream_t s) {
+  if (P > 256 || k > MAXPTR) fatal_combo("launch_update_norm");
+  int nblk = GRAM_BLOCKS;
+  const int64_t minpts = (256 / P) * 4;
+  if (N < (int64_t)nblk * minpts) nblk = (int)((N + minpts - 1) / minpts);
+  if (nblk < 1) nblk = 1;
+  if (p == P64)
+    hipLaunchKernelGGL((k_update_norm_part<c128>), dim3(nblk), dim3(256), 0, s, N, ld, P, k, X, C, (c128*)Y, part);
+  else if (p == P32)
+    hipLaunchKernelGGL((k_update_norm_part<c64>), dim3(nblk), dim3(256), 0, s, N, ld, P, k, X, C, (c64*)Y, part);
+  else
+    fatal_combo("launch_update_norm");
+  hipLaunchKernelGGL(k_gram_final, dim3((P + 63) / 64), dim3(256), 0, s, nblk, P, 1, 1, 0, 0, 1, part, G);
+  hipLaunchKernelGGL(k_diag_real, dim3((P + 255) / 256), dim3(256), 0, s, P, G, nrm2);
+}
+
+// From ||w||^2 per column (block size 1): R = ||w||, Rinv = 1/||w|| (0 and a
+// breakdown flag when the column vanished, or is tiny against ref2).
+__global__ void k_norm_to_r(int P, const double* __restrict__ n2, const double* __restrict__ ref2, double tol,
+                            c128* __restrict__ R, c128* __restrict__ Rinv, int* __restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  const double v = n2[c];
+  const bool bad = !(v > tol * (ref2 ? ref2[c] : 0.0)) || !(v > 0.0);
+  const double nr = bad ? 0.0 : sqrt(v);
+  R[c] = c128{nr, 0.0};
+  Rinv[c] = c128{bad ? 0.0 : 1.0 / nr, 0.0};
+  flag[c] = bad ? 1 : 0;
+}
+void launch_norm_to_r(int P, const double* n2, const double* ref2, double tol, c128* R, c128* Rinv, int* flag,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_to_r, dim3((P + 255) / 256), dim3(256), 0, s, P, n2, ref2, tol, R, Rinv, flag);
 }
 
 // ---------------------------------------------------------------------------

@@ -154,28 +154,22 @@ __global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, con
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = {(T)0, (T)0};
   const cx<T>* sp = st + i * NS;
-  const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+  // one stencil entry per iteration, unrolled by 3 only: bounds the number
+  // of neighbour loads in flight (and so the registers they hold)
+#pragma unroll 3
+  for (int o = 0; o < NS; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
+    const bool ok = (x + ox >= 0) && (x + ox < g.nx) && (y + oy >= 0) && (y + oy < g.ny) && (z + oz >= 0) &&
+                    (z + oz < g.nz);
+    const int64_t off = (((int64_t)oz * g.ny + oy) * g.nx + ox) * g.P;
+    ldKz<K, S, T>(u + base + off, ok, nb);
+    if (o == NS / 2) {
 #pragma unroll
-  for (int oz = zlo; oz <= zhi; ++oz) {
-    const bool okz = (z + oz >= 0) && (z + oz < g.nz);
-#pragma unroll
-    for (int oy = -1; oy <= 1; ++oy) {
-      const bool oky = okz && (y + oy >= 0) && (y + oy < g.ny);
-#pragma unroll
-      for (int ox = -1; ox <= 1; ++ox) {
-        const bool ok = oky && (x + ox >= 0) && (x + ox < g.nx);
-        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-        const int64_t off = (((int64_t)oz * g.ny + oy) * g.nx + ox) * g.P;
-        ldKz<K, S, T>(u + base + off, ok, nb);
-        if (ox == 0 && oy == 0 && oz == 0) {
-#pragma unroll
-          for (int k = 0; k < K; ++k) uc[k] = nb[k];
-        }
-        const cx<T> a = sp[o];
-#pragma unroll
-        for (int k = 0; k < K; ++k) cfma(acc[k], a, nb[k]);
-      }
+      for (int k = 0; k < K; ++k) uc[k] = nb[k];
     }
+    const cx<T> a = sp[o];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cfma(acc[k], a, nb[k]);
   }
   if (MODE == 0) {
     stK<K, S, T>(out + base, acc);

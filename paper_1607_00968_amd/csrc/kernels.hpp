@@ -87,10 +87,19 @@ void launch_block_ls(int ng, int pb, int j, const c128* Hb, int ldh, int64_t hst
 // G: scratch of P complex.
 void launch_colnorm2(Prec p, int64_t N, int ld, int P, const void* X, c128* part, c128* G, double* out,
                      hipStream_t s);
+// out[c] = Re G[c], c < P.
+void launch_diag_real(int P, const c128* G, double* out, hipStream_t s);
 // Columns with active[g]==0 are zeroed in Y (inactive groups of the block).
 void launch_mask_cols(int64_t N, int ld, int P, int pb, const int* active, c128* Y, hipStream_t s);
 // Scale columns: Y[n][c] = s[c] * X[n][c] (in place allowed).
 void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const void* X, void* Y, hipStream_t s);
+// Block size 1: Y -= sum_i X_i C_i (per column) and nrm2[c] = ||Y_c||^2 after
+// the update (part: gram_part_elems scratch; G: P complex scratch).
+void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& X, const c128* C, void* Y,
+                        c128* part, c128* G, double* nrm2, hipStream_t s);
+// R = ||w||, Rinv = 1/||w|| per column from n2; flag where n2 <= tol*ref2.
+void launch_norm_to_r(int P, const double* n2, const double* ref2, double tol, c128* R, c128* Rinv, int* flag,
+                      hipStream_t s);
 // Fixed-step per-column GMRES helpers for the coarsest grid.
 void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s);
 void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);
