@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--coarse-iters", type=int, default=20)
     ap.add_argument("--reorth", type=int, default=2)
     ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--max-cycles", type=int, default=2000,
+                    help="cap on cycles per solve (profiling runs; a capped solve reports value 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -86,7 +88,7 @@ def main():
     U = torch.zeros_like(Q)
 
     def step():
-        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=2000,
+        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
                                    block_size=args.block_size, reorth=args.reorth)
 
     for _ in range(args.warmup):

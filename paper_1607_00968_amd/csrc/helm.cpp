@@ -703,7 +703,7 @@ helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* 
 // Krylov workspace layout (bytes, 256-aligned).
 // ---------------------------------------------------------------------------
 struct WsLayout {
-  size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, w2, hn2, flag, act, ls, end;
+  size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, w2, hn2, nu, flag, act, ls, end;
 };
 
 static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
@@ -733,6 +733,7 @@ static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
   w.rn2 = o; o += al(8 * (size_t)P);
   w.w2 = o; o += al(8 * (size_t)P);
   w.hn2 = o; o += al(8 * (size_t)P);
+  w.nu = o; o += al(8 * (size_t)P * (m + 1));
   w.flag = o; o += al(4 * (size_t)ng);
   w.act = o; o += al(4 * (size_t)ng);
   w.ls = o; o += al(16 * (size_t)ng * (m + 1) * pb * (m + 1) * pb);
@@ -855,6 +856,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   double* dr = (double*)(base + w.rn2);
   double* dw2 = (double*)(base + w.w2);
   double* dhn2 = (double*)(base + w.hn2);
+  double* dnu = (double*)(base + w.nu);
   int* dflag = (int*)(base + w.flag);
   int* dact = (int*)(base + w.act);
   c128* lsw = (c128*)(base + w.ls);
@@ -915,14 +917,15 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       PtrList xl{};
       xl.p[0] = V[0];
       if (pb == 1) {
-        launch_norm_to_r(Pa, dr, nullptr, 0.0, S, Rinv, dflag, s);
+        // unnormalised basis: v~_0 = r with nu_0 = ||r|| (no scaling pass)
+        launch_lazy_start(Pa, dr, dnu, S, dflag, s);
       } else {
         { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, xl, V[0], part, G, s); }
         launch_cholqr_small(ng, pb, G, S, Rinv, dflag, chol_tol, s);
+        hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s); }
+        std::swap(V[0], W);
       }
-      hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-      { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s); }
-      std::swap(V[0], W);
       HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
       HCHECK(hipMemsetAsync(Hb, 0, 16 * (size_t)hstride * ng, s));
       HCHECK(hipStreamSynchronize(s));
@@ -957,14 +960,16 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       PtrList vl{};
       for (int i = 0; i <= j; ++i) vl.p[i] = V[i];
       if (pb == 1) {
-        // one pass computes V^H W and ||W||^2; the update returns ||W'||^2;
-        // a second pass runs when asked (reorth 1) or when the norm dropped
-        // below half (reorth 2, the "twice is enough" test)
+        // One pass gives v~_i^H W~ and ||W~||^2, the update returns ||W~'||^2;
+        // a second pass runs when asked (reorth 1) or where the norm fell
+        // below half (reorth 2, the "twice is enough" test). The new vector
+        // is kept unnormalised (nu_{j+1} = its norm), so W~' becomes v~_{j+1}.
         PtrList vw = vl;
         vw.p[j + 1] = W;
-        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 2, vw, W, part, Gc, s); }
-        launch_diag_real(Pa, Gc + (size_t)(j + 1) * Pa, dw2, s);
-        { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G, dhn2, s); }
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 2, vw, W, part, G, s); }
+        launch_diag_real(Pa, G + (size_t)(j + 1) * Pa, dw2, s);
+        launch_lazy_coef(Pa, j, G, dnu, Gc, Hb, ldh, hstride, 0, s);
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
         bool again = o.reorth == 1;
         if (o.reorth == 2) {
           std::vector<double> a(Pa), b(Pa);
@@ -976,15 +981,11 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
         }
         if (again) {
           { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 1, vl, W, part, G, s); }
-          { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, G, W, part, G + (size_t)(j + 1) * Pa, dhn2, s); }
-          const int64_t ne = (int64_t)(j + 1) * Pa;
-          hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
+          launch_lazy_coef(Pa, j, G, dnu, Gc, Hb, ldh, hstride, 1, s);
+          { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
         }
-        launch_norm_to_r(Pa, dhn2, dw2, 1e-28, Rm, Rinv, dflag, s);
-        hipLaunchKernelGGL(k_zero_inactive, dim3((P + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-        PtrList wl{};
-        wl.p[0] = W;
-        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s); }
+        launch_lazy_next(Pa, j, dhn2, dw2, 1e-28, dnu, Hb, ldh, hstride, dflag, s);
+        std::swap(V[j + 1], W);
       } else {
         { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, j + 1, vl, W, part, Gc, s); }
         { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(0, P64, P64, N, P, Pa, pb, j + 1, vl, Gc, W, s); }
@@ -1001,7 +1002,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
         hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
         { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s); }
       }
-      hipLaunchKernelGGL(k_hscatter, dim3(ng), dim3(256), 0, s, pb, j, Pa, Gc, Rm, Hb, ldh, hstride);
+      if (pb > 1) hipLaunchKernelGGL(k_hscatter, dim3(ng), dim3(256), 0, s, pb, j, Pa, Gc, Rm, Hb, ldh, hstride);
       launch_block_ls(ng, pb, j, Hb, ldh, hstride, S, Yc, 0, dest, lsw, dact, s);
       HCHECK(hipMemcpyAsync(hest, dest, 8 * Pa, hipMemcpyDeviceToHost, s));
       HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
@@ -1015,7 +1016,8 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       jlast = j;
       if (conv || brk || j == m - 1 || cycles >= o.max_cycles) break;
     }
-    // X += sum_j Z_j Y_j
+    // X += sum_j Z_j Y_j (block size 1: the stored z~_j carry the factor nu_j)
+    if (pb == 1) launch_lazy_y(Pa, jlast + 1, dnu, Yc, s);
     hipLaunchKernelGGL(k_zero_inactive, dim3((unsigned)(((jlast + 1) * P * pb + 255) / 256)), dim3(256), 0, s, ng,
                        pb, Pa, jlast + 1, dact, Yc);
     PtrList zl{};

@@ -21,83 +21,95 @@ __device__ inline cx<double> tcx(c128 v) { return {v.re, v.im}; }
 __device__ inline c128 fcx(cx<double> v) { return {v.re, v.im}; }
 
 constexpr int GRAM_MAXACC = 16;
-constexpr int GRAM_BLOCKS = 1024;
+constexpr int GRAM_BLOCKS = 2048;
 
 // part[blk][i][c][a] for i < k, c < P, a < na (a offset by a0 in the group).
-template <class S>
+// KN = k * na accumulators, a compile-time count so that every load of a
+// point is issued before its multiply-adds (many loads in flight per wave).
+template <class S, int KN>
 __global__ __launch_bounds__(256) void k_gram_part(int64_t N, int ld, int P, int pb, int k, int a0, int na,
                                                    PtrList X, const S* __restrict__ Y,
                                                    c128* __restrict__ part) {
-  extern __shared__ cx<double> red[];  // [256][k*na]
+  extern __shared__ cx<double> red[];  // [256][KN]
   const int tid = threadIdx.x;
   const int PT = 256 / P;
   const int c = tid % P, r = tid / P;
-  const int kn = k * na;
-  cx<double> acc[GRAM_MAXACC];
+  cx<double> acc[KN];
 #pragma unroll
-  for (int e = 0; e < GRAM_MAXACC; ++e) acc[e] = {0.0, 0.0};
+  for (int e = 0; e < KN; ++e) acc[e] = {0.0, 0.0};
   const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const int64_t nb0 = (int64_t)blockIdx.x * chunk;
   const int64_t nb1 = nb0 + chunk < N ? nb0 + chunk : N;
   if (r < PT) {
     const int cb = (c / pb) * pb + a0;
+    const S* xp[KN];
+#pragma unroll
+    for (int e = 0; e < KN; ++e) {
+      const int i = e / na, a = e - i * na;
+      xp[e] = static_cast<const S*>(X.p[i]) + cb + a;
+    }
     for (int64_t n = nb0 + r; n < nb1; n += PT) {
       const S yv = Y[n * ld + c];
+      S xv[KN];
+#pragma unroll
+      for (int e = 0; e < KN; ++e) xv[e] = xp[e][n * ld];
       const cx<double> y = {(double)yv.re, (double)yv.im};
 #pragma unroll
-      for (int e = 0; e < GRAM_MAXACC; ++e) {
-        if (e < kn) {
-          const int i = e / na, a = e - i * na;
-          const S xv = static_cast<const S*>(X.p[i])[n * ld + cb + a];
-          const cx<double> x = {(double)xv.re, (double)xv.im};
-          cfmac(acc[e], x, y);
-        }
-      }
+      for (int e = 0; e < KN; ++e) cfmac(acc[e], cx<double>{(double)xv[e].re, (double)xv[e].im}, y);
     }
   }
 #pragma unroll
-  for (int e = 0; e < GRAM_MAXACC; ++e)
-    if (e < kn) red[tid * kn + e] = acc[e];
+  for (int e = 0; e < KN; ++e) red[tid * KN + e] = acc[e];
   __syncthreads();
-  for (int o = tid; o < P * kn; o += 256) {
-    const int cc = o / kn, e = o - cc * kn;
+  for (int o = tid; o < P * KN; o += 256) {
+    const int cc = o / KN, e = o - cc * KN;
     cx<double> s = {0.0, 0.0};
-    for (int rr = 0; rr < PT; ++rr) s = s + red[(rr * P + cc) * kn + e];
+    for (int rr = 0; rr < PT; ++rr) s = s + red[(rr * P + cc) * KN + e];
     const int i = e / na, a = e - i * na;
-    part[(((int64_t)blockIdx.x * k + i) * P + cc) * na + a] = fcx(s);
+    part[((((int64_t)i * P + cc) * na + a)) * gridDim.x + blockIdx.x] = fcx(s);
   }
 }
 
-// G[i][c][a0+a] = sum over blocks of part, in a fixed order: each
-// workgroup owns 64 consecutive outputs; its four waves sum interleaved
-// quarters of the partials (eight independent accumulators per lane) and
-// the quarters are added through LDS.
+template <class S, int KN>
+static void gram_part_launch(int nblk, hipStream_t s, int64_t N, int ld, int P, int pb, int k, int a0, int na,
+                             const PtrList& X, const void* Y, c128* part) {
+  const size_t shm = sizeof(cx<double>) * 256 * KN;
+  hipLaunchKernelGGL((k_gram_part<S, KN>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, k, a0, na, X,
+                     (const S*)Y, part);
+}
+
+template <class S>
+static void gram_part_dispatch(int kn, int nblk, hipStream_t s, int64_t N, int ld, int P, int pb, int k, int a0,
+                               int na, const PtrList& X, const void* Y, c128* part) {
+  switch (kn) {
+#define HELM_KN(v) \
+  case v: gram_part_launch<S, v>(nblk, s, N, ld, P, pb, k, a0, na, X, Y, part); break;
+    HELM_KN(1) HELM_KN(2) HELM_KN(3) HELM_KN(4) HELM_KN(5) HELM_KN(6) HELM_KN(7) HELM_KN(8)
+    HELM_KN(9) HELM_KN(10) HELM_KN(11) HELM_KN(12) HELM_KN(13) HELM_KN(14) HELM_KN(15) HELM_KN(16)
+#undef HELM_KN
+    default: fatal_combo("gram_part_dispatch");
+  }
+}
+
+// G[i][c][a0+a] = sum over blocks of part[o][blk], one workgroup per output:
+// each lane sums a fixed interleaved subset, then a fixed-order tree in LDS
+// (deterministic).
 __global__ __launch_bounds__(256) void k_gram_final(int nblk, int P, int pb, int k, int i0, int a0, int na,
                                                     const c128* __restrict__ part, c128* __restrict__ G) {
-  __shared__ cx<double> red[4][64];
-  const int nout = k * P * na;
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int o = blockIdx.x * 64 + lane;
-  cx<double> acc[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = {0.0, 0.0};
-  if (o < nout) {
-    int b = q;
-    for (; b + 28 < nblk; b += 32) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = acc[u] + tcx(part[(int64_t)(b + 4 * u) * nout + o]);
-    }
-    for (; b < nblk; b += 4) acc[0] = acc[0] + tcx(part[(int64_t)b * nout + o]);
-  }
-  cx<double> s = acc[0];
-#pragma unroll
-  for (int u = 1; u < 8; ++u) s = s + acc[u];
-  red[q][lane] = s;
+  __shared__ cx<double> red[256];
+  const int o = blockIdx.x;
+  const c128* p = part + (int64_t)o * nblk;
+  cx<double> s = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) s = s + tcx(p[b]);
+  red[threadIdx.x] = s;
   __syncthreads();
-  if (q == 0 && o < nout) {
-    s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
     const int a = o % na, c = (o / na) % P, i = o / (na * P);
-    G[((int64_t)(i0 + i) * P + c) * pb + a0 + a] = fcx(s);
+    G[((int64_t)(i0 + i) * P + c) * pb + a0 + a] = fcx(red[0]);
   }
 }
 
@@ -120,13 +132,11 @@ void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList&
       PtrList sub{};
       for (int i = 0; i < kc; ++i) sub.p[i] = X.p[i0 + i];
       if (p == P64)
-        hipLaunchKernelGGL((k_gram_part<c128>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, kc, a0, na, sub,
-                           (const c128*)Y, part);
+        gram_part_dispatch<c128>(kc * na, nblk, s, N, ld, P, pb, kc, a0, na, sub, Y, part);
       else
-        hipLaunchKernelGGL((k_gram_part<c64>), dim3(nblk), dim3(256), shm, s, N, ld, P, pb, kc, a0, na, sub,
-                           (const c64*)Y, part);
+        gram_part_dispatch<c64>(kc * na, nblk, s, N, ld, P, pb, kc, a0, na, sub, Y, part);
       const int outs = kc * P * na;
-      hipLaunchKernelGGL(k_gram_final, dim3((outs + 63) / 64), dim3(256), 0, s, nblk, P, pb, kc, i0, a0, na, part, G);
+      hipLaunchKernelGGL(k_gram_final, dim3(outs), dim3(256), 0, s, nblk, P, pb, kc, i0, a0, na, part, G);
     }
   }
 }
@@ -161,10 +171,69 @@ __global__ __launch_bounds__(256) void k_block_update(int mode, int64_t N, int l
   *yp = SY{(E)r.re, (E)r.im};
 }
 
+// Block size 1 with a compile-time vector count (loads issued together).
+template <class SX, class SY, int KX>
+__global__ __launch_bounds__(256) void k_update1(int mode, int64_t N, int ld, int P, PtrList X,
+                                                 const c128* __restrict__ C, SY* __restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * P) return;
+  const int64_t n = t / P;
+  const int c = (int)(t - n * P);
+  SX xv[KX];
+#pragma unroll
+  for (int i = 0; i < KX; ++i) xv[i] = static_cast<const SX*>(X.p[i])[n * ld + c];
+  cx<double> acc = {0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < KX; ++i) cfma(acc, cx<double>{(double)xv[i].re, (double)xv[i].im}, tcx(C[(int64_t)i * P + c]));
+  SY* yp = Y + n * ld + c;
+  cx<double> r = acc;
+  if (mode != 1) {
+    const SY yv = *yp;
+    const cx<double> y = {(double)yv.re, (double)yv.im};
+    r = mode == 0 ? y - acc : y + acc;
+  }
+  using E = decltype(yp->re);
+  *yp = SY{(E)r.re, (E)r.im};
+}
+
+template <class SX, class SY>
+static void update1_dispatch(int kx, dim3 gr, hipStream_t s, int mode, int64_t N, int ld, int P, const PtrList& X,
+                             const c128* C, void* Y) {
+  switch (kx) {
+#define HELM_KX(v)                                                                                              \
+  case v:                                                                                                       \
+    hipLaunchKernelGGL((k_update1<SX, SY, v>), gr, dim3(256), 0, s, mode, N, ld, P, X, C, (SY*)Y);          \
+    break;
+    HELM_KX(1) HELM_KX(2) HELM_KX(3) HELM_KX(4) HELM_KX(5) HELM_KX(6) HELM_KX(7) HELM_KX(8)
+    HELM_KX(9) HELM_KX(10) HELM_KX(11) HELM_KX(12) HELM_KX(13) HELM_KX(14) HELM_KX(15) HELM_KX(16)
+#undef HELM_KX
+    default: fatal_combo("update1_dispatch");
+  }
+}
+
 void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, int pb, int k, const PtrList& X,
                          const c128* C, void* Y, hipStream_t s) {
   const dim3 gr((unsigned)((N * P + 255) / 256));
   if (k > MAXPTR) fatal_combo("launch_block_update");
+  if (pb == 1) {
+    // chunks of at most 16 vectors; later chunks accumulate into Y
+    for (int i0 = 0; i0 < k; i0 += 16) {
+      const int kx = (k - i0) < 16 ? (k - i0) : 16;
+      PtrList sub{};
+      for (int i = 0; i < kx; ++i) sub.p[i] = X.p[i0 + i];
+      const int md = (i0 == 0) ? mode : (mode == 1 ? 2 : mode);
+      const c128* Cs = C + (int64_t)i0 * P;
+      if (px == P64 && py == P64)
+        update1_dispatch<c128, c128>(kx, gr, s, md, N, ld, P, sub, Cs, Y);
+      else if (px == P32 && py == P64)
+        update1_dispatch<c64, c128>(kx, gr, s, md, N, ld, P, sub, Cs, Y);
+      else if (px == P32 && py == P32)
+        update1_dispatch<c64, c64>(kx, gr, s, md, N, ld, P, sub, Cs, Y);
+      else
+        fatal_combo("launch_block_update");
+    }
+    return;
+  }
   if (px == P64 && py == P64)
     hipLaunchKernelGGL((k_block_update<c128, c128>), gr, dim3(256), 0, s, mode, N, ld, P, pb, k, X, C, (c128*)Y);
   else if (px == P32 && py == P64)
@@ -410,8 +479,8 @@ void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const
 // per-workgroup partials (same lane layout as the Gram kernel, so the final
 // reduction is k_gram_final with k = na = pb = 1).
 // ---------------------------------------------------------------------------
-template <class S>
-__global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int P, int k, PtrList X,
+template <class S, int KX>
+__global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int P, int with_norm, PtrList X,
                                                           const c128* __restrict__ C, S* __restrict__ Y,
                                                           c128* __restrict__ part) {
   __shared__ double red[256];
@@ -424,27 +493,50 @@ __global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int
   double nrm = 0.0;
   using E = decltype(Y->re);
   if (r < PT) {
-    cx<double> coef[MAXPTR];
-    for (int i = 0; i < k; ++i) coef[i] = tcx(C[(int64_t)i * P + c]);
+    cx<double> coef[KX];
+    const S* xp[KX];
+#pragma unroll
+    for (int i = 0; i < KX; ++i) {
+      coef[i] = tcx(C[(int64_t)i * P + c]);
+      xp[i] = static_cast<const S*>(X.p[i]) + c;
+    }
     for (int64_t n = nb0 + r; n < nb1; n += PT) {
       const int64_t e = n * ld + c;
       const S yv = Y[e];
+      S xv[KX];
+#pragma unroll
+      for (int i = 0; i < KX; ++i) xv[i] = xp[i][n * ld];
       cx<double> y = {(double)yv.re, (double)yv.im};
-      for (int i = 0; i < k; ++i) {
-        const S xv = static_cast<const S*>(X.p[i])[e];
-        cfma(y, cx<double>{-(double)xv.re, -(double)xv.im}, coef[i]);
-      }
+#pragma unroll
+      for (int i = 0; i < KX; ++i) cfma(y, cx<double>{-(double)xv[i].re, -(double)xv[i].im}, coef[i]);
       const S out = S{(E)y.re, (E)y.im};
       Y[e] = out;
       nrm += (double)out.re * (double)out.re + (double)out.im * (double)out.im;
     }
   }
+  if (!with_norm) return;
   red[tid] = nrm;
   __syncthreads();
   for (int cc = tid; cc < P; cc += 256) {
     double s = 0.0;
     for (int rr = 0; rr < PT; ++rr) s += red[rr * P + cc];
-    part[(int64_t)blockIdx.x * P + cc] = c128{s, 0.0};
+    part[(int64_t)cc * gridDim.x + blockIdx.x] = c128{s, 0.0};
+  }
+}
+
+template <class S>
+static void update_norm_dispatch(int kx, int nblk, hipStream_t s, int64_t N, int ld, int P, int with_norm,
+                                 const PtrList& X, const c128* C, void* Y, c128* part) {
+  switch (kx) {
+#define HELM_KX(v)                                                                                             \
+  case v:                                                                                                      \
+    hipLaunchKernelGGL((k_update_norm_part<S, v>), dim3(nblk), dim3(256), 0, s, N, ld, P, with_norm, X, C, \
+                       (S*)Y, part);                                                                           \
+    break;
+    HELM_KX(1) HELM_KX(2) HELM_KX(3) HELM_KX(4) HELM_KX(5) HELM_KX(6) HELM_KX(7) HELM_KX(8)
+    HELM_KX(9) HELM_KX(10) HELM_KX(11) HELM_KX(12) HELM_KX(13) HELM_KX(14) HELM_KX(15) HELM_KX(16)
+#undef HELM_KX
+    default: fatal_combo("update_norm_dispatch");
   }
 }
 
@@ -455,13 +547,20 @@ void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& 
   const int64_t minpts = (256 / P) * 4;
   if (N < (int64_t)nblk * minpts) nblk = (int)((N + minpts - 1) / minpts);
   if (nblk < 1) nblk = 1;
-  if (p == P64)
-    hipLaunchKernelGGL((k_update_norm_part<c128>), dim3(nblk), dim3(256), 0, s, N, ld, P, k, X, C, (c128*)Y, part);
-  else if (p == P32)
-    hipLaunchKernelGGL((k_update_norm_part<c64>), dim3(nblk), dim3(256), 0, s, N, ld, P, k, X, C, (c64*)Y, part);
-  else
-    fatal_combo("launch_update_norm");
-  hipLaunchKernelGGL(k_gram_final, dim3((P + 63) / 64), dim3(256), 0, s, nblk, P, 1, 1, 0, 0, 1, part, G);
+  // at most 16 vectors per pass; the norm comes from the last pass
+  for (int i0 = 0; i0 < k; i0 += 16) {
+    const int kx = (k - i0) < 16 ? (k - i0) : 16;
+    PtrList sub{};
+    for (int i = 0; i < kx; ++i) sub.p[i] = X.p[i0 + i];
+    const int last = i0 + 16 >= k;
+    if (p == P64)
+      update_norm_dispatch<c128>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part);
+    else if (p == P32)
+      update_norm_dispatch<c64>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part);
+    else
+      fatal_combo("launch_update_norm");
+  }
+  hipLaunchKernelGGL(k_gram_final, dim3(P), dim3(256), 0, s, nblk, P, 1, 1, 0, 0, 1, part, G);
   hipLaunchKernelGGL(k_diag_real, dim3((P + 255) / 256), dim3(256), 0, s, P, G, nrm2);
 }
 
@@ -481,6 +580,79 @@ __global__ void k_norm_to_r(int P, const double* __restrict__ n2, const double* 
 void launch_norm_to_r(int P, const double* n2, const double* ref2, double tol, c128* R, c128* Rinv, int* flag,
                       hipStream_t s) {
   hipLaunchKernelGGL(k_norm_to_r, dim3((P + 255) / 256), dim3(256), 0, s, P, n2, ref2, tol, R, Rinv, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Block size 1 with an unnormalised basis: the stored vector v~_i = nu_i v_i
+// (nu_i = ||v~_i||), W~ = H M(v~_j) = nu_j H z_j. From the raw Gram values
+// g_i = v~_i^H W~ (i <= j): update coefficients c_i = g_i / nu_i^2 (so that
+// W~ - sum c_i v~_i = nu_j (w - sum v_i h_ij)) and the Hessenberg entries
+// h_ij = g_i / (nu_i nu_j), written to column j of Hbar (ld ldh per column).
+// ---------------------------------------------------------------------------
+__global__ void k_lazy_coef(int P, int j, const c128* __restrict__ Graw, const double* __restrict__ nu,
+                            c128* __restrict__ C, c128* __restrict__ Hb, int ldh, int64_t hstride, int accumulate) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  const double nj = nu[(int64_t)j * P + c];
+  c128* H = Hb + (int64_t)c * hstride + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) {
+    const c128 g = Graw[(int64_t)i * P + c];
+    const double ni = nu[(int64_t)i * P + c];
+    const double a = ni > 0.0 ? 1.0 / (ni * ni) : 0.0;
+    const double b = (ni > 0.0 && nj > 0.0) ? 1.0 / (ni * nj) : 0.0;
+    C[(int64_t)i * P + c] = c128{g.re * a, g.im * a};
+    const c128 h = accumulate ? H[i] : c128{0.0, 0.0};
+    H[i] = c128{h.re + g.re * b, h.im + g.im * b};
+  }
+}
+void launch_lazy_coef(int P, int j, const c128* Graw, const double* nu, c128* C, c128* Hb, int ldh, int64_t hstride,
+                      int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_lazy_coef, dim3((P + 63) / 64), dim3(64), 0, s, P, j, Graw, nu, C, Hb, ldh, hstride,
+                     accumulate);
+}
+// nu_{j+1} = ||W~'||; h_{j+1,j} = nu_{j+1} / nu_j; breakdown flag when the new
+// vector vanished against ||W~|| before orthogonalisation (ref2).
+__global__ void k_lazy_next(int P, int j, const double* __restrict__ n2, const double* __restrict__ ref2, double tol,
+                            double* __restrict__ nu, c128* __restrict__ Hb, int ldh, int64_t hstride,
+                            int* __restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  const double v = n2[c];
+  const bool bad = !(v > tol * ref2[c]) || !(v > 0.0);
+  const double nn = bad ? 0.0 : sqrt(v);
+  const double nj = nu[(int64_t)j * P + c];
+  nu[(int64_t)(j + 1) * P + c] = nn;
+  Hb[(int64_t)c * hstride + (int64_t)j * ldh + j + 1] = c128{nj > 0.0 ? nn / nj : 0.0, 0.0};
+  flag[c] = bad ? 1 : 0;
+}
+void launch_lazy_next(int P, int j, const double* n2, const double* ref2, double tol, double* nu, c128* Hb, int ldh,
+                      int64_t hstride, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_lazy_next, dim3((P + 63) / 64), dim3(64), 0, s, P, j, n2, ref2, tol, nu, Hb, ldh, hstride,
+                     flag);
+}
+// nu_0 = ||r||, S = nu_0 (first LS block), inactive/zero columns flagged.
+__global__ void k_lazy_start(int P, const double* __restrict__ r2, double* __restrict__ nu, c128* __restrict__ S,
+                             int* __restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  const double n = r2[c] > 0.0 ? sqrt(r2[c]) : 0.0;
+  nu[c] = n;
+  S[c] = c128{n, 0.0};
+  flag[c] = n > 0.0 ? 0 : 1;
+}
+void launch_lazy_start(int P, const double* r2, double* nu, c128* S, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_lazy_start, dim3((P + 63) / 64), dim3(64), 0, s, P, r2, nu, S, flag);
+}
+// Solution coefficients for the stored z~_i = nu_i z_i: Y[i][c] /= nu_i.
+__global__ void k_lazy_y(int P, int k, const double* __restrict__ nu, c128* __restrict__ Y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * P) return;
+  const double n = nu[t];
+  const double a = n > 0.0 ? 1.0 / n : 0.0;
+  Y[t] = c128{Y[t].re * a, Y[t].im * a};
+}
+void launch_lazy_y(int P, int k, const double* nu, c128* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_lazy_y, dim3((k * P + 255) / 256), dim3(256), 0, s, P, k, nu, Y);
 }
 
 // ---------------------------------------------------------------------------

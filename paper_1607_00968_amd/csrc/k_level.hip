@@ -124,6 +124,95 @@ __global__ __launch_bounds__(256) void k_fine(Geo g, const SU* __restrict__ u, c
 }
 
 // ---------------------------------------------------------------------------
+// 3D fine-level operator, z-marching: each lane owns K columns of one (x, y)
+// grid column and walks a chunk of z planes, keeping u(z-1), u(z), u(z+1) in
+// registers, so every value of u is fetched from memory once; the in-plane
+// neighbours come from L1/L2. Workgroups are numbered so that each XCD (the
+// hardware deals workgroup b to XCD b % 8) receives a contiguous run of
+// tiles ordered y-fastest: tiles of neighbouring y rows run at the same time
+// on the same XCD and share its L2. Same modes as k_fine except JAC0.
+// ---------------------------------------------------------------------------
+struct ZTiles {
+  int nxb, nzc, zc;  // x-blocks, z-chunks, planes per chunk
+  int per;           // tiles per XCD
+  int64_t ntiles;
+};
+
+template <class SU, class SF, class SO, class T, int MODE>
+__global__ __launch_bounds__(256) void k_fine_zm(Geo g, ZTiles zt, const SU* __restrict__ u,
+                                                 const SF* __restrict__ f, SO* __restrict__ out,
+                                                 const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw, T ihx,
+                                                 T ihy, T ihz) {
+  constexpr int K = kmax3<SU, SF, SO>();
+  const int L = g.P / K;      // lanes per point
+  const int PPB = 256 / L;    // points per workgroup along x
+  const int lane = threadIdx.x % L, px = threadIdx.x / L;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * zt.per + blockIdx.x / 8;
+  if (t >= zt.ntiles || px >= PPB) return;
+  const int y = (int)(t % g.ny);
+  const int xb = (int)((t / g.ny) % zt.nxb);
+  const int zc = (int)(t / ((int64_t)g.ny * zt.nxb));
+  const int x = xb * PPB + px;
+  if (x >= g.nx) return;
+  const int z0 = zc * zt.zc;
+  const int z1 = z0 + zt.zc < g.nz ? z0 + zt.zc : g.nz;
+  const int c = lane * K;
+  const int64_t sx = g.P, sy = (int64_t)g.nx * g.P, sz = (int64_t)g.nx * g.ny * g.P;
+  const int64_t i0 = ((int64_t)z0 * g.ny + y) * g.nx + x;
+  const SU* up = u + i0 * g.P + c;
+  cx<T> um[K], uc[K], un[K], nb[K];
+  ldKz<K, SU, T>(up - sz, z0 > 0, um);
+  ldK<K, SU, T>(up, uc);
+  int64_t i = i0;
+  for (int z = z0; z < z1; ++z, i += (int64_t)g.nx * g.ny, up += sz) {
+    ldKz<K, SU, T>(up + sz, z + 1 < g.nz, un);
+    const cx<T> d = dg[i];
+    cx<T> acc[K], sum[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[k] = d * uc[k];
+      sum[k] = ihz * (um[k] + un[k]);
+    }
+    ldKz<K, SU, T>(up - sx, x > 0, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
+    ldKz<K, SU, T>(up + sx, x < g.nx - 1, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
+    ldKz<K, SU, T>(up - sy, y > 0, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihy * nb[k];
+    ldKz<K, SU, T>(up + sy, y < g.ny - 1, nb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sum[k] = sum[k] + ihy * nb[k];
+      acc[k] = acc[k] - sum[k];
+    }
+    const int64_t o = i * g.P + c;
+    if (MODE == 0) {
+      stK<K, SO, T>(out + o, acc);
+    } else {
+      cx<T> fv[K], res[K];
+      ldK<K, SF, T>(f + o, fv);
+      if (MODE == 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
+      } else {
+        const cx<T> w = dw[i];
+#pragma unroll
+        for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
+      }
+      stK<K, SO, T>(out + o, res);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      um[k] = uc[k];
+      uc[k] = un[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Galerkin-level operator family (same modes), stencil [N][NS], NS = 3^DIM.
 // ---------------------------------------------------------------------------
 template <int DIM, class S, class T, int MODE>
@@ -339,10 +428,29 @@ __global__ __launch_bounds__(256) void k_to_abi(int64_t N, int nrhs, int P, cons
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 255) / 256)); }
 
+// Planes per z-chunk of the marching kernel: long enough to amortise the
+// two halo planes, short enough for many workgroups per XCD.
+static int zchunk_planes = 16;
+void set_zchunk(int zc) { zchunk_planes = zc > 0 ? zc : 16; }
+
 template <class SU, class SF, class SO, class T, int MODE>
 static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, void* out, const void* dg,
                           const void* dw, const double ih[3], hipStream_t s) {
   constexpr int K = kmax3<SU, SF, SO>();
+  const int L = g.P / K;
+  if (dim == 3 && MODE != 3 && L <= 256) {
+    ZTiles zt;
+    const int PPB = 256 / L;
+    zt.nxb = (g.nx + PPB - 1) / PPB;
+    zt.zc = zchunk_planes;
+    zt.nzc = (g.nz + zt.zc - 1) / zt.zc;
+    zt.ntiles = (int64_t)zt.nxb * g.ny * zt.nzc;
+    zt.per = (int)((zt.ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_fine_zm<SU, SF, SO, T, MODE>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(256), 0, s, g,
+                       zt, (const SU*)u, (const SF*)f, (SO*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
+                       (T)ih[1], (T)ih[2]);
+    return;
+  }
   const int64_t thr = g.npts * (g.P / K);
   if (dim == 3)
     hipLaunchKernelGGL((k_fine<3, SU, SF, SO, T, MODE>), grid1(thr), dim3(256), 0, s, g, (const SU*)u, (const SF*)f,

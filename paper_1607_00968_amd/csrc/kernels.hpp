@@ -100,6 +100,13 @@ void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& 
 // R = ||w||, Rinv = 1/||w|| per column from n2; flag where n2 <= tol*ref2.
 void launch_norm_to_r(int P, const double* n2, const double* ref2, double tol, c128* R, c128* Rinv, int* flag,
                       hipStream_t s);
+// Block size 1 with an unnormalised Krylov basis (see k_krylov.hip).
+void launch_lazy_coef(int P, int j, const c128* Graw, const double* nu, c128* C, c128* Hb, int ldh, int64_t hstride,
+                      int accumulate, hipStream_t s);
+void launch_lazy_next(int P, int j, const double* n2, const double* ref2, double tol, double* nu, c128* Hb, int ldh,
+                      int64_t hstride, int* flag, hipStream_t s);
+void launch_lazy_start(int P, const double* r2, double* nu, c128* S, int* flag, hipStream_t s);
+void launch_lazy_y(int P, int k, const double* nu, c128* Y, hipStream_t s);
 // Fixed-step per-column GMRES helpers for the coarsest grid.
 void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s);
 void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);
