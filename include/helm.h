@@ -160,10 +160,20 @@ helm_status helm_level_stencil(helm_handle h, int32_t level, double* st);
  * R, E: DEVICE complex128 [nrhs][N_coarsest]. */
 helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* E, void* stream);
 
+/* Tile shape (rows per lane, planes per z-chunk) of the 3D finest-level
+ * stencil kernels for blocks of nrhs columns. helm_fine_tile runs the
+ * autotuner if this width has not been tuned (timing each candidate on the
+ * handle's buffers; cached in the JSON-lines file named by HELM_TUNE_CACHE;
+ * HELM_AUTOTUNE=0 keeps the default) and returns the choice;
+ * helm_set_fine_tile forces one (ry in {1,2,4}, zc >= 1). Results are
+ * bitwise identical for every tile. */
+helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]);
+helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]);
+
 /* Per-class kernel timing with HIP events recorded on the solve's stream
  * around every launch of the class (for roofline accounting). */
 enum {
-  HELM_K_FINE_SWEEP = 0, /* damped-Jacobi sweeps on the finest level */
+  HELM_K_FINE_SWEEP = 0, /* damped-Jacobi sweeps from a nonzero guess, finest level */
   HELM_K_FINE_RESID,     /* residual of the cycle on the finest level */
   HELM_K_OUTER_APPLY,    /* W = H Z and R = Q - H X of the outer Krylov (FP64) */
   HELM_K_TRANSFER,       /* restriction and prolongation, all levels */
@@ -171,6 +181,7 @@ enum {
   HELM_K_COARSEST,       /* the whole coarsest-grid solve */
   HELM_K_GRAM,           /* block Gram products and column norms */
   HELM_K_UPDATE,         /* block updates W -= V H, V = W R^-1, X += Z Y */
+  HELM_K_FINE_SWEEP0,    /* the first (zero initial guess) sweep on the finest level */
   HELM_K_NCLASS
 };
 typedef struct {

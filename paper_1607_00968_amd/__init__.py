@@ -40,10 +40,11 @@ ABI_SYMBOLS = (
     "helm_setup_desc_default", "helm_setup", "helm_destroy", "helm_workspace_size",
     "helm_solve_block", "helm_residual", "helm_apply", "helm_precond",
     "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
-    "helm_profile_enable", "helm_profile_read", "helm_status_string", "helm_last_error",
+    "helm_profile_enable", "helm_profile_read", "helm_fine_tile", "helm_set_fine_tile",
+    "helm_status_string", "helm_last_error",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
-                  "coarsest", "gram", "update")
+                  "coarsest", "gram", "update", "fine_sweep0")
 
 
 class HelmError(RuntimeError):
@@ -100,6 +101,8 @@ def lib():
         L.helm_level_stencil.argtypes = [P, I, P]
         L.helm_coarse_solve.argtypes = [P, I, P, P, P]
         L.helm_profile_enable.argtypes = [P, I]
+        L.helm_fine_tile.argtypes = [P, I, P]
+        L.helm_set_fine_tile.argtypes = [P, I, P]
         L.helm_profile_read.argtypes = [P, P]
         L.helm_status_string.restype = C.c_char_p
         L.helm_status_string.argtypes = [I]
@@ -278,3 +281,16 @@ def helm_profile_read(hd: Handle) -> dict:
     arr = (KernelStat * len(KERNEL_CLASSES))()
     _check(lib().helm_profile_read(hd.ptr, C.cast(arr, C.c_void_p)))
     return {name: (arr[i].launches, arr[i].total_ms) for i, name in enumerate(KERNEL_CLASSES)}
+
+
+def helm_fine_tile(hd: Handle, nrhs: int):
+    """(rows per lane, planes per z-chunk) used for nrhs columns (autotuned on first use)."""
+    t = (C.c_int32 * 2)()
+    _check(lib().helm_fine_tile(hd.ptr, nrhs, t))
+    return int(t[0]), int(t[1])
+
+
+def helm_set_fine_tile(hd: Handle, nrhs: int, ry: int, zc: int):
+    """Force the tile of the finest-level stencil kernels for nrhs columns."""
+    t = (C.c_int32 * 2)(ry, zc)
+    _check(lib().helm_set_fine_tile(hd.ptr, nrhs, t))

@@ -17,6 +17,9 @@ SOURCES = ["k_level.hip", "k_setup.hip", "k_krylov.hip", "learned.hip", "helm.cp
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+         # arithmetic in source order (explicit fma where wanted): results do not
+         # depend on how a kernel instance is scheduled or tiled
+         "-ffp-contract=off",
          # keep packed-FP32 instructions out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]

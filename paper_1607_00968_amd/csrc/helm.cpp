@@ -108,6 +108,9 @@ struct helm_ctx {
   std::vector<void*> kbuf;
   double* hbuf = nullptr;  // pinned host scratch
   size_t hbufn = 0;
+  // tuned tile of the finest-level marching kernel, per block width P
+  int tileP = 0;
+  FineTile tile = {4, 32};
   // per-class kernel timing
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -167,7 +170,10 @@ __global__ void k_add_c128(int64_t n, const c128* __restrict__ x, c128* __restri
 
 // One relaxation-family launch on level l (mode as launch_fine).
 static void level_op(helm_ctx* c, int l, int mode, int P, const void* u, const void* f, void* out, hipStream_t s) {
-  Prof pr(c, l == 0 ? (mode == 1 ? HELM_K_FINE_RESID : HELM_K_FINE_SWEEP) : HELM_K_COARSE_SWEEP, s);
+  Prof pr(c,
+          l == 0 ? (mode == 1 ? HELM_K_FINE_RESID : (mode == 3 ? HELM_K_FINE_SWEEP0 : HELM_K_FINE_SWEEP))
+                 : HELM_K_COARSE_SWEEP,
+          s);
   const Level& L = c->lv[l];
   const Prec pf = field_prec(c, l), pt = comp_prec(c);
   if (l == 0) {
@@ -313,6 +319,8 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
 // ---------------------------------------------------------------------------
 // Field allocation for a block of P columns.
 // ---------------------------------------------------------------------------
+static int padP(int nrhs) { return (nrhs + 3) / 4 * 4; }
+
 static helm_status ensure_fields(helm_ctx* c, int P) {
   if (c->fieldsP >= P && c->fieldmem) return HELM_OK;
   if (c->fieldmem) {
@@ -339,6 +347,103 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
     HCHECK(hipMalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
   }
   c->fieldsP = P;
+  return HELM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the finest-level marching kernel: times each candidate tile
+// (rows per lane x planes per chunk) on the real buffers with HIP events and
+// keeps the fastest. Choices are cached in a JSON-lines file named by the
+// HELM_TUNE_CACHE environment variable, keyed by arch, grid, block width and
+// precision; HELM_AUTOTUNE=0 keeps the default tile.
+// ---------------------------------------------------------------------------
+static std::string tune_key(const helm_ctx* c, int P) {
+  char b[160];
+  std::snprintf(b, sizeof(b), "gfx950:%d:%d:%d:%d:%s", c->lv[0].nu[0], c->lv[0].nu[1], c->lv[0].nu[2], P,
+                c->precision == HELM_FP64 ? "fp64" : "mixed");
+  return b;
+}
+
+static bool tune_cache_lookup(const std::string& key, FineTile* t) {
+  const char* path = std::getenv("HELM_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), fp)) {
+    char k[200];
+    int ry, zc;
+    if (std::sscanf(line, " {\"key\": \"%199[^\"]\", \"ry\": %d, \"zc\": %d", k, &ry, &zc) == 3 && key == k &&
+        (ry == 1 || ry == 2 || ry == 4) && zc > 0) {
+      *t = FineTile{ry, zc};
+      found = true;  // the last entry for a key wins
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+static void tune_cache_store(const std::string& key, FineTile t, double ms) {
+  const char* path = std::getenv("HELM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "{\"key\": \"%s\", \"ry\": %d, \"zc\": %d, \"ms\": %.4f}\n", key.c_str(), t.ry, t.zc, ms);
+  std::fclose(fp);
+}
+
+static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
+  if (c->dim != 3 || c->tileP == P) return HELM_OK;
+  c->tileP = P;
+  c->tile = FineTile{4, 32};
+  const char* en = std::getenv("HELM_AUTOTUNE");
+  if (en && std::strcmp(en, "0") == 0) return HELM_OK;
+  const std::string key = tune_key(c, P);
+  FineTile t;
+  if (tune_cache_lookup(key, &t)) {
+    c->tile = t;
+    return HELM_OK;
+  }
+  Level& L = c->lv[0];
+  const size_t bytes = psize(field_prec(c, 0)) * L.npts * P;
+  HCHECK(hipMemsetAsync(L.U0, 0, bytes, s));
+  HCHECK(hipMemsetAsync(L.F, 0, bytes, s));
+  hipEvent_t a, b;
+  HCHECK(hipEventCreate(&a));
+  HCHECK(hipEventCreate(&b));
+  const int rys[3] = {1, 2, 4};
+  const int zcs[3] = {16, 32, 64};
+  double best = 1e30;
+  FineTile bt = c->tile;
+  const bool was = c->prof;
+  c->prof = false;
+  for (int ri = 0; ri < 3; ++ri)
+    for (int zi = 0; zi < 3; ++zi) {
+      set_fine_tile(FineTile{rys[ri], zcs[zi]});
+      level_op(c, 0, 2, P, L.U0, L.F, L.U1, s);  // warm-up
+      std::vector<float> ts;
+      for (int r = 0; r < 3; ++r) {
+        hipEventRecord(a, s);
+        level_op(c, 0, 2, P, L.U0, L.F, L.U1, s);
+        hipEventRecord(b, s);
+        hipEventSynchronize(b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        ts.push_back(ms);
+      }
+      std::sort(ts.begin(), ts.end());
+      if (ts[1] < best) {
+        best = ts[1];
+        bt = FineTile{rys[ri], zcs[zi]};
+      }
+    }
+  c->prof = was;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  HCHECK(hipGetLastError());
+  c->tile = bt;
+  tune_cache_store(key, bt, best);
   return HELM_OK;
 }
 
@@ -607,6 +712,25 @@ helm_status helm_profile_read(helm_handle h, helm_kernel_stat* stats) {
   return HELM_OK;
 }
 
+helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]) {
+  if (!h || !tile || nrhs < 1 || nrhs > 256) return fail(HELM_ERR_INVALID_ARG, "bad argument");
+  const int P = padP(nrhs);
+  helm_status st;
+  if ((st = ensure_fields(h, P)) != HELM_OK) return st;
+  if ((st = autotune_fine(h, P, nullptr)) != HELM_OK) return st;
+  tile[0] = h->tile.ry;
+  tile[1] = h->tile.zc;
+  return HELM_OK;
+}
+
+helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]) {
+  if (!h || !tile || nrhs < 1 || nrhs > 256) return fail(HELM_ERR_INVALID_ARG, "bad argument");
+  if (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4) || tile[1] < 1) return fail(HELM_ERR_INVALID_ARG, "bad tile");
+  h->tileP = padP(nrhs);
+  h->tile = FineTile{tile[0], tile[1]};
+  return HELM_OK;
+}
+
 helm_status helm_level_dims(helm_handle h, int32_t level, int32_t nu[3]) {
   if (!h || !nu || level < 0 || level >= h->L) return fail(HELM_ERR_INVALID_ARG, "bad level");
   for (int a = 0; a < 3; ++a) nu[a] = h->lv[level].nu[a];
@@ -621,7 +745,6 @@ helm_status helm_level_stencil(helm_handle h, int32_t level, double* st) {
   return HELM_OK;
 }
 
-static int padP(int nrhs) { return (nrhs + 3) / 4 * 4; }
 
 static helm_status check_block(helm_handle h, int32_t nrhs, const void* a, const void* b) {
   if (!h) return fail(HELM_ERR_INVALID_ARG, "null handle");
@@ -667,6 +790,7 @@ helm_status helm_precond(helm_handle h, int32_t nrhs, const void* R, void* Z, vo
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int P = padP(nrhs);
   if ((st = ensure_fields(h, P)) != HELM_OK) return st;
+  set_fine_tile(h->tileP == P ? h->tile : FineTile{4, 32});
   Level& L = h->lv[0];
   const Prec pf = field_prec(h, 0);
   c128 *A, *B;
@@ -810,6 +934,8 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   const Level& L0 = c->lv[0];
   const Prec pz = c->precision == HELM_FP64 ? P64 : P32;
   if ((st = ensure_fields(c, P)) != HELM_OK) return st;
+  if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
+  set_fine_tile(c->tile);
   const WsLayout w = ws_layout(c, P, m, pb);
   char* base = static_cast<char*>(workspace);
   if (!base) {

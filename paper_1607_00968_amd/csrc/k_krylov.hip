@@ -115,14 +115,20 @@ __global__ __launch_bounds__(256) void k_gram_final(int nblk, int P, int pb, int
 
 int64_t gram_part_elems(int P) { return (int64_t)GRAM_BLOCKS * GRAM_MAXACC * P; }
 
+// Workgroups for a column reduction over N points: at least 32 loop trips
+// per lane (PT = 256/P points per trip), at most GRAM_BLOCKS.
+static int part_blocks(int64_t N, int P) {
+  const int64_t pts = (int64_t)(256 / P) * 32;
+  int64_t nb = (N + pts - 1) / pts;
+  if (nb > GRAM_BLOCKS) nb = GRAM_BLOCKS;
+  return nb < 1 ? 1 : (int)nb;
+}
+
 void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList& X, const void* Y, c128* part,
                  c128* G, hipStream_t s) {
   if (p != P64 && p != P32) fatal_combo("launch_gram");
   if (P > 256 || P % pb != 0) fatal_combo("launch_gram");
-  int nblk = GRAM_BLOCKS;
-  const int64_t minpts = (256 / P) * 4;
-  if (N < (int64_t)nblk * minpts) nblk = (int)((N + minpts - 1) / minpts);
-  if (nblk < 1) nblk = 1;
+  const int nblk = part_blocks(N, P);
   const int na = pb < GRAM_MAXACC ? pb : GRAM_MAXACC;
   const int kk = GRAM_MAXACC / na;
   for (int i0 = 0; i0 < k; i0 += kk) {
@@ -543,10 +549,7 @@ static void update_norm_dispatch(int kx, int nblk, hipStream_t s, int64_t N, int
 void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& X, const c128* C, void* Y,
                         c128* part, c128* G, double* nrm2, hipStream_t s) {
   if (P > 256 || k > MAXPTR) fatal_combo("launch_update_norm");
-  int nblk = GRAM_BLOCKS;
-  const int64_t minpts = (256 / P) * 4;
-  if (N < (int64_t)nblk * minpts) nblk = (int)((N + minpts - 1) / minpts);
-  if (nblk < 1) nblk = 1;
+  const int nblk = part_blocks(N, P);
   // at most 16 vectors per pass; the norm comes from the last pass
   for (int i0 = 0; i0 < k; i0 += 16) {
     const int kx = (k - i0) < 16 ? (k - i0) : 16;

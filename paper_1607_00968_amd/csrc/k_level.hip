@@ -138,7 +138,7 @@ struct ZTiles {
   int64_t ntiles;
 };
 
-template <class SU, class SF, class SO, class T, int MODE>
+template <class SU, class SF, class SO, class T, int MODE, int RY>
 __global__ __launch_bounds__(256) void k_fine_zm(Geo g, ZTiles zt, const SU* __restrict__ u,
                                                  const SF* __restrict__ f, SO* __restrict__ out,
                                                  const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw, T ihx,
@@ -149,66 +149,80 @@ __global__ __launch_bounds__(256) void k_fine_zm(Geo g, ZTiles zt, const SU* __r
   const int lane = threadIdx.x % L, px = threadIdx.x / L;
   const int64_t t = (int64_t)(blockIdx.x % 8) * zt.per + blockIdx.x / 8;
   if (t >= zt.ntiles || px >= PPB) return;
-  const int y = (int)(t % g.ny);
-  const int xb = (int)((t / g.ny) % zt.nxb);
-  const int zc = (int)(t / ((int64_t)g.ny * zt.nxb));
+  const int nyb = (g.ny + RY - 1) / RY;
+  const int yb = (int)(t % nyb);
+  const int xb = (int)((t / nyb) % zt.nxb);
+  const int zc = (int)(t / ((int64_t)nyb * zt.nxb));
   const int x = xb * PPB + px;
   if (x >= g.nx) return;
+  const int y0 = yb * RY;
+  const int ry = g.ny - y0 < RY ? g.ny - y0 : RY;  // rows of this tile
   const int z0 = zc * zt.zc;
   const int z1 = z0 + zt.zc < g.nz ? z0 + zt.zc : g.nz;
   const int c = lane * K;
   const int64_t sx = g.P, sy = (int64_t)g.nx * g.P, sz = (int64_t)g.nx * g.ny * g.P;
-  const int64_t i0 = ((int64_t)z0 * g.ny + y) * g.nx + x;
-  const SU* up = u + i0 * g.P + c;
-  cx<T> um[K], uc[K], un[K], nb[K];
-  ldKz<K, SU, T>(up - sz, z0 > 0, um);
-  ldK<K, SU, T>(up, uc);
-  int64_t i = i0;
-  for (int z = z0; z < z1; ++z, i += (int64_t)g.nx * g.ny, up += sz) {
-    ldKz<K, SU, T>(up + sz, z + 1 < g.nz, un);
-    const cx<T> d = dg[i];
-    cx<T> acc[K], sum[K];
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  int64_t i = ((int64_t)z0 * g.ny + y0) * g.nx + x;  // point (x, y0, z)
+  const SU* up = u + i * g.P + c;
+  // rows r >= ry never load and never store (values stay zero)
+  cx<T> um[RY][K], uc[RY][K], un[RY][K], nb[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      acc[k] = d * uc[k];
-      sum[k] = ihz * (um[k] + un[k]);
-    }
-    ldKz<K, SU, T>(up - sx, x > 0, nb);
+  for (int r = 0; r < RY; ++r) {
+    ldKz<K, SU, T>(up + r * sy - sz, r < ry && z0 > 0, um[r]);
+    ldKz<K, SU, T>(up + r * sy, r < ry, uc[r]);
+  }
+  for (int z = z0; z < z1; ++z, i += plane, up += sz) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
-    ldKz<K, SU, T>(up + sx, x < g.nx - 1, nb);
+    for (int r = 0; r < RY; ++r) ldKz<K, SU, T>(up + r * sy + sz, r < ry && z + 1 < g.nz, un[r]);
+    cx<T> lo[K], hi[K];  // y-halo rows y0-1 and y0+ry
+    ldKz<K, SU, T>(up - sy, y0 > 0, lo);
+    ldKz<K, SU, T>(up + ry * sy, y0 + ry < g.ny, hi);
 #pragma unroll
-    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
-    ldKz<K, SU, T>(up - sy, y > 0, nb);
+    for (int r = 0; r < RY; ++r) {
+      if (r >= ry) break;
+      const int64_t ir = i + (int64_t)r * g.nx;
+      const cx<T> d = dg[ir];
+      cx<T> acc[K], sum[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihy * nb[k];
-    ldKz<K, SU, T>(up + sy, y < g.ny - 1, nb);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      sum[k] = sum[k] + ihy * nb[k];
-      acc[k] = acc[k] - sum[k];
-    }
-    const int64_t o = i * g.P + c;
-    if (MODE == 0) {
-      stK<K, SO, T>(out + o, acc);
-    } else {
-      cx<T> fv[K], res[K];
-      ldK<K, SF, T>(f + o, fv);
-      if (MODE == 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
-      } else {
-        const cx<T> w = dw[i];
-#pragma unroll
-        for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
+      for (int k = 0; k < K; ++k) {
+        acc[k] = d * uc[r][k];
+        const cx<T> ylo = r == 0 ? lo[k] : uc[r > 0 ? r - 1 : 0][k];
+        const cx<T> yhi = r == ry - 1 ? hi[k] : uc[r + 1 < RY ? r + 1 : r][k];
+        sum[k] = ihz * (um[r][k] + un[r][k]) + ihy * (ylo + yhi);
       }
-      stK<K, SO, T>(out + o, res);
+      ldKz<K, SU, T>(up + r * sy - sx, x > 0, nb);
+#pragma unroll
+      for (int k = 0; k < K; ++k) sum[k] = sum[k] + ihx * nb[k];
+      ldKz<K, SU, T>(up + r * sy + sx, x < g.nx - 1, nb);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        sum[k] = sum[k] + ihx * nb[k];
+        acc[k] = acc[k] - sum[k];
+      }
+      const int64_t o = ir * g.P + c;
+      if (MODE == 0) {
+        stK<K, SO, T>(out + o, acc);
+      } else {
+        cx<T> fv[K], res[K];
+        ldK<K, SF, T>(f + o, fv);
+        if (MODE == 1) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
+        } else {
+          const cx<T> w = dw[ir];
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = uc[r][k] + w * (fv[k] - acc[k]);
+        }
+        stK<K, SO, T>(out + o, res);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      um[k] = uc[k];
-      uc[k] = un[k];
-    }
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        um[r][k] = uc[r][k];
+        uc[r][k] = un[r][k];
+      }
   }
 }
 
@@ -243,8 +257,8 @@ __global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, con
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = {(T)0, (T)0};
   const cx<T>* sp = st + i * NS;
-  // one stencil entry per iteration, unrolled by 3 only: bounds the number
-  // of neighbour loads in flight (and so the registers they hold)
+  // one stencil entry per iteration, unrolled by 3 only: bounds the
+  // number of neighbour loads in flight (and so the registers they hold)
 #pragma unroll 3
   for (int o = 0; o < NS; ++o) {
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
@@ -428,10 +442,27 @@ __global__ __launch_bounds__(256) void k_to_abi(int64_t N, int nrhs, int P, cons
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 255) / 256)); }
 
-// Planes per z-chunk of the marching kernel: long enough to amortise the
-// two halo planes, short enough for many workgroups per XCD.
-static int zchunk_planes = 16;
-void set_zchunk(int zc) { zchunk_planes = zc > 0 ? zc : 16; }
+// Tile shape of the 3D marching kernel (set by the host's autotuner):
+// y rows per lane and z planes per chunk. Every shape computes each output
+// from the same loads in the same order, so results are bitwise identical.
+static thread_local FineTile g_tile = {4, 32};
+void set_fine_tile(FineTile t) { g_tile = t; }
+FineTile get_fine_tile() { return g_tile; }
+
+template <class SU, class SF, class SO, class T, int MODE, int RY>
+static void fine_zm_launch(const Geo& g, int L, const void* u, const void* f, void* out, const void* dg,
+                           const void* dw, const double ih[3], int zc, hipStream_t s) {
+  ZTiles zt;
+  const int PPB = 256 / L;
+  zt.nxb = (g.nx + PPB - 1) / PPB;
+  zt.zc = zc;
+  zt.nzc = (g.nz + zt.zc - 1) / zt.zc;
+  zt.ntiles = (int64_t)zt.nxb * ((g.ny + RY - 1) / RY) * zt.nzc;
+  zt.per = (int)((zt.ntiles + 7) / 8);
+  hipLaunchKernelGGL((k_fine_zm<SU, SF, SO, T, MODE, RY>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(256), 0, s,
+                     g, zt, (const SU*)u, (const SF*)f, (SO*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
+                     (T)ih[1], (T)ih[2]);
+}
 
 template <class SU, class SF, class SO, class T, int MODE>
 static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, void* out, const void* dg,
@@ -439,16 +470,16 @@ static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, v
   constexpr int K = kmax3<SU, SF, SO>();
   const int L = g.P / K;
   if (dim == 3 && MODE != 3 && L <= 256) {
-    ZTiles zt;
-    const int PPB = 256 / L;
-    zt.nxb = (g.nx + PPB - 1) / PPB;
-    zt.zc = zchunk_planes;
-    zt.nzc = (g.nz + zt.zc - 1) / zt.zc;
-    zt.ntiles = (int64_t)zt.nxb * g.ny * zt.nzc;
-    zt.per = (int)((zt.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_fine_zm<SU, SF, SO, T, MODE>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(256), 0, s, g,
-                       zt, (const SU*)u, (const SF*)f, (SO*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
-                       (T)ih[1], (T)ih[2]);
+    // one row per lane when the output is wider than the input (keeps the
+    // FP64-result apply at full occupancy); otherwise the tuned shape
+    const int ry = sizeof(SO) > sizeof(SU) ? 1 : g_tile.ry;
+    const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
+    if (ry == 1)
+      fine_zm_launch<SU, SF, SO, T, MODE, 1>(g, L, u, f, out, dg, dw, ih, zc, s);
+    else if (ry == 2)
+      fine_zm_launch<SU, SF, SO, T, MODE, 2>(g, L, u, f, out, dg, dw, ih, zc, s);
+    else
+      fine_zm_launch<SU, SF, SO, T, MODE, 4>(g, L, u, f, out, dg, dw, ih, zc, s);
     return;
   }
   const int64_t thr = g.npts * (g.P / K);

@@ -19,6 +19,13 @@ struct PtrList {
 [[noreturn]] void fatal_combo(const char* where);
 
 // ---- k_level.hip ------------------------------------------------------------
+// Tile shape of the 3D finest-level marching kernel (rows per lane 1/2/4,
+// planes per z-chunk); results do not depend on it.
+struct FineTile {
+  int ry, zc;
+};
+void set_fine_tile(FineTile t);
+FineTile get_fine_tile();
 // mode: 0 apply (out = A u), 1 residual (out = f - A u),
 //       2 Jacobi (out = u + dw (f - A u)), 3 zero-guess Jacobi (out = dw f).
 void launch_fine(int mode, Prec pu, Prec pf, Prec po, Prec pt, int dim, const Geo& g, const void* u, const void* f,
