@@ -256,3 +256,98 @@ def setup_problem(prob, levels=None, **kw) -> Hierarchy:
     g = grid(prob.dim, prob.n, prob.h)
     L = levels or prob.levels
     return Hierarchy(g, prob.m, prob.gamma, prob.omega, prob.shift, L, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Convolutional network of the learned coarsest-grid correction
+# (channels last: [B][D][D][D][C] with x fastest; taps t = (dx+1)+3(dy+1)+9(dz+1))
+# ---------------------------------------------------------------------------
+def _conv_lib():
+    L = lib()
+    if not hasattr(L, "_conv_ready"):
+        P, I, D = C.c_void_p, C.c_int, C.c_double
+        L.orc_conv3d_fwd.argtypes = [I, I, I, I, P, P, P, I, P]
+        L.orc_conv3d_bwd_data.argtypes = [I, I, I, I, P, P, P]
+        L.orc_conv3d_bwd_weight.argtypes = [I, I, I, I, P, P, P, P]
+        L.orc_avgpool2.argtypes = [I, I, I, P, P]
+        L.orc_upsample2.argtypes = [I, I, I, P, P]
+        L.orc_unet_nparams.restype = C.c_long
+        L.orc_unet_forward.argtypes = [I, I, P, P, P]
+        L.orc_unet_loss_grad.restype = D
+        L.orc_unet_loss_grad.argtypes = [I, I, P, P, P, P, P]
+        L._conv_ready = True
+    return L
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def conv3d(x, W, b=None, relu=False):
+    """x [B,D,D,D,Cin], W [27,Cin,Cout], b [Cout] -> [B,D,D,D,Cout]."""
+    x, W = _f64(x), _f64(W)
+    B, D, Cin, Cout = x.shape[0], x.shape[1], x.shape[4], W.shape[2]
+    y = np.empty(x.shape[:4] + (Cout,))
+    bb = None if b is None else _f64(b)
+    _conv_lib().orc_conv3d_fwd(B, D, Cin, Cout, _p(x), _p(W), None if bb is None else _p(bb), int(relu), _p(y))
+    return y
+
+
+def conv3d_bwd_data(dy, W):
+    dy, W = _f64(dy), _f64(W)
+    B, D, Cin, Cout = dy.shape[0], dy.shape[1], W.shape[1], W.shape[2]
+    dx = np.empty(dy.shape[:4] + (Cin,))
+    _conv_lib().orc_conv3d_bwd_data(B, D, Cin, Cout, _p(dy), _p(W), _p(dx))
+    return dx
+
+
+def conv3d_bwd_weight(x, dy):
+    x, dy = _f64(x), _f64(dy)
+    B, D, Cin, Cout = x.shape[0], x.shape[1], x.shape[4], dy.shape[4]
+    dW = np.empty((27, Cin, Cout))
+    db = np.empty(Cout)
+    _conv_lib().orc_conv3d_bwd_weight(B, D, Cin, Cout, _p(x), _p(dy), _p(dW), _p(db))
+    return dW, db
+
+
+def avgpool2(x):
+    x = _f64(x)
+    B, D, Cc = x.shape[0], x.shape[1], x.shape[4]
+    y = np.empty((B, D // 2, D // 2, D // 2, Cc))
+    _conv_lib().orc_avgpool2(B, D, Cc, _p(x), _p(y))
+    return y
+
+
+def upsample2(x):
+    x = _f64(x)
+    B, d, Cc = x.shape[0], x.shape[1], x.shape[4]
+    y = np.empty((B, 2 * d, 2 * d, 2 * d, Cc))
+    _conv_lib().orc_upsample2(B, d, Cc, _p(x), _p(y))
+    return y
+
+
+UNET_LAYERS = ((4, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32), (32, 32), (48, 16), (16, 16))
+
+
+def unet_nparams():
+    return int(_conv_lib().orc_unet_nparams())
+
+
+def unet_forward(params, x):
+    """params: packed float64 vector; x [B,D,D,D,4] -> out [B,D,D,D,2]."""
+    params, x = _f64(params), _f64(x)
+    B, D = x.shape[0], x.shape[1]
+    out = np.empty((B, D, D, D, 2))
+    _conv_lib().orc_unet_forward(B, D, _p(params), _p(x), _p(out))
+    return out
+
+
+def unet_loss_grad(params, x, target, mask=None):
+    """Mean over samples of ||out - t||^2/||t||^2 (on mask != 0) and its gradient."""
+    params, x, target = _f64(params), _f64(x), _f64(target)
+    B, D = x.shape[0], x.shape[1]
+    g = np.empty_like(params)
+    mk = None if mask is None else _f64(mask)
+    loss = _conv_lib().orc_unet_loss_grad(B, D, _p(params), _p(x), _p(target),
+                                          None if mk is None else _p(mk), _p(g))
+    return loss, g
