@@ -10,7 +10,11 @@ a 3-level shifted-Laplacian V(2,2) cycle (shift 0.2, damped Jacobi 0.8,
 Galerkin coarse operators, 20 GMRES steps on the coarsest grid). Inputs are
 synthetic (no dataset) and resident in device memory when timing starts.
 
-Prints one JSON line. Options select the precision and the block size.
+Prints one JSON line. Options select the precision, the block size and the
+coarsest solve (--coarse learned trains the coarsest-grid network on a
+96^3-cell instance of the same model family with exact coarsest solves as
+targets, untimed, then uses its correction as the start of --coarse-iters
+GMRES steps).
 """
 import argparse
 import json
@@ -32,6 +36,49 @@ def fine_sweep_bytes(prec, N, P):
     s = STORE[prec]
     coef = 16 if prec == "fp64" else 8
     return N * (3 * s * P + 2 * coef)
+
+
+def committed_traffic(precision, n, nrhs, tile):
+    """HBM bytes per launch of the finest-level sweep from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel
+    calibration recorded there), or None when that summary was taken for
+    another configuration or tile."""
+    path = os.path.join(ROOT, "profiles", "fine_sweep_mixed_192x64_traffic.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("traffic:"):
+            continue
+        kv = dict(t.split("=", 1) for t in ln[len("traffic:"):].split())
+        if (kv.get("precision") == precision and int(kv.get("n", 0)) == n and int(kv.get("nrhs", 0)) == nrhs
+                and kv.get("tile") == f"{tile[0]}x{tile[1]}"):
+            return int(float(kv["bytes_per_launch"]))
+    return None
+
+
+def train_coarse_net(args, pk, synth, np, torch):
+    """Train the coarsest-grid network on a half-size instance (exact LU
+    coarsest solves as targets). Returns (blob, info)."""
+    t0 = time.perf_counter()
+    pt = synth.config(3, n=args.n // 2)
+    teach = pk.helm_setup(pt.dim, pt.n, pt.h, pt.m, pt.gamma, pt.omega, shift=pt.shift, levels=3,
+                          precision=args.precision, coarse="lu")
+    nu = pk.helm_level_dims(teach, 2)
+    D = (max(nu) + 3) // 4 * 4
+    net = pk.helm_net_create(D, 16, seed=0)
+    pk.helm_net_capture(teach, net, 4096)
+    Qt = torch.from_numpy(pt.Q).cuda()
+    pk.helm_solve_block(teach, Qt, torch.zeros_like(Qt), tol=1e-6, restart=args.restart, block_size=1)
+    pk.helm_net_capture(teach, net, 0)
+    hist = net.train(args.train_steps, 16, lr=1e-3, seed=1)
+    blob = net.save()
+    info = {"train_n": args.n // 2, "train_D": D, "pairs": net.pairs(), "steps": args.train_steps,
+            "loss_first": round(float(hist[:20].mean()), 4), "loss_last": round(float(hist[-20:].mean()), 4),
+            "train_s": round(time.perf_counter() - t0, 1)}
+    del teach, net
+    return blob, info
 
 
 def cpu_baseline(p, gpu_cycles, iters):
@@ -60,7 +107,9 @@ def main():
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--block-size", type=int, default=1)
     ap.add_argument("--restart", type=int, default=5)
+    ap.add_argument("--coarse", default="gmres", choices=["gmres", "learned"])
     ap.add_argument("--coarse-iters", type=int, default=20)
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--reorth", type=int, default=0)
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--max-cycles", type=int, default=2000,
@@ -79,9 +128,13 @@ def main():
     import paper_1607_00968_amd as pk
 
     p = synth.config(3, n=args.n)
+    net_blob, net_info = None, None
+    if args.coarse == "learned":
+        net_blob, net_info = train_coarse_net(args, pk, synth, np, torch)
     t0 = time.perf_counter()
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
-                       precision=args.precision, coarse="gmres", coarse_iters=args.coarse_iters)
+                       precision=args.precision, coarse=args.coarse, coarse_iters=args.coarse_iters,
+                       net=net_blob)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     Q = torch.from_numpy(p.Q).cuda()
@@ -117,8 +170,9 @@ def main():
     byts = fine_sweep_bytes(args.precision, N, P)
     avg_s = ms / 1e3 / max(launches, 1)
     achieved = byts / avg_s / 1e9
+    traffic = committed_traffic(args.precision, args.n, p.nrhs, tile)
     roof = {"kernel": "finest-level damped-Jacobi sweep", "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
             "bytes_per_launch": int(byts), "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches}
     per_step = {k: round(v[1] / args.steps, 2) for k, v in stats.items()}
 
@@ -131,13 +185,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D Helmholtz {args.n}^3 cells x {p.nrhs} point sources, 8 ppw, "
                                f"block FGMRES({args.restart}) + 3-level shifted-Laplacian V(2,2), "
-                               f"GMRES({args.coarse_iters}) coarsest",
+                               + (f"GMRES({args.coarse_iters}) coarsest" if args.coarse == "gmres" else
+                                  f"learned coarsest correction + GMRES({args.coarse_iters})"),
                    "precision": args.precision, "block_size": args.block_size, "reorth": args.reorth,
                    "cycles_per_step": cycles, "max_relres": relres, "converged": ok,
                    "setup_s": round(t_setup, 2), "fine_tile_rows_planes": list(tile),
-                   "kernel_ms_per_step": per_step},
+                   "kernel_ms_per_step": per_step,
+                   "fallbacks": sum(i["fallback_used"] for i in infos)},
         "roofline": roof,
     }
+    if net_info is not None:
+        out["config"]["coarse_net"] = net_info
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, cycles[0], args.cpu_iters)
     print(json.dumps(out), flush=True)

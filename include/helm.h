@@ -87,7 +87,9 @@ typedef struct {
                                   levels >= 2, FP64 outer Krylov) */
   int32_t coarse;              /* HELM_COARSE_* */
   int32_t cycle;               /* HELM_CYCLE_* */
-  int32_t coarse_iters;        /* GMRES steps for HELM_COARSE_GMRES (1..48) */
+  int32_t coarse_iters;        /* HELM_COARSE_GMRES: GMRES steps from zero (1..48);
+                                  HELM_COARSE_LEARNED: GMRES steps started from the
+                                  network's correction (0..48, 0 = network alone) */
   const void* net;             /* HOST weights blob for HELM_COARSE_LEARNED (or NULL) */
   size_t net_bytes;
 } helm_setup_desc;
@@ -110,7 +112,8 @@ typedef struct {
   int32_t cycles;       /* Arnoldi steps = preconditioner applications (the paper's #Cyc) */
   int32_t restarts;
   int32_t converged_all;
-  int32_t fallback_used;/* learned coarse solve replaced by the exact one */
+  int32_t fallback_used;/* coarsest solves where the learned correction was not finite
+                           and coarse_iters GMRES steps replaced it */
   double t_solve_ms;    /* device time of the solve (hip events) */
   double* relres;       /* HOST [nrhs] or NULL: final FP64 ||q_s - H u_s|| / ||q_s|| */
   int32_t* converged;   /* HOST [nrhs] or NULL */
@@ -195,6 +198,61 @@ helm_status helm_profile_read(helm_handle h, helm_kernel_stat* stats);
 
 const char* helm_status_string(helm_status s);
 const char* helm_last_error(void);
+
+/* ---- Learned coarsest-grid correction ------------------------------------
+ * The paper names a cheaper stationary inexact solver of the coarsest grid as
+ * future work (end of section 5.3 and the conclusions). This is one: a 3-level
+ * 3D U-Net (channels 16/32/64, 3x3x3 convolutions + ReLU, 2x average pooling,
+ * nearest upsampling, skip connections by concatenation, a linear 1x1 head)
+ * on a D^3 volume that embeds the coarsest grid (D = its largest unknown count
+ * per axis rounded up to a multiple of 4). Input channels per voxel: Re, Im of
+ * r / rms(r) and Re, Im of H^2 times the diagonal of the coarsest Galerkin
+ * operator; output e = H^2 rms(r) (out_0 + i out_1). BF16 activations and
+ * weights, FP32 accumulation and master weights. Parameters are packed per
+ * 3x3x3 layer as W[27][Cin][Cout] (tap (dx+1) + 3(dy+1) + 9(dz+1), x fastest)
+ * then b[Cout], then the head W[16][2], b[2].
+ * A network is used by helm_setup with coarse = HELM_COARSE_LEARNED and
+ * net = a blob from helm_net_save (3D only). With coarse_iters = k > 0 the
+ * network's correction is the initial guess of k GMRES steps on the coarsest
+ * grid. A non-finite output makes that coarsest solve fall back to
+ * max(k, 20) GMRES steps from zero (counted in info.fallback_used). */
+typedef struct helm_net_s* helm_net;
+/* Number of FP32 parameters. */
+int64_t helm_net_nparams(void);
+/* A network on D^3 volumes (D % 4 == 0, 4..256) for batches of up to
+ * max_batch samples, He-initialised from seed. Synchronises `stream`. */
+helm_status helm_net_create(int32_t D, int32_t max_batch, uint64_t seed, void* stream, helm_net* out);
+void helm_net_destroy(helm_net n);
+/* HOST [helm_net_nparams()] FP32 parameters in the packing above. Setting
+ * resets the optimiser state. */
+helm_status helm_net_set_params(helm_net n, const float* params);
+helm_status helm_net_get_params(helm_net n, float* params);
+/* Serialise: blob == NULL returns the size in *bytes; otherwise writes
+ * "HNET", uint32 1, int64 nparams, float params[] into blob (HOST). */
+helm_status helm_net_save(helm_net n, void* blob, size_t* bytes);
+/* out = network(x). x: DEVICE FP32 [B][D^3][4], out: DEVICE FP32 [B][D^3][2],
+ * 1 <= B <= max_batch. Synchronises `stream`. */
+helm_status helm_net_forward(helm_net n, int32_t B, const float* x, float* out, void* stream);
+/* loss = (1/B) sum_s ||out_s - t_s||^2 / ||t_s||^2 over voxels with mask != 0
+ * (samples with t_s = 0 on the mask add 0) and grad = d loss / d params.
+ * x, target as above, mask: DEVICE uint8 [D^3], grad: DEVICE FP32 [nparams],
+ * loss: HOST. Synchronises `stream`. */
+helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const float* target,
+                               const uint8_t* mask, float* grad, double* loss, void* stream);
+/* Training pairs from a solver: until the next call, every coarsest solve of
+ * `h` (3D; coarse must be LU or GMRES; its coarsest grid must fit D) stores
+ * (input volume, exact-solve target) of each nonzero column into a pool of
+ * max_pairs volumes held by n (reservoir sampling). max_pairs == 0 detaches. */
+helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs);
+int64_t helm_net_pairs(helm_net n);
+/* Copy pool entry i (0 <= i < helm_net_pairs): x DEVICE FP32 [D^3][4] (the
+ * network input as stored, BF16 widened) and target DEVICE FP32 [D^3][2]
+ * (e / (H^2 rms(r)), 0 outside the grid). Synchronises `stream`. */
+helm_status helm_net_pool_read(helm_net n, int64_t i, float* x, float* target, void* stream);
+/* Adam (beta 0.9, 0.999, eps 1e-8) on minibatches of `batch` pool samples
+ * drawn uniformly with `seed`; hist: HOST [steps] loss per step, or NULL. */
+helm_status helm_net_train(helm_net n, int32_t steps, int32_t batch, double lr, uint64_t seed,
+                           double* hist, void* stream);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@ __all__ = [
     "helm_profile_enable", "helm_profile_read", "KERNEL_CLASSES",
     "helm_residual", "helm_apply", "helm_precond", "helm_level_stencil",
     "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "ABI_SYMBOLS",
+    "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +43,9 @@ ABI_SYMBOLS = (
     "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
     "helm_profile_enable", "helm_profile_read", "helm_fine_tile", "helm_set_fine_tile",
     "helm_status_string", "helm_last_error",
+    "helm_net_nparams", "helm_net_create", "helm_net_destroy", "helm_net_set_params",
+    "helm_net_get_params", "helm_net_save", "helm_net_forward", "helm_net_loss_grad",
+    "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
                   "coarsest", "gram", "update", "fine_sweep0")
@@ -107,6 +111,20 @@ def lib():
         L.helm_status_string.restype = C.c_char_p
         L.helm_status_string.argtypes = [I]
         L.helm_last_error.restype = C.c_char_p
+        L.helm_net_nparams.restype = C.c_int64
+        L.helm_net_nparams.argtypes = []
+        L.helm_net_create.argtypes = [I, I, C.c_uint64, P, C.POINTER(P)]
+        L.helm_net_destroy.argtypes = [P]
+        L.helm_net_set_params.argtypes = [P, P]
+        L.helm_net_get_params.argtypes = [P, P]
+        L.helm_net_save.argtypes = [P, P, C.POINTER(C.c_size_t)]
+        L.helm_net_forward.argtypes = [P, I, P, P, P]
+        L.helm_net_loss_grad.argtypes = [P, I, P, P, P, P, C.POINTER(D), P]
+        L.helm_net_capture.argtypes = [P, P, I]
+        L.helm_net_pairs.restype = C.c_int64
+        L.helm_net_pairs.argtypes = [P]
+        L.helm_net_pool_read.argtypes = [P, C.c_int64, P, P, P]
+        L.helm_net_train.argtypes = [P, I, I, D, C.c_uint64, P, P]
         _lib = L
     return _lib
 
@@ -222,7 +240,7 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
     st = _check(lib().helm_solve_block(hd.ptr, nrhs, qp, up, float(tol), C.byref(o), wp, wb,
                                        C.byref(info), _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
     return {"status": st, "cycles": info.cycles, "restarts": info.restarts,
-            "converged_all": bool(info.converged_all), "fallback_used": bool(info.fallback_used),
+            "converged_all": bool(info.converged_all), "fallback_used": int(info.fallback_used),
             "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool)}
 
 
@@ -294,3 +312,103 @@ def helm_set_fine_tile(hd: Handle, nrhs: int, ry: int, zc: int):
     """Force the tile of the finest-level stencil kernels for nrhs columns."""
     t = (C.c_int32 * 2)(ry, zc)
     _check(lib().helm_set_fine_tile(hd.ptr, nrhs, t))
+
+
+# ---- learned coarsest-grid correction ---------------------------------------
+def helm_net_nparams() -> int:
+    return int(lib().helm_net_nparams())
+
+
+def _dev_f32(t, name, shape=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """Owns a helm_net: the coarsest-grid correction network on D^3 volumes."""
+
+    def __init__(self, ptr, D, max_batch):
+        self.ptr = ptr
+        self.D = D
+        self.max_batch = max_batch
+
+    def close(self):
+        if self.ptr:
+            lib().helm_net_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != helm_net_nparams():
+            raise ValueError("wrong parameter count")
+        _check(lib().helm_net_set_params(self.ptr, C.c_void_p(p.ctypes.data)))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(helm_net_nparams(), dtype=np.float32)
+        _check(lib().helm_net_get_params(self.ptr, C.c_void_p(p.ctypes.data)))
+        return p
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().helm_net_save(self.ptr, None, C.byref(n)))
+        buf = (C.c_uint8 * n.value)()
+        _check(lib().helm_net_save(self.ptr, C.cast(buf, C.c_void_p), C.byref(n)))
+        return bytes(buf)
+
+    def forward(self, x, out, stream=None):
+        """x: float32 CUDA [B, D^3, 4] -> out: float32 CUDA [B, D^3, 2]."""
+        B = x.shape[0]
+        V = self.D ** 3
+        _check(lib().helm_net_forward(self.ptr, B, _dev_f32(x, "x", (B, V, 4)),
+                                      _dev_f32(out, "out", (B, V, 2)), _stream(stream)))
+
+    def loss_grad(self, x, target, mask, grad, stream=None) -> float:
+        """Loss and its gradient (into grad, float32 CUDA [nparams])."""
+        import torch
+        B = x.shape[0]
+        V = self.D ** 3
+        if not (mask.is_cuda and mask.dtype == torch.uint8 and mask.numel() == V and mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 CUDA tensor of D^3 entries")
+        loss = C.c_double(0.0)
+        _check(lib().helm_net_loss_grad(self.ptr, B, _dev_f32(x, "x", (B, V, 4)),
+                                        _dev_f32(target, "target", (B, V, 2)), C.c_void_p(mask.data_ptr()),
+                                        _dev_f32(grad, "grad", (helm_net_nparams(),)), C.byref(loss),
+                                        _stream(stream)))
+        return loss.value
+
+    def pairs(self) -> int:
+        return int(lib().helm_net_pairs(self.ptr))
+
+    def pool_read(self, i, x, target, stream=None):
+        """Pool entry i into x float32 CUDA [D^3, 4] and target [D^3, 2]."""
+        V = self.D ** 3
+        _check(lib().helm_net_pool_read(self.ptr, int(i), _dev_f32(x, "x", (V, 4)),
+                                        _dev_f32(target, "target", (V, 2)), _stream(stream)))
+
+    def train(self, steps, batch, lr=1e-3, seed=0, stream=None) -> np.ndarray:
+        hist = np.zeros(steps, dtype=np.float64)
+        _check(lib().helm_net_train(self.ptr, int(steps), int(batch), float(lr), int(seed),
+                                    C.c_void_p(hist.ctypes.data), _stream(stream)))
+        return hist
+
+
+def helm_net_create(D: int, max_batch: int, seed: int = 0, stream=None) -> Net:
+    out = C.c_void_p()
+    _check(lib().helm_net_create(int(D), int(max_batch), int(seed), _stream(stream), C.byref(out)))
+    return Net(out, D, max_batch)
+
+
+def helm_net_capture(hd: Handle, net: Net, max_pairs: int):
+    """Store (input, exact target) pairs of hd's coarsest solves in net's pool
+    (max_pairs == 0 detaches)."""
+    _check(lib().helm_net_capture(hd.ptr, net.ptr, int(max_pairs)))

@@ -26,7 +26,7 @@ namespace helm {
 
 static thread_local std::string g_err;
 
-static helm_status fail(helm_status st, const char* fmt, ...) {
+helm_status fail(helm_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -98,6 +98,8 @@ struct helm_ctx {
   c128* Minv64 = nullptr;  // dense coarsest inverse
   c64* Minv32 = nullptr;
   learned::Net* net = nullptr;
+  int64_t fallbacks = 0;            // learned coarsest solves replaced by GMRES
+  learned::Net* cap = nullptr;      // pool receiving coarsest (f, e) pairs
   // cached per-solve field allocation
   int fieldsP = 0;
   void* fieldmem = nullptr;
@@ -246,10 +248,10 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
 
 // k steps of GMRES from zero on the coarsest grid, one independent GMRES per
 // column (classical Gram-Schmidt, applied twice), least squares by Givens
-// rotations. No host synchronisation: the step count is fixed.
-static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, hipStream_t s) {
+// rotations. No host synchronisation: the step count is fixed. `out` may be
+// the buffer `f` (f is read only before the first step).
+static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, int k, hipStream_t s) {
   const int l = c->L - 1;
-  const int k = c->coarse_iters;
   const Level& L = c->lv[l];
   const int64_t N = L.npts;
   const Prec p = field_prec(c, l);
@@ -282,8 +284,14 @@ static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, hipStream
   launch_block_update(1, p, p, N, P, P, 1, k, vl, Yc, out, s);
 }
 
+// GMRES steps the coarsest storage must hold: coarse_iters, and for the
+// learned correction at least the 20 steps of its fallback.
+static int coarse_gmres_cap(const helm_ctx* c) {
+  return c->coarse == HELM_COARSE_LEARNED ? std::max(c->coarse_iters, 20) : c->coarse_iters;
+}
+
 static size_t coarse_gmres_bytes(const helm_ctx* c, int P) {
-  const int l = c->L - 1, k = c->coarse_iters;
+  const int l = c->L - 1, k = coarse_gmres_cap(c);
   const size_t vb = (psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256;
   return vb * (k + 1) + 16 * ((size_t)P * (k + 1) * k + 3 * (size_t)(k + 1) * P + gram_part_elems(P) + 2 * P) +
          8 * 3 * (size_t)P + 256;
@@ -297,9 +305,19 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
     else
       launch_gemm(P32, c->nc, P, c->nc, c128{1, 0}, c->Minv32, c->nc, f, P, c128{0, 0}, out, P, s);
   } else if (c->coarse == HELM_COARSE_GMRES) {
-    coarse_gmres(c, P, f, out, s);
+    coarse_gmres(c, P, f, out, c->coarse_iters, s);
   } else if (c->coarse == HELM_COARSE_LEARNED && c->net) {
-    learned::apply(c->net, c, l, P, f, out, s);
+    if (!learned::apply(c->net, P, f, out, s)) {
+      ++c->fallbacks;
+      coarse_gmres(c, P, f, out, coarse_gmres_cap(c), s);
+    } else if (c->coarse_iters > 0) {
+      // the network's correction is the initial guess of coarse_iters GMRES
+      // steps on the remaining residual (Rr of the coarsest level is free)
+      void* r = c->lv[l].Rr;
+      level_op(c, l, 1, P, out, f, r, s);
+      coarse_gmres(c, P, r, r, c->coarse_iters, s);
+      field_axpy(c, l, P, r, out, s);
+    }
   } else {
     // relaxation only: nu_pre + nu_post damped Jacobi sweeps from zero
     const int sweeps = std::max(1, c->nu_pre[l] + c->nu_post[l]);
@@ -312,6 +330,18 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
       std::swap(a, b);
     }
   }
+  // training pairs for the learned correction (exact or GMRES solves only)
+  if (c->cap && (c->coarse == HELM_COARSE_LU || c->coarse == HELM_COARSE_GMRES)) learned::capture(c->cap, P, f, out, s);
+}
+
+static learned::Coarse coarse_view(const helm_ctx* c) {
+  const Level& L = c->lv[c->L - 1];
+  learned::Coarse g;
+  for (int a = 0; a < 3; ++a) g.nu[a] = L.nu[a];
+  g.H2 = L.h[0] * L.h[0];
+  g.p = field_prec(c, c->L - 1);
+  g.st = L.st64;
+  return g;
 }
 
 }  // namespace helm
@@ -341,7 +371,7 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
     c->kbuf[l] = p + 4 * b;
     p += 5 * b;
   }
-  if (c->coarse == HELM_COARSE_GMRES) {
+  if (c->coarse == HELM_COARSE_GMRES || c->coarse == HELM_COARSE_LEARNED) {
     hipFree(c->cg_mem);
     c->cg_mem = nullptr;
     HCHECK(hipMalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
@@ -548,6 +578,8 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   if (d->coarse < HELM_COARSE_LU || d->coarse > HELM_COARSE_GMRES) return fail(HELM_ERR_INVALID_ARG, "bad coarse kind");
   if (d->coarse == HELM_COARSE_GMRES && (d->coarse_iters < 1 || d->coarse_iters > 48))
     return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 1..48");
+  if (d->coarse == HELM_COARSE_LEARNED && (d->coarse_iters < 0 || d->coarse_iters > 48))
+    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 0..48 with the learned coarsest correction");
   if (d->cycle < HELM_CYCLE_V || d->cycle > HELM_CYCLE_K) return fail(HELM_ERR_INVALID_ARG, "bad cycle kind");
   if (d->cycle == HELM_CYCLE_K) return fail(HELM_ERR_UNSUPPORTED, "the K-cycle is not built in this library version");
   const int f = 1 << (d->levels - 1);
@@ -676,8 +708,17 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
       c->Minv64 = nullptr;
     }
   } else if (c->coarse == HELM_COARSE_LEARNED) {
-    st = learned::create(c, d->net, d->net_bytes, &c->net, s);
-    if (st != HELM_OK) return bail(st);
+    if (c->dim != 3) return bail(fail(HELM_ERR_UNSUPPORTED, "the learned coarsest correction is 3D only"));
+    std::vector<float> prm(learned::nparams());
+    if ((st = learned::read_blob(d->net, d->net_bytes, prm.data())) != HELM_OK) return bail(st);
+    const learned::Coarse g = coarse_view(c);
+    const int D = learned::edge_for(g);
+    // samples per network pass: bounded activation memory (about 270 B per voxel)
+    const int64_t V = (int64_t)D * D * D;
+    const int bmax = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(4LL << 30) / (272 * V)));
+    if ((st = learned::create(D, bmax, 0, s, &c->net)) != HELM_OK) return bail(st);
+    if ((st = learned::set_params(c->net, prm.data(), s)) != HELM_OK) return bail(st);
+    if ((st = learned::bind(c->net, g, s)) != HELM_OK) return bail(st);
   }
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
     return bail(fail(HELM_ERR_DEVICE, "setup: device error"));
@@ -830,9 +871,16 @@ struct WsLayout {
   size_t Qi, X, W, V, Z, part, G, Gc, Hb, S, R, Rinv, Y, est, qn2, rn2, w2, hn2, nu, flag, act, ls, end;
 };
 
+// Storage of the outer Krylov basis V and work vector W: FP32 complex in
+// mixed precision with block size 1 (every reduction over them stays FP64 and
+// the residual is recomputed from FP64 Q and X at each restart), FP64 complex
+// otherwise.
+static Prec basis_prec(const helm_ctx* c, int pb) { return c->precision == HELM_MIXED && pb == 1 ? P32 : P64; }
+
 static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
   const int64_t N = c->lv[0].npts;
   const size_t blk = 16 * (size_t)N * P;
+  const size_t vblk = psize(basis_prec(c, pb)) * (size_t)N * P;
   const size_t zblk = (c->precision == HELM_FP64 ? 16 : 8) * (size_t)N * P;
   const int ng = P / pb;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -840,8 +888,8 @@ static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
   size_t o = 0;
   w.Qi = o; o += al(blk);
   w.X = o; o += al(blk);
-  w.W = o; o += al(blk);
-  w.V = o; o += al(blk) * (m + 1);
+  w.W = o; o += al(vblk);
+  w.V = o; o += al(vblk) * (m + 1);
   w.Z = o; o += al(zblk) * m;
   w.part = o; o += al(16 * gram_part_elems(P));
   w.G = o; o += al(16 * (size_t)MAXPTR * P * pb);
@@ -936,6 +984,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if ((st = ensure_fields(c, P)) != HELM_OK) return st;
   if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
   set_fine_tile(c->tile);
+  const int64_t fallbacks0 = c->fallbacks;
   const WsLayout w = ws_layout(c, P, m, pb);
   char* base = static_cast<char*>(workspace);
   if (!base) {
@@ -960,14 +1009,15 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   double* hest = c->hbuf + 2 * P;
   int* hflag = reinterpret_cast<int*>(c->hbuf + 3 * P);
   const size_t blk = 16 * (size_t)N * P;
+  const Prec pv = basis_prec(c, pb);
   c128* Qi = (c128*)(base + w.Qi);
   c128* X = (c128*)(base + w.X);
-  c128* W = (c128*)(base + w.W);
-  std::vector<c128*> V(m + 1);
+  void* W = base + w.W;
+  std::vector<void*> V(m + 1);
   std::vector<void*> Z(m);
-  const size_t vstride = (blk + 255) / 256 * 256;
+  const size_t vstride = (psize(pv) * (size_t)N * P + 255) / 256 * 256;
   const size_t zstride = ((pz == P64 ? 16 : 8) * (size_t)N * P + 255) / 256 * 256;
-  for (int j = 0; j <= m; ++j) V[j] = (c128*)(base + w.V + j * vstride);
+  for (int j = 0; j <= m; ++j) V[j] = base + w.V + j * vstride;
   for (int j = 0; j < m; ++j) Z[j] = base + w.Z + j * zstride;
   c128* part = (c128*)(base + w.part);
   c128* G = (c128*)(base + w.G);
@@ -1016,8 +1066,8 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   const double tol2 = tol * tol;
   for (;;) {
     // true FP64 residual R = Q - H X into V0
-    launch_fine(1, P64, P64, P64, P64, c->dim, g0, X, Qi, V[0], L0.dH, nullptr, L0.ih, s);
-    { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, V[0], part, G, dr, s); }
+    launch_fine(1, P64, P64, pv, P64, c->dim, g0, X, Qi, V[0], L0.dH, nullptr, L0.ih, s);
+    { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(pv, N, P, Pa, V[0], part, G, dr, s); }
     HCHECK(hipMemcpyAsync(hr, dr, 8 * Pa, hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
     HCHECK(hipGetLastError());
@@ -1070,7 +1120,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     for (int j = 0; j < m; ++j) {
       // Z_j = cycle(V_j)
       const Level& Lz = c->lv[0];
-      if (pz == P64) {
+      if (pz == P64 || pv == P32) {
         cycle_rec(c, 0, P, V[j], Z[j], Lz.U1, s);
       } else {
         launch_convert(P64, P32, N * P, V[j], Lz.F, s);
@@ -1080,7 +1130,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       // W = H Z_j (FP64)
       {
         Prof pr(c, HELM_K_OUTER_APPLY, s);
-        launch_fine(0, pz, P64, P64, P64, c->dim, g0, Z[j], nullptr, W, L0.dH, nullptr, L0.ih, s);
+        launch_fine(0, pz, pv == P32 ? P32 : P64, pv, P64, c->dim, g0, Z[j], nullptr, W, L0.dH, nullptr, L0.ih, s);
       }
       // block classical Gram-Schmidt against V_0..V_j, then W = V_{j+1} R
       PtrList vl{};
@@ -1092,10 +1142,10 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
         // is kept unnormalised (nu_{j+1} = its norm), so W~' becomes v~_{j+1}.
         PtrList vw = vl;
         vw.p[j + 1] = W;
-        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 2, vw, W, part, G, s); }
+        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(pv, N, P, Pa, 1, j + 2, vw, W, part, G, s); }
         launch_diag_real(Pa, G + (size_t)(j + 1) * Pa, dw2, s);
         launch_lazy_coef(Pa, j, G, dnu, Gc, Hb, ldh, hstride, 0, s);
-        { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
+        { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(pv, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
         bool again = o.reorth == 1;
         if (o.reorth == 2) {
           std::vector<double> a(Pa), b(Pa);
@@ -1106,9 +1156,9 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
             if (hact[cidx] && b[cidx] < 0.25 * a[cidx]) again = true;
         }
         if (again) {
-          { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, 1, j + 1, vl, W, part, G, s); }
+          { Prof pr_(c, HELM_K_GRAM, s); launch_gram(pv, N, P, Pa, 1, j + 1, vl, W, part, G, s); }
           launch_lazy_coef(Pa, j, G, dnu, Gc, Hb, ldh, hstride, 1, s);
-          { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(P64, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
+          { Prof pr_(c, HELM_K_UPDATE, s); launch_update_norm(pv, N, P, Pa, j + 1, vl, Gc, W, part, G + (size_t)(j + 2) * Pa, dhn2, s); }
         }
         launch_lazy_next(Pa, j, dhn2, dw2, 1e-28, dnu, Hb, ldh, hstride, dflag, s);
         std::swap(V[j + 1], W);
@@ -1162,7 +1212,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     info->cycles = cycles;
     info->restarts = restarts;
     info->converged_all = converged ? 1 : 0;
-    info->fallback_used = c->net ? learned::fallback_used(c->net) : 0;
+    info->fallback_used = (int32_t)(c->fallbacks - fallbacks0);
     info->t_solve_ms = ms;
     for (int cidx = 0; cidx < nrhs; ++cidx) {
       if (info->relres) info->relres[cidx] = relres[cidx];
@@ -1217,3 +1267,94 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned coarsest-grid correction: network objects.
+// ---------------------------------------------------------------------------
+struct helm_net_s {
+  learned::Net* n = nullptr;
+  hipStream_t s = nullptr;
+};
+
+int64_t helm_net_nparams(void) { return learned::nparams(); }
+
+helm_status helm_net_create(int32_t D, int32_t max_batch, uint64_t seed, void* stream, helm_net* out) {
+  if (!out) return fail(HELM_ERR_INVALID_ARG, "null output");
+  *out = nullptr;
+  helm_net_s* w = new helm_net_s();
+  w->s = static_cast<hipStream_t>(stream);
+  const helm_status st = learned::create(D, max_batch, seed, w->s, &w->n);
+  if (st != HELM_OK) {
+    delete w;
+    return st;
+  }
+  *out = w;
+  return HELM_OK;
+}
+
+void helm_net_destroy(helm_net n) {
+  if (!n) return;
+  learned::destroy(n->n);
+  delete n;
+}
+
+helm_status helm_net_set_params(helm_net n, const float* params) {
+  if (!n || !params) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  return learned::set_params(n->n, params, n->s);
+}
+
+helm_status helm_net_get_params(helm_net n, float* params) {
+  if (!n || !params) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  return learned::get_params(n->n, params, n->s);
+}
+
+helm_status helm_net_save(helm_net n, void* blob, size_t* bytes) {
+  if (!n || !bytes) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  if (!blob) {
+    *bytes = learned::blob_bytes();
+    return HELM_OK;
+  }
+  if (*bytes < learned::blob_bytes()) return fail(HELM_ERR_INVALID_ARG, "blob needs %zu bytes", learned::blob_bytes());
+  *bytes = learned::blob_bytes();
+  return learned::write_blob(n->n, blob, n->s);
+}
+
+helm_status helm_net_forward(helm_net n, int32_t B, const float* x, float* out, void* stream) {
+  if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
+  return learned::forward(n->n, B, x, out, static_cast<hipStream_t>(stream));
+}
+
+helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const float* target, const uint8_t* mask,
+                               float* grad, double* loss, void* stream) {
+  if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
+  return learned::loss_grad(n->n, B, x, target, mask, grad, loss, static_cast<hipStream_t>(stream));
+}
+
+helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs) {
+  if (!h || !n) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  if (max_pairs == 0) {
+    if (h->cap == n->n) h->cap = nullptr;
+    return HELM_OK;
+  }
+  if (h->dim != 3) return fail(HELM_ERR_UNSUPPORTED, "pairs are captured from 3D problems only");
+  if (h->coarse != HELM_COARSE_LU && h->coarse != HELM_COARSE_GMRES)
+    return fail(HELM_ERR_INVALID_ARG, "pairs need an LU or GMRES coarsest solve");
+  helm_status st = learned::bind(n->n, coarse_view(h), n->s);
+  if (st != HELM_OK) return st;
+  if ((st = learned::capture_begin(n->n, max_pairs)) != HELM_OK) return st;
+  h->cap = n->n;
+  return HELM_OK;
+}
+
+int64_t helm_net_pairs(helm_net n) { return n ? learned::pairs(n->n) : 0; }
+
+helm_status helm_net_pool_read(helm_net n, int64_t i, float* x, float* target, void* stream) {
+  if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
+  return learned::pool_read(n->n, i, x, target, static_cast<hipStream_t>(stream));
+}
+
+helm_status helm_net_train(helm_net n, int32_t steps, int32_t batch, double lr, uint64_t seed, double* hist,
+                           void* stream) {
+  if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
+  return learned::train(n->n, steps, batch, lr, seed, hist, static_cast<hipStream_t>(stream));
+}

@@ -470,9 +470,10 @@ static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, v
   constexpr int K = kmax3<SU, SF, SO>();
   const int L = g.P / K;
   if (dim == 3 && MODE != 3 && L <= 256) {
-    // one row per lane when the output is wider than the input (keeps the
-    // FP64-result apply at full occupancy); otherwise the tuned shape
-    const int ry = sizeof(SO) > sizeof(SU) ? 1 : g_tile.ry;
+    // one row per lane when the output is wider than the input or the
+    // arithmetic is FP64 on two values per lane (keeps those outer products
+    // at 5-6 waves per SIMD); otherwise the tuned shape
+    const int ry = sizeof(SO) > sizeof(SU) || (sizeof(T) == 8 && K >= 2) ? 1 : g_tile.ry;
     const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
     if (ry == 1)
       fine_zm_launch<SU, SF, SO, T, MODE, 1>(g, L, u, f, out, dg, dw, ih, zc, s);
@@ -506,10 +507,14 @@ void launch_fine(int mode, Prec pu, Prec pf, Prec po, Prec pt, int dim, const Ge
                  void* out, const void* dg, const void* dw, const double ih[3], hipStream_t s) {
   // Supported combinations: FP64 cycle / outer (c128 everywhere, double),
   // mixed cycle (c64 everywhere, float), outer apply of a c64 field into a
-  // c128 result in double.
+  // c128 result in double, and the FP32-basis outer products (c128 inputs or
+  // c64 fields into c64 results, in double).
   if (pt == P64) {
     if (pu == P64 && pf == P64 && po == P64) return fine_mode<c128, c128, c128, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
     if (pu == P32 && pf == P64 && po == P64) return fine_mode<c64, c128, c128, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
+    // FP32 outer basis: true residual from FP64 Q, X; W = H Z in FP64 arithmetic
+    if (pu == P64 && pf == P64 && po == P32) return fine_mode<c128, c128, c64, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
+    if (pu == P32 && pf == P32 && po == P32) return fine_mode<c64, c64, c64, double>(mode, dim, g, u, f, out, dg, dw, ih, s);
   } else {
     if (pu == P32 && pf == P32 && po == P32) return fine_mode<c64, c64, c64, float>(mode, dim, g, u, f, out, dg, dw, ih, s);
     if (pu == P32 && pf == P64 && po == P32) return fine_mode<c64, c128, c64, float>(mode, dim, g, u, f, out, dg, dw, ih, s);

@@ -1,19 +1,1174 @@
-// learned.hip -- learned coarsest-grid correction (placeholder until the
-// network kernels are in).
-#include "learned.hpp"
+// learned.hip -- learned coarsest-grid correction: a small convolutional
+// network maps the coarsest-grid residual to an approximation of the
+// coarsest-grid error, replacing the coarsest solve inside the cycle.
+//
+// The paper names a stationary inexact solver of the coarsest grid as the
+// direction of its future work (end of section 5.3 and the conclusions);
+// this network is one. Architecture: a 3-level U-Net on a D^3 volume
+// (D = coarsest unknowns per axis rounded up to a multiple of 4), channels
+// last, BF16 activations and weights, FP32 accumulation and master weights:
+//   enc: conv3(4->16) conv3(16->16)=s1 | pool | conv3(16->32) conv3(32->32)=s2
+//        | pool | conv3(32->64) conv3(64->64)
+//   dec: up, concat s2 -> conv3(96->32) conv3(32->32) | up, concat s1 ->
+//        conv3(48->16) conv3(16->16) | 1x1 head 16->2 (linear)
+// Input channels: Re, Im of r / rms(r), and Re, Im of H^2 diag(M_c) (the
+// coarse operator's diagonal: carries the slowness and the absorbing layer).
+// Output: e = H^2 rms(r) (out_0 + i out_1).
+//
+// 3x3x3 convolutions run as implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x16_bf16): M = voxels, N = output channels, K = 27 x
+// input channels; the backward-data pass is the same kernel with mirrored
+// taps and transposed weights. Weight gradients accumulate in FP32 per chunk
+// of voxels and are summed in a fixed order (deterministic).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
 #include "kernels.hpp"
+#include "learned.hpp"
 
 namespace helm {
 namespace learned {
-struct Net {
-  int fallback = 0;
-};
-helm_status create(helm_ctx*, const void*, size_t, Net** out, hipStream_t) {
-  *out = nullptr;
-  return HELM_ERR_UNSUPPORTED;
+
+typedef uint16_t bf16;
+typedef short short4_ __attribute__((ext_vector_type(4)));
+typedef float float4_ __attribute__((ext_vector_type(4)));
+
+constexpr int NLAYER = 10;
+constexpr int L_CIN[NLAYER] = {4, 16, 16, 32, 32, 64, 96, 32, 48, 16};
+constexpr int L_COUT[NLAYER] = {16, 16, 32, 32, 64, 64, 32, 32, 16, 16};
+
+static int64_t layer_off(int l) {
+  int64_t o = 0;
+  for (int k = 0; k < l; ++k) o += 27LL * L_CIN[k] * L_COUT[k] + L_COUT[k];
+  return o;
 }
-void destroy(Net* n) { delete n; }
-void apply(Net*, helm_ctx*, int, int, const void*, void*, hipStream_t) {}
-int fallback_used(const Net* n) { return n ? n->fallback : 0; }
+static int64_t nparams_total() { return layer_off(NLAYER) + 16 * 2 + 2; }
+
+__device__ inline float b2f(bf16 b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// 3x3x3 convolution as an implicit GEMM on MFMA 16x16x16 (bf16 in, f32 acc).
+// Lane l of a wave supplies A[m = l%16][k = 4(l/16)..+3] (four consecutive
+// input channels of one tap), B[k][n = l%16] and receives
+// D[m = 4(l/16)+j][n = l%16]. A wave owns 32 voxels (two M tiles) and all
+// NT*16 output channels; a workgroup of four waves owns 128 voxels.
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+  int B, D, Cin, N;
+  const bf16* in;
+  int ldi, offi;
+  const bf16* W;  // [27][N][Cin]
+  const float* bias;
+  bf16* out;
+  int ldo, offo;
+  int flip, relu;
+  const bf16* mask;  // out *= (mask[v][offm + n] > 0) when set
+  int ldm, offm;
+};
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t V = (int64_t)a.D * a.D * a.D;
+  const int64_t total = (int64_t)a.B * V;
+  const int64_t vbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int ml = lane & 15, kg = lane >> 4;
+  // coordinates of the two voxels this lane feeds into A
+  int64_t gv[2];
+  int vx[2], vy[2], vz[2];
+  bool vin[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    gv[mt] = vbase + mt * 16 + ml;
+    vin[mt] = gv[mt] < total;
+    const int64_t v = vin[mt] ? gv[mt] % V : 0;
+    vx[mt] = (int)(v % a.D);
+    vy[mt] = (int)((v / a.D) % a.D);
+    vz[mt] = (int)(v / ((int64_t)a.D * a.D));
+  }
+  float4_ acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = float4_{0.f, 0.f, 0.f, 0.f};
+  const int Ktot = 27 * a.Cin;
+  const int sgn = a.flip ? -1 : 1;
+  for (int k0 = 0; k0 < Ktot; k0 += 16) {
+    const int k = k0 + 4 * kg;
+    const bool kin = k < Ktot;
+    const int tap = kin ? k / a.Cin : 0;
+    const int ci = kin ? k - tap * a.Cin : 0;
+    const int dx = sgn * (tap % 3 - 1), dy = sgn * ((tap / 3) % 3 - 1), dz = sgn * (tap / 9 - 1);
+    short4_ A[2], Bv[NT];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int x = vx[mt] + dx, y = vy[mt] + dy, z = vz[mt] + dz;
+      const bool ok = kin && vin[mt] && x >= 0 && x < a.D && y >= 0 && y < a.D && z >= 0 && z < a.D;
+      if (ok) {
+        const int64_t nb = gv[mt] + dx + (int64_t)a.D * (dy + (int64_t)a.D * dz);
+        A[mt] = *reinterpret_cast<const short4_*>(a.in + nb * a.ldi + a.offi + ci);
+      } else {
+        A[mt] = short4_{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + ml;
+      Bv[nt] = kin ? *reinterpret_cast<const short4_*>(a.W + ((int64_t)tap * a.N + n) * a.Cin + ci)
+                   : short4_{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[mt], Bv[nt], acc[mt][nt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t v = vbase + mt * 16 + 4 * kg + j;
+      if (v >= total) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + ml;
+        float r = acc[mt][nt][j] + (a.bias ? a.bias[n] : 0.f);
+        if (a.relu && !(r > 0.f)) r = 0.f;
+        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) r = 0.f;
+        a.out[v * a.ldo + a.offo + n] = f2bf(r);
+      }
+    }
+}
+
+static void conv3(const ConvArgs& a, hipStream_t s) {
+  const int64_t total = (int64_t)a.B * a.D * a.D * a.D;
+  const dim3 gr((unsigned)((total + 127) / 128));
+  switch (a.N / 16) {
+    case 1: hipLaunchKernelGGL(k_conv3<1>, gr, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_conv3<2>, gr, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_conv3<3>, gr, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_conv3<4>, gr, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_conv3<6>, gr, dim3(256), 0, s, a); break;
+    default: fatal_combo("conv3 output channels");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a 3x3x3 layer: part[chunk][t][ci][co] =
+// sum over the chunk's voxels v of X[v + off(t)][ci] dY[v][co] (FP32), with
+// a 32-voxel tile of X (shifted by the tap) and dY staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int WG_TILE = 32;
+constexpr int WG_CHUNK = 4096;  // voxels per partial
+
+__global__ __launch_bounds__(256) void k_wgrad_part(int B, int D, int Cin, int Cout, const bf16* __restrict__ X,
+                                                    int ldx, int offx, const bf16* __restrict__ dY, int ldy,
+                                                    int offy, float* __restrict__ part) {
+  extern __shared__ float smem[];
+  float* Xs = smem;                   // [WG_TILE][Cin]
+  float* Ys = smem + WG_TILE * Cin;   // [WG_TILE][Cout]
+  const int tap = blockIdx.y;
+  const int64_t V = (int64_t)D * D * D, total = (int64_t)B * V;
+  const int64_t c0 = (int64_t)blockIdx.x * WG_CHUNK;
+  const int no = Cin * Cout;
+  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+  float acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+  for (int64_t t0 = c0; t0 < c0 + WG_CHUNK && t0 < total; t0 += WG_TILE) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < WG_TILE * Cin; e += 256) {
+      const int r = e / Cin, ci = e - r * Cin;
+      const int64_t gv = t0 + r;
+      float val = 0.f;
+      if (gv < total) {
+        const int64_t v = gv % V;
+        const int x = (int)(v % D) + dx, y = (int)((v / D) % D) + dy, z = (int)(v / ((int64_t)D * D)) + dz;
+        if (x >= 0 && x < D && y >= 0 && y < D && z >= 0 && z < D) {
+          const int64_t nb = gv + dx + (int64_t)D * (dy + (int64_t)D * dz);
+          val = b2f(X[nb * ldx + offx + ci]);
+        }
+      }
+      Xs[e] = val;
+    }
+    for (int e = threadIdx.x; e < WG_TILE * Cout; e += 256) {
+      const int r = e / Cout, co = e - r * Cout;
+      const int64_t gv = t0 + r;
+      Ys[e] = gv < total ? b2f(dY[gv * ldy + offy + co]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int o = threadIdx.x + 256 * e;
+      if (o < no) {
+        const int ci = o / Cout, co = o - ci * Cout;
+        float s = acc[e];
+        for (int r = 0; r < WG_TILE; ++r) s = fmaf(Xs[r * Cin + ci], Ys[r * Cout + co], s);
+        acc[e] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int o = threadIdx.x + 256 * e;
+    if (o < no) part[((int64_t)blockIdx.x * 27 + tap) * no + o] = acc[e];
+  }
+}
+
+// g[i] = sum over chunks of part[chunk][i] (fixed order), i < n.
+__global__ void k_sum_chunks(int nchunk, int64_t n, const float* __restrict__ part, float* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + i];
+  g[i] = s;
+}
+
+// Bias gradient: db[co] = sum_v dY[v][co], one workgroup per channel.
+__global__ __launch_bounds__(256) void k_bias_grad(int64_t total, int Cout, const bf16* __restrict__ dY, int ldy,
+                                                   int offy, float* __restrict__ db) {
+  __shared__ float red[256];
+  const int co = blockIdx.x;
+  float s = 0.f;
+  for (int64_t v = threadIdx.x; v < total; v += 256) s += b2f(dY[v * ldy + offy + co]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[co] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Pooling, upsampling, skip gradients (channels last, slices of wider buffers)
+// ---------------------------------------------------------------------------
+__global__ void k_pool2(int B, int D, int C, const bf16* __restrict__ in, int ldi, int offi, bf16* __restrict__ out,
+                        int ldo) {
+  const int d = D / 2;
+  const int64_t Vd = (int64_t)d * d * d;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * Vd * C) return;
+  const int c = (int)(t % C);
+  const int64_t bv = t / C, b = bv / Vd, v = bv % Vd;
+  const int x = (int)(v % d), y = (int)((v / d) % d), z = (int)(v / ((int64_t)d * d));
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t iv = (2 * x + (k & 1)) + (int64_t)D * ((2 * y + ((k >> 1) & 1)) + (int64_t)D * (2 * z + (k >> 2)));
+    s += b2f(in[(b * D * D * D + iv) * ldi + offi + c]);
+  }
+  out[bv * ldo + c] = f2bf(0.125f * s);
+}
+
+// out slice [B][(2d)^3][C] at (ldo, offo) = nearest upsampling of in [B][d^3][C]
+__global__ void k_up2(int B, int d, int C, const bf16* __restrict__ in, bf16* __restrict__ out, int ldo, int offo) {
+  const int D = 2 * d;
+  const int64_t VD = (int64_t)D * D * D;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * VD * C) return;
+  const int c = (int)(t % C);
+  const int64_t bv = t / C, b = bv / VD, v = bv % VD;
+  const int x = (int)(v % D), y = (int)((v / D) % D), z = (int)(v / ((int64_t)D * D));
+  const int64_t iv = (x / 2) + (int64_t)d * ((y / 2) + (int64_t)d * (z / 2));
+  out[bv * ldo + offo + c] = in[(b * d * d * d + iv) * C + c];
+}
+
+// out [B][d^3][C] = (sum over the 8 children of the gradient slice) masked
+// by (act > 0) where act is [B][d^3][C].
+__global__ void k_up2_bwd(int B, int d, int C, const bf16* __restrict__ g, int ldg, int offg,
+                          const bf16* __restrict__ act, bf16* __restrict__ out) {
+  const int D = 2 * d;
+  const int64_t Vd = (int64_t)d * d * d;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * Vd * C) return;
+  const int c = (int)(t % C);
+  const int64_t bv = t / C, b = bv / Vd, v = bv % Vd;
+  const int x = (int)(v % d), y = (int)((v / d) % d), z = (int)(v / ((int64_t)d * d));
+  float s = 0.f;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t iv = (2 * x + (k & 1)) + (int64_t)D * ((2 * y + ((k >> 1) & 1)) + (int64_t)D * (2 * z + (k >> 2)));
+    s += b2f(g[(b * D * D * D + iv) * ldg + offg + c]);
+  }
+  if (!(b2f(act[bv * C + c]) > 0.f)) s = 0.f;
+  out[bv * C + c] = f2bf(s);
+}
+
+// Gradient of a skip activation s (= a slice of a concat buffer): the
+// decoder's slice gradient plus 1/8 of the pooled gradient of its parent,
+// masked by (s > 0). out [B][D^3][C].
+__global__ void k_skip_grad(int B, int D, int C, const bf16* __restrict__ gcat, int ldc, int offc,
+                            const bf16* __restrict__ gpool, const bf16* __restrict__ s, int lds, int offs,
+                            bf16* __restrict__ out) {
+  const int d = D / 2;
+  const int64_t VD = (int64_t)D * D * D;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * VD * C) return;
+  const int c = (int)(t % C);
+  const int64_t bv = t / C, b = bv / VD, v = bv % VD;
+  const int x = (int)(v % D), y = (int)((v / D) % D), z = (int)(v / ((int64_t)D * D));
+  const int64_t pv = (x / 2) + (int64_t)d * ((y / 2) + (int64_t)d * (z / 2));
+  float r = b2f(gcat[bv * ldc + offc + c]) + 0.125f * b2f(gpool[(b * d * d * d + pv) * C + c]);
+  if (!(b2f(s[bv * lds + offs + c]) > 0.f)) r = 0.f;
+  out[bv * C + c] = f2bf(r);
+}
+
+// ---------------------------------------------------------------------------
+// 1x1 head (16 -> 2, linear, FP32 output) and its backward
+// ---------------------------------------------------------------------------
+__global__ void k_head_fwd(int64_t total, const bf16* __restrict__ a, const float* __restrict__ W,
+                           const float* __restrict__ b, float* __restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  float o0 = b[0], o1 = b[1];
+  for (int ci = 0; ci < 16; ++ci) {
+    const float x = b2f(a[v * 16 + ci]);
+    o0 = fmaf(x, W[ci * 2 + 0], o0);
+    o1 = fmaf(x, W[ci * 2 + 1], o1);
+  }
+  out[v * 2 + 0] = o0;
+  out[v * 2 + 1] = o1;
+}
+
+// ga[v][ci] = (sum_co W[ci][co] dout[v][co]) masked by a > 0; partial head
+// weight gradients per workgroup: part[blk][0..31] = sum a*dout, [32..33] = sum dout.
+__global__ __launch_bounds__(256) void k_head_bwd(int64_t total, const bf16* __restrict__ a,
+                                                  const float* __restrict__ W, const float* __restrict__ dout,
+                                                  bf16* __restrict__ ga, float* __restrict__ part) {
+  __shared__ float red[256];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float g0 = 0.f, g1 = 0.f;
+  float xs[16];
+  if (v < total) {
+    g0 = dout[v * 2 + 0];
+    g1 = dout[v * 2 + 1];
+    for (int ci = 0; ci < 16; ++ci) {
+      const float x = b2f(a[v * 16 + ci]);
+      xs[ci] = x;
+      const float g = W[ci * 2] * g0 + W[ci * 2 + 1] * g1;
+      ga[v * 16 + ci] = f2bf(x > 0.f ? g : 0.f);
+    }
+  } else {
+    for (int ci = 0; ci < 16; ++ci) xs[ci] = 0.f;
+  }
+  for (int e = 0; e < 34; ++e) {
+    float val;
+    if (e < 32) val = xs[e / 2] * ((e & 1) ? g1 : g0);
+    else val = (e == 32) ? g0 : g1;
+    red[threadIdx.x] = val;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 34 + e] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Loss: per sample num = sum_mask |out - t|^2, den = sum_mask |t|^2;
+// dout = mask ? 2 (out - t) / den / B : 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss_sums(int64_t V, const float* __restrict__ out,
+                                                   const float* __restrict__ tgt, const uint8_t* __restrict__ mask,
+                                                   float* __restrict__ numden) {
+  __shared__ float rn[256], rd[256];
+  const int s = blockIdx.x;
+  float n = 0.f, d = 0.f;
+  for (int64_t v = threadIdx.x; v < V; v += 256) {
+    if (!mask[v]) continue;
+    const int64_t i = ((int64_t)s * V + v) * 2;
+    const float e0 = out[i] - tgt[i], e1 = out[i + 1] - tgt[i + 1];
+    n += e0 * e0 + e1 * e1;
+    d += tgt[i] * tgt[i] + tgt[i + 1] * tgt[i + 1];
+  }
+  rn[threadIdx.x] = n;
+  rd[threadIdx.x] = d;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    numden[2 * s] = rn[0];
+    numden[2 * s + 1] = rd[0];
+  }
+}
+
+__global__ void k_loss_grad(int B, int64_t V, const float* __restrict__ out, const float* __restrict__ tgt,
+                            const uint8_t* __restrict__ mask, const float* __restrict__ numden,
+                            float* __restrict__ dout) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * V) return;
+  const int64_t s = t / V, v = t % V;
+  const float den = numden[2 * s + 1];
+  const float f = (mask[v] && den > 0.f) ? 2.f / den / B : 0.f;
+  dout[2 * t] = f * (out[2 * t] - tgt[2 * t]);
+  dout[2 * t + 1] = f * (out[2 * t + 1] - tgt[2 * t + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// Parameters: FP32 master (oracle packing), BF16 working layouts, Adam.
+// ---------------------------------------------------------------------------
+// Wf[t][co][ci] (forward) and Wb[t][ci][co] (backward data) from W[t][ci][co].
+__global__ void k_wpack(int Cin, int Cout, const float* __restrict__ W, bf16* __restrict__ Wf, bf16* __restrict__ Wb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 27LL * Cin * Cout) return;
+  const int co = (int)(t % Cout);
+  const int64_t r = t / Cout;
+  const int ci = (int)(r % Cin), tap = (int)(r / Cin);
+  const bf16 w = f2bf(W[t]);
+  Wb[t] = w;
+  Wf[((int64_t)tap * Cout + co) * Cin + ci] = w;
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Glue with the solver: coarse fields [Nc][P] <-> network volumes. The
+// unknown (x, y, z) of the nx x ny x nz coarsest grid sits at voxel (x, y, z)
+// of the D^3 volume; the rest of the volume is padding (input 0).
+// ---------------------------------------------------------------------------
+struct Box {
+  int nx, ny, nz;
+};
+
+__device__ inline int64_t box_index(const Box& b, int D, int64_t v) {
+  const int x = (int)(v % D), y = (int)((v / D) % D), z = (int)(v / ((int64_t)D * D));
+  if (x >= b.nx || y >= b.ny || z >= b.nz) return -1;
+  return x + (int64_t)b.nx * (y + (int64_t)b.ny * z);
+}
+
+__device__ inline uint2 pack_in(float a, float b, float c, float d) {
+  return uint2{(uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16), (uint32_t)f2bf(c) | ((uint32_t)f2bf(d) << 16)};
+}
+
+// Sample b < nb of x0 = (Re, Im of f[n][c0 + b] sc[c0 + b], Re, Im of dgn[n]).
+template <class S>
+__global__ void k_net_input(int P, int c0, int nb, int D, Box bx, const S* __restrict__ f,
+                            const double* __restrict__ sc, const float* __restrict__ dgn, bf16* __restrict__ x0) {
+  const int64_t V = (int64_t)D * D * D;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nb * V) return;
+  const int c = c0 + (int)(t / V);
+  const int64_t n = box_index(bx, D, t % V);
+  uint2 w{0u, 0u};
+  if (n >= 0) {
+    const S fv = f[n * P + c];
+    const float s = (float)sc[c];
+    w = pack_in((float)fv.re * s, (float)fv.im * s, dgn[2 * n], dgn[2 * n + 1]);
+  }
+  reinterpret_cast<uint2*>(x0)[t] = w;
+}
+
+// e[n][c0 + b] = os[c0 + b] (out[b][v][0] + i out[b][v][1]); counts
+// non-finite outputs in *bad.
+template <class S>
+__global__ void k_net_output(int P, int c0, int nb, int D, Box bx, const float* __restrict__ out,
+                             const double* __restrict__ os, S* __restrict__ e, int* __restrict__ bad) {
+  const int64_t Nc = (int64_t)bx.nx * bx.ny * bx.nz;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Nc * nb) return;
+  const int64_t n = t / nb;
+  const int b = (int)(t % nb);
+  const int x = (int)(n % bx.nx), y = (int)((n / bx.nx) % bx.ny), z = (int)(n / ((int64_t)bx.nx * bx.ny));
+  const int64_t v = (int64_t)b * D * D * D + x + (int64_t)D * (y + (int64_t)D * z);
+  const float o0 = out[2 * v], o1 = out[2 * v + 1];
+  if (!isfinite(o0) || !isfinite(o1)) atomicAdd(bad, 1);
+  using E = decltype(e->re);
+  e[n * P + c0 + b] = S{(E)(os[c0 + b] * o0), (E)(os[c0 + b] * o1)};
+}
+
+// Training pair of column c into pool slot `slot`: input as k_net_input and
+// target e / (H^2 rms) (FP32, 0 in the padding).
+template <class S>
+__global__ void k_capture(int P, int c, int D, Box bx, const S* __restrict__ f, const S* __restrict__ e,
+                          const double* __restrict__ sc, double h2inv, const float* __restrict__ dgn, int64_t slot,
+                          bf16* __restrict__ xs, float* __restrict__ ts) {
+  const int64_t V = (int64_t)D * D * D;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int64_t n = box_index(bx, D, v);
+  uint2 w{0u, 0u};
+  float t0 = 0.f, t1 = 0.f;
+  if (n >= 0) {
+    const S fv = f[n * P + c], ev = e[n * P + c];
+    const float s = (float)sc[c];
+    w = pack_in((float)fv.re * s, (float)fv.im * s, dgn[2 * n], dgn[2 * n + 1]);
+    t0 = (float)((double)ev.re * sc[c] * h2inv);
+    t1 = (float)((double)ev.im * sc[c] * h2inv);
+  }
+  reinterpret_cast<uint2*>(xs)[slot * V + v] = w;
+  ts[2 * (slot * V + v)] = t0;
+  ts[2 * (slot * V + v) + 1] = t1;
+}
+
+// dgn[n] = H^2 (centre coefficient of the coarsest stencil) as FP32 pairs.
+__global__ void k_net_dgn(int64_t N, int NS, const c128* __restrict__ st, double h2, float* __restrict__ dgn) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const c128 a = st[n * NS + NS / 2];
+  dgn[2 * n] = (float)(h2 * a.re);
+  dgn[2 * n + 1] = (float)(h2 * a.im);
+}
+
+// mask[v] = 1 on voxels that hold an unknown.
+__global__ void k_net_mask(int D, Box bx, uint8_t* __restrict__ mask) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (int64_t)D * D * D) return;
+  mask[v] = box_index(bx, D, v) >= 0 ? 1 : 0;
+}
+
+// sc[c] = 1/rms (0 for a zero column), os[c] = H^2 rms, from ||f_c||^2.
+__global__ void k_net_scales(int P, int64_t Nc, double h2, const double* __restrict__ n2, double* __restrict__ sc,
+                             double* __restrict__ os) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  const double rms = sqrt(n2[c] / (double)Nc);
+  sc[c] = rms > 0.0 ? 1.0 / rms : 0.0;
+  os[c] = h2 * rms;
+}
+
+// Minibatch sample b = pool entry idx[b] with its residual and target turned
+// by the unit phase rot[b] = (cos, sin): the exact coarsest solve commutes
+// with that rotation, so every phase is a valid training pair.
+__global__ void k_gather_samples(int nb, const int* __restrict__ idx, const float* __restrict__ rot, int64_t V,
+                                 const bf16* __restrict__ xs, const float* __restrict__ ts, bf16* __restrict__ x0,
+                                 float* __restrict__ tgt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nb * V) return;
+  const int b = (int)(t / V);
+  const int64_t v = t % V;
+  const int64_t src = (int64_t)idx[b] * V + v;
+  const float cs = rot[2 * b], sn = rot[2 * b + 1];
+  const uint2 w = reinterpret_cast<const uint2*>(xs)[src];
+  const float xr = b2f((bf16)(w.x & 0xffffu)), xi = b2f((bf16)(w.x >> 16));
+  const float yr = cs * xr - sn * xi, yi = sn * xr + cs * xi;
+  reinterpret_cast<uint2*>(x0)[t] = uint2{(uint32_t)f2bf(yr) | ((uint32_t)f2bf(yi) << 16), w.y};
+  const float tr = ts[2 * src], ti = ts[2 * src + 1];
+  tgt[2 * t] = cs * tr - sn * ti;
+  tgt[2 * t + 1] = sn * tr + cs * ti;
+}
+
+// loss = (1/B) sum over samples with den > 0 of num / den.
+__global__ void k_loss_value(int B, const float* __restrict__ numden, float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float l = 0.f;
+  for (int s = 0; s < B; ++s)
+    if (numden[2 * s + 1] > 0.f) l += numden[2 * s] / numden[2 * s + 1];
+  *loss = l / B;
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+__global__ void k_f32_to_bf16(int64_t n, const float* __restrict__ a, bf16* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = f2bf(a[i]);
+}
+
+__global__ void k_bf16_to_f32(int64_t n, const bf16* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = b2f(a[i]);
+}
+
+static inline dim3 g1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+struct Net {
+  int D = 0, Bmax = 0;
+  int64_t V = 0;
+  int64_t np = 0;
+  float* p = nullptr;   // FP32 master parameters, packed as the oracle packs them
+  float* g = nullptr;   // gradient
+  float* am = nullptr;  // Adam moments
+  float* av = nullptr;
+  int64_t adam_t = 0;
+  void* wmem = nullptr;
+  bf16* Wf[NLAYER] = {};
+  bf16* Wb[NLAYER] = {};
+  // activations (channels last, BF16) for Bmax samples
+  void* amem = nullptr;
+  bf16 *x0 = nullptr, *a1 = nullptr, *c1 = nullptr, *p1 = nullptr, *a2 = nullptr, *c2 = nullptr, *p2 = nullptr,
+       *a4 = nullptr, *a5 = nullptr, *a6 = nullptr, *a7 = nullptr, *a8 = nullptr, *a9 = nullptr;
+  float* out = nullptr;
+  float* numden = nullptr;
+  float* lossd = nullptr;
+  // backward buffers (allocated on first use)
+  void* bmem = nullptr;
+  float *dout = nullptr, *tgt = nullptr, *wpart = nullptr, *hpart = nullptr;
+  bf16 *g9 = nullptr, *g8 = nullptr, *gc1 = nullptr, *g7 = nullptr, *g6 = nullptr, *gc2 = nullptr, *g5 = nullptr,
+       *g4 = nullptr, *gp2 = nullptr, *g3 = nullptr, *g2 = nullptr, *gp1 = nullptr, *g1 = nullptr, *g0 = nullptr;
+  int* idx = nullptr;
+  float* rot = nullptr;
+  float* hist = nullptr;
+  int hist_n = 0;
+  // binding to a coarsest grid
+  bool bound = false;
+  Box box{0, 0, 0};
+  int64_t Nc = 0;
+  double H2 = 1.0;
+  Prec pf = P64;
+  float* dgn = nullptr;
+  uint8_t* mask = nullptr;
+  double* n2 = nullptr;  // [Pmax] column norms^2, then scales
+  double* sc = nullptr;
+  double* os = nullptr;
+  c128* part = nullptr;
+  c128* Gs = nullptr;
+  int Pmax = 0;
+  int* bad = nullptr;
+  int* hbad = nullptr;     // pinned
+  double* hn2 = nullptr;   // pinned [Pmax]
+  // pool of training pairs
+  int cap_max = 0, cap_n = 0;
+  int64_t cap_seen = 0;
+  bf16* xs = nullptr;
+  float* ts = nullptr;
+  std::mt19937_64 rng{12345};
+};
+
+#define LCHECK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? HELM_ERR_OOM : HELM_ERR_DEVICE, "network: %s: %s", #expr, \
+                  hipGetErrorString(e_));                                                              \
+  } while (0)
+
+static size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+int64_t nparams() { return nparams_total(); }
+
+int edge_for(const Coarse& g) {
+  const int m = std::max(g.nu[0], std::max(g.nu[1], g.nu[2]));
+  return (m + 3) / 4 * 4;
+}
+
+static void pack_weights(Net* n, hipStream_t s) {
+  for (int l = 0; l < NLAYER; ++l) {
+    const int64_t nw = 27LL * L_CIN[l] * L_COUT[l];
+    hipLaunchKernelGGL(k_wpack, g1(nw), dim3(256), 0, s, L_CIN[l], L_COUT[l], n->p + layer_off(l), n->Wf[l], n->Wb[l]);
+  }
+}
+
+helm_status create(int D, int max_batch, uint64_t seed, hipStream_t s, Net** out) {
+  *out = nullptr;
+  if (D < 4 || D % 4 != 0 || D > 256) return fail(HELM_ERR_INVALID_ARG, "network edge D=%d must be a multiple of 4 in 4..256", D);
+  if (max_batch < 1 || max_batch > 1024) return fail(HELM_ERR_INVALID_ARG, "max_batch must be 1..1024");
+  Net* n = new Net();
+  n->D = D;
+  n->Bmax = max_batch;
+  n->V = (int64_t)D * D * D;
+  n->np = nparams_total();
+  auto bail = [&](helm_status st) {
+    destroy(n);
+    return st;
+  };
+  const size_t pb = al(4 * (size_t)n->np);
+  if (hipMalloc(&n->p, 4 * pb) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network parameters"));
+  n->g = n->p + pb / 4;
+  n->am = n->g + pb / 4;
+  n->av = n->am + pb / 4;
+  int64_t nw = 0;
+  for (int l = 0; l < NLAYER; ++l) nw += al(2 * 27LL * L_CIN[l] * L_COUT[l]);
+  if (hipMalloc(&n->wmem, 2 * nw) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network weights"));
+  char* w = static_cast<char*>(n->wmem);
+  for (int l = 0; l < NLAYER; ++l) {
+    const size_t b = al(2 * 27LL * L_CIN[l] * L_COUT[l]);
+    n->Wf[l] = reinterpret_cast<bf16*>(w);
+    n->Wb[l] = reinterpret_cast<bf16*>(w + b);
+    w += 2 * b;
+  }
+  // activations
+  const int64_t BV = (int64_t)max_batch * n->V, BV2 = BV / 8, BV4 = BV / 64;
+  const size_t sizes[] = {al(2 * BV * 4),   al(2 * BV * 16),  al(2 * BV * 48),  al(2 * BV2 * 16), al(2 * BV2 * 32),
+                          al(2 * BV2 * 96), al(2 * BV4 * 32), al(2 * BV4 * 64), al(2 * BV4 * 64), al(2 * BV2 * 32),
+                          al(2 * BV2 * 32), al(2 * BV * 16),  al(2 * BV * 16),  al(4 * BV * 2),   al(8 * (size_t)max_batch),
+                          al(4)};
+  size_t tot = 0;
+  for (size_t b : sizes) tot += b;
+  if (hipMalloc(&n->amem, tot) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network activations (%zu bytes)", tot));
+  char* a = static_cast<char*>(n->amem);
+  void** slots[] = {(void**)&n->x0, (void**)&n->a1, (void**)&n->c1, (void**)&n->p1, (void**)&n->a2, (void**)&n->c2,
+                    (void**)&n->p2, (void**)&n->a4, (void**)&n->a5, (void**)&n->a6, (void**)&n->a7, (void**)&n->a8,
+                    (void**)&n->a9, (void**)&n->out, (void**)&n->numden, (void**)&n->lossd};
+  for (size_t k = 0; k < sizeof(sizes) / sizeof(sizes[0]); ++k) {
+    *slots[k] = a;
+    a += sizes[k];
+  }
+  if (hipHostMalloc(&n->hbad, sizeof(int)) != hipSuccess) return bail(fail(HELM_ERR_OOM, "pinned host memory"));
+  // He-scaled initial weights, zero biases
+  std::vector<float> h(n->np, 0.f);
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<float> nd(0.f, 1.f);
+  for (int l = 0; l < NLAYER; ++l) {
+    const float sd = std::sqrt(2.f / (27.f * L_CIN[l]));
+    const int64_t o = layer_off(l);
+    for (int64_t k = 0; k < 27LL * L_CIN[l] * L_COUT[l]; ++k) h[o + k] = sd * nd(rng);
+  }
+  for (int k = 0; k < 32; ++k) h[n->np - 34 + k] = 0.25f * nd(rng);
+  helm_status st = set_params(n, h.data(), s);
+  if (st != HELM_OK) return bail(st);
+  *out = n;
+  return HELM_OK;
+}
+
+void destroy(Net* n) {
+  if (!n) return;
+  hipDeviceSynchronize();
+  hipFree(n->p);
+  hipFree(n->wmem);
+  hipFree(n->amem);
+  hipFree(n->bmem);
+  hipFree(n->idx);
+  hipFree(n->rot);
+  hipFree(n->hist);
+  hipFree(n->dgn);
+  hipFree(n->mask);
+  hipFree(n->n2);
+  hipFree(n->part);
+  hipFree(n->xs);
+  hipFree(n->ts);
+  if (n->hbad) hipHostFree(n->hbad);
+  if (n->hn2) hipHostFree(n->hn2);
+  delete n;
+}
+
+helm_status set_params(Net* n, const float* host, hipStream_t s) {
+  for (int64_t k = 0; k < n->np; ++k)
+    if (!std::isfinite(host[k])) return fail(HELM_ERR_NONFINITE, "network parameter %lld is not finite", (long long)k);
+  LCHECK(hipMemcpyAsync(n->p, host, 4 * n->np, hipMemcpyHostToDevice, s));
+  LCHECK(hipMemsetAsync(n->am, 0, 4 * n->np, s));
+  LCHECK(hipMemsetAsync(n->av, 0, 4 * n->np, s));
+  n->adam_t = 0;
+  pack_weights(n, s);
+  LCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
+helm_status get_params(Net* n, float* host, hipStream_t s) {
+  LCHECK(hipMemcpyAsync(host, n->p, 4 * n->np, hipMemcpyDeviceToHost, s));
+  LCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
+size_t blob_bytes() { return 16 + 4 * (size_t)nparams_total(); }
+
+helm_status write_blob(Net* n, void* blob, hipStream_t s) {
+  char* b = static_cast<char*>(blob);
+  std::memcpy(b, "HNET", 4);
+  const uint32_t ver = 1;
+  const int64_t np = n->np;
+  std::memcpy(b + 4, &ver, 4);
+  std::memcpy(b + 8, &np, 8);
+  return get_params(n, reinterpret_cast<float*>(b + 16), s);
+}
+
+helm_status read_blob(const void* blob, size_t bytes, float* params) {
+  const char* b = static_cast<const char*>(blob);
+  if (!blob || bytes < 16 || std::memcmp(b, "HNET", 4) != 0) return fail(HELM_ERR_INVALID_ARG, "network blob: bad header");
+  uint32_t ver;
+  int64_t np;
+  std::memcpy(&ver, b + 4, 4);
+  std::memcpy(&np, b + 8, 8);
+  if (ver != 1 || np != nparams_total() || bytes != blob_bytes())
+    return fail(HELM_ERR_INVALID_ARG, "network blob: version %u, %lld parameters, %zu bytes (expected 1, %lld, %zu)", ver,
+                (long long)np, bytes, (long long)nparams_total(), blob_bytes());
+  std::memcpy(params, b + 16, 4 * (size_t)np);
+  return HELM_OK;
+}
+
+// ---- passes -----------------------------------------------------------------
+static void conv_fwd(Net* n, int l, int B, int D, const bf16* in, int ldi, int offi, bf16* out, int ldo, int offo,
+                     hipStream_t s) {
+  ConvArgs a{};
+  a.B = B;
+  a.D = D;
+  a.Cin = L_CIN[l];
+  a.N = L_COUT[l];
+  a.in = in;
+  a.ldi = ldi;
+  a.offi = offi;
+  a.W = n->Wf[l];
+  a.bias = n->p + layer_off(l) + 27LL * L_CIN[l] * L_COUT[l];
+  a.out = out;
+  a.ldo = ldo;
+  a.offo = offo;
+  a.flip = 0;
+  a.relu = 1;
+  conv3(a, s);
+}
+
+// gx = (adjoint of layer l's convolution) dy, optionally masked by act > 0.
+static void conv_bwd_data(Net* n, int l, int B, int D, const bf16* dy, bf16* gx, int ldx, const bf16* act,
+                          hipStream_t s) {
+  ConvArgs a{};
+  a.B = B;
+  a.D = D;
+  a.Cin = L_COUT[l];
+  a.N = L_CIN[l];
+  a.in = dy;
+  a.ldi = L_COUT[l];
+  a.offi = 0;
+  a.W = n->Wb[l];
+  a.bias = nullptr;
+  a.out = gx;
+  a.ldo = ldx;
+  a.offo = 0;
+  a.flip = 1;
+  a.relu = 0;
+  a.mask = act;
+  a.ldm = L_CIN[l];
+  a.offm = 0;
+  conv3(a, s);
+}
+
+static void conv_bwd_weight(Net* n, int l, int B, int D, const bf16* x, int ldx, int offx, const bf16* dy,
+                            hipStream_t s) {
+  const int Cin = L_CIN[l], Cout = L_COUT[l];
+  const int64_t total = (int64_t)B * D * D * D;
+  const int nchunk = (int)((total + WG_CHUNK - 1) / WG_CHUNK);
+  const size_t lds = sizeof(float) * WG_TILE * (Cin + Cout);
+  hipLaunchKernelGGL(k_wgrad_part, dim3(nchunk, 27), dim3(256), lds, s, B, D, Cin, Cout, x, ldx, offx, dy, Cout, 0,
+                     n->wpart);
+  const int64_t nw = 27LL * Cin * Cout;
+  float* gW = n->g + layer_off(l);
+  hipLaunchKernelGGL(k_sum_chunks, g1(nw), dim3(256), 0, s, nchunk, nw, (const float*)n->wpart, gW);
+  hipLaunchKernelGGL(k_bias_grad, dim3(Cout), dim3(256), 0, s, total, Cout, dy, Cout, 0, gW + nw);
+}
+
+static void run_forward(Net* n, int B, hipStream_t s) {
+  const int D = n->D, d2 = D / 2, d4 = D / 4;
+  const int64_t BV = (int64_t)B * n->V;
+  conv_fwd(n, 0, B, D, n->x0, 4, 0, n->a1, 16, 0, s);
+  conv_fwd(n, 1, B, D, n->a1, 16, 0, n->c1, 48, 32, s);  // s1 -> second slice of c1
+  hipLaunchKernelGGL(k_pool2, g1(BV / 8 * 16), dim3(256), 0, s, B, D, 16, (const bf16*)n->c1, 48, 32, n->p1, 16);
+  conv_fwd(n, 2, B, d2, n->p1, 16, 0, n->a2, 32, 0, s);
+  conv_fwd(n, 3, B, d2, n->a2, 32, 0, n->c2, 96, 64, s);  // s2 -> second slice of c2
+  hipLaunchKernelGGL(k_pool2, g1(BV / 64 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->c2, 96, 64, n->p2, 32);
+  conv_fwd(n, 4, B, d4, n->p2, 32, 0, n->a4, 64, 0, s);
+  conv_fwd(n, 5, B, d4, n->a4, 64, 0, n->a5, 64, 0, s);
+  hipLaunchKernelGGL(k_up2, g1(BV / 8 * 64), dim3(256), 0, s, B, d4, 64, (const bf16*)n->a5, n->c2, 96, 0);
+  conv_fwd(n, 6, B, d2, n->c2, 96, 0, n->a6, 32, 0, s);
+  conv_fwd(n, 7, B, d2, n->a6, 32, 0, n->a7, 32, 0, s);
+  hipLaunchKernelGGL(k_up2, g1(BV * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->a7, n->c1, 48, 0);
+  conv_fwd(n, 8, B, D, n->c1, 48, 0, n->a8, 16, 0, s);
+  conv_fwd(n, 9, B, D, n->a8, 16, 0, n->a9, 16, 0, s);
+  hipLaunchKernelGGL(k_head_fwd, g1(BV), dim3(256), 0, s, BV, (const bf16*)n->a9, (const float*)(n->p + n->np - 34),
+                     (const float*)(n->p + n->np - 2), n->out);
+}
+
+static helm_status ensure_backward(Net* n) {
+  if (n->bmem) return HELM_OK;
+  const int64_t BV = (int64_t)n->Bmax * n->V, BV2 = BV / 8, BV4 = BV / 64;
+  int64_t wp = 0;
+  const int64_t vox[3] = {BV, BV2, BV4};
+  const int lev[NLAYER] = {0, 0, 1, 1, 2, 2, 1, 1, 0, 0};
+  for (int l = 0; l < NLAYER; ++l) {
+    const int64_t nch = (vox[lev[l]] + WG_CHUNK - 1) / WG_CHUNK;
+    wp = std::max<int64_t>(wp, nch * 27 * L_CIN[l] * L_COUT[l]);
+  }
+  const int64_t hblk = (BV + 255) / 256;
+  const size_t sizes[] = {al(4 * BV * 2),    al(4 * BV * 2),    al(4 * (size_t)wp), al(4 * hblk * 34),
+                          al(2 * BV * 16),   al(2 * BV * 16),   al(2 * BV * 48),    al(2 * BV2 * 32),
+                          al(2 * BV2 * 32),  al(2 * BV2 * 96),  al(2 * BV4 * 64),   al(2 * BV4 * 64),
+                          al(2 * BV4 * 32),  al(2 * BV2 * 32),  al(2 * BV2 * 32),   al(2 * BV2 * 16),
+                          al(2 * BV * 16),   al(2 * BV * 16)};
+  size_t tot = 0;
+  for (size_t b : sizes) tot += b;
+  if (hipMalloc(&n->bmem, tot) != hipSuccess) return fail(HELM_ERR_OOM, "network gradients (%zu bytes)", tot);
+  char* a = static_cast<char*>(n->bmem);
+  void** slots[] = {(void**)&n->dout, (void**)&n->tgt, (void**)&n->wpart, (void**)&n->hpart, (void**)&n->g9,
+                    (void**)&n->g8,   (void**)&n->gc1, (void**)&n->g7,    (void**)&n->g6,    (void**)&n->gc2,
+                    (void**)&n->g5,   (void**)&n->g4,  (void**)&n->gp2,   (void**)&n->g3,    (void**)&n->g2,
+                    (void**)&n->gp1,  (void**)&n->g1,  (void**)&n->g0};
+  for (size_t k = 0; k < sizeof(sizes) / sizeof(sizes[0]); ++k) {
+    *slots[k] = a;
+    a += sizes[k];
+  }
+  return HELM_OK;
+}
+
+// Loss of the forward output against n->tgt on `mask`, gradient into n->g.
+static void run_loss_backward(Net* n, int B, const uint8_t* mask, float* loss_dst, hipStream_t s) {
+  const int D = n->D, d2 = D / 2, d4 = D / 4;
+  const int64_t BV = (int64_t)B * n->V;
+  hipLaunchKernelGGL(k_loss_sums, dim3(B), dim3(256), 0, s, n->V, (const float*)n->out, (const float*)n->tgt, mask,
+                     n->numden);
+  hipLaunchKernelGGL(k_loss_value, dim3(1), dim3(64), 0, s, B, (const float*)n->numden, loss_dst);
+  hipLaunchKernelGGL(k_loss_grad, g1(BV), dim3(256), 0, s, B, n->V, (const float*)n->out, (const float*)n->tgt, mask,
+                     (const float*)n->numden, n->dout);
+  // head
+  const int64_t hblk = (BV + 255) / 256;
+  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)hblk), dim3(256), 0, s, BV, (const bf16*)n->a9,
+                     (const float*)(n->p + n->np - 34), (const float*)n->dout, n->g9, n->hpart);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(64), 0, s, (int)hblk, (int64_t)34, (const float*)n->hpart,
+                     n->g + n->np - 34);
+  // decoder, full resolution
+  conv_bwd_weight(n, 9, B, D, n->a8, 16, 0, n->g9, s);
+  conv_bwd_data(n, 9, B, D, n->g9, n->g8, 16, n->a8, s);
+  conv_bwd_weight(n, 8, B, D, n->c1, 48, 0, n->g8, s);
+  conv_bwd_data(n, 8, B, D, n->g8, n->gc1, 48, nullptr, s);
+  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 8 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc1, 48, 0,
+                     (const bf16*)n->a7, n->g7);
+  // decoder, half resolution
+  conv_bwd_weight(n, 7, B, d2, n->a6, 32, 0, n->g7, s);
+  conv_bwd_data(n, 7, B, d2, n->g7, n->g6, 32, n->a6, s);
+  conv_bwd_weight(n, 6, B, d2, n->c2, 96, 0, n->g6, s);
+  conv_bwd_data(n, 6, B, d2, n->g6, n->gc2, 96, nullptr, s);
+  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 64 * 64), dim3(256), 0, s, B, d4, 64, (const bf16*)n->gc2, 96, 0,
+                     (const bf16*)n->a5, n->g5);
+  // bottom
+  conv_bwd_weight(n, 5, B, d4, n->a4, 64, 0, n->g5, s);
+  conv_bwd_data(n, 5, B, d4, n->g5, n->g4, 64, n->a4, s);
+  conv_bwd_weight(n, 4, B, d4, n->p2, 32, 0, n->g4, s);
+  conv_bwd_data(n, 4, B, d4, n->g4, n->gp2, 32, nullptr, s);
+  // encoder, half resolution: s2 feeds the pool and the skip
+  hipLaunchKernelGGL(k_skip_grad, g1(BV / 8 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc2, 96, 64,
+                     (const bf16*)n->gp2, (const bf16*)n->c2, 96, 64, n->g3);
+  conv_bwd_weight(n, 3, B, d2, n->a2, 32, 0, n->g3, s);
+  conv_bwd_data(n, 3, B, d2, n->g3, n->g2, 32, n->a2, s);
+  conv_bwd_weight(n, 2, B, d2, n->p1, 16, 0, n->g2, s);
+  conv_bwd_data(n, 2, B, d2, n->g2, n->gp1, 16, nullptr, s);
+  // encoder, full resolution: s1 feeds the pool and the skip
+  hipLaunchKernelGGL(k_skip_grad, g1(BV * 16), dim3(256), 0, s, B, D, 16, (const bf16*)n->gc1, 48, 32,
+                     (const bf16*)n->gp1, (const bf16*)n->c1, 48, 32, n->g1);
+  conv_bwd_weight(n, 1, B, D, n->a1, 16, 0, n->g1, s);
+  conv_bwd_data(n, 1, B, D, n->g1, n->g0, 16, n->a1, s);
+  conv_bwd_weight(n, 0, B, D, n->x0, 4, 0, n->g0, s);
+}
+
+helm_status forward(Net* n, int B, const float* x, float* out, hipStream_t s) {
+  if (B < 1 || B > n->Bmax) return fail(HELM_ERR_INVALID_ARG, "batch %d outside 1..%d", B, n->Bmax);
+  if (!x || !out) return fail(HELM_ERR_INVALID_ARG, "null buffer");
+  const int64_t BV = (int64_t)B * n->V;
+  hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
+  run_forward(n, B, s);
+  LCHECK(hipMemcpyAsync(out, n->out, 8 * BV, hipMemcpyDeviceToDevice, s));
+  LCHECK(hipStreamSynchronize(s));
+  LCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+helm_status loss_grad(Net* n, int B, const float* x, const float* target, const uint8_t* mask, float* grad,
+                      double* loss, hipStream_t s) {
+  if (B < 1 || B > n->Bmax) return fail(HELM_ERR_INVALID_ARG, "batch %d outside 1..%d", B, n->Bmax);
+  if (!x || !target || !mask || !grad) return fail(HELM_ERR_INVALID_ARG, "null buffer");
+  helm_status st = ensure_backward(n);
+  if (st != HELM_OK) return st;
+  const int64_t BV = (int64_t)B * n->V;
+  hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
+  LCHECK(hipMemcpyAsync(n->tgt, target, 8 * BV, hipMemcpyDeviceToDevice, s));
+  run_forward(n, B, s);
+  run_loss_backward(n, B, mask, n->lossd, s);
+  LCHECK(hipMemcpyAsync(grad, n->g, 4 * n->np, hipMemcpyDeviceToDevice, s));
+  float lf = 0.f;
+  LCHECK(hipMemcpyAsync(&lf, n->lossd, 4, hipMemcpyDeviceToHost, s));
+  LCHECK(hipStreamSynchronize(s));
+  LCHECK(hipGetLastError());
+  if (loss) *loss = lf;
+  return HELM_OK;
+}
+
+// ---- solver glue --------------------------------------------------------------
+helm_status bind(Net* n, const Coarse& g, hipStream_t s) {
+  if (edge_for(g) != n->D)
+    return fail(HELM_ERR_INVALID_ARG, "network edge %d does not fit a %dx%dx%d coarsest grid (needs %d)", n->D, g.nu[0],
+                g.nu[1], g.nu[2], edge_for(g));
+  if (g.p != P64 && g.p != P32) return fail(HELM_ERR_UNSUPPORTED, "coarsest fields must be FP64 or FP32 complex");
+  n->box = Box{g.nu[0], g.nu[1], g.nu[2]};
+  n->Nc = (int64_t)g.nu[0] * g.nu[1] * g.nu[2];
+  n->H2 = g.H2;
+  n->pf = g.p;
+  hipFree(n->dgn);
+  hipFree(n->mask);
+  n->dgn = nullptr;
+  n->mask = nullptr;
+  LCHECK(hipMalloc(&n->dgn, 8 * n->Nc));
+  LCHECK(hipMalloc(&n->mask, n->V));
+  hipLaunchKernelGGL(k_net_dgn, g1(n->Nc), dim3(256), 0, s, n->Nc, 27, g.st, g.H2, n->dgn);
+  hipLaunchKernelGGL(k_net_mask, g1(n->V), dim3(256), 0, s, n->D, n->box, n->mask);
+  LCHECK(hipStreamSynchronize(s));
+  n->bound = true;
+  return HELM_OK;
+}
+
+static helm_status ensure_cols(Net* n, int P) {
+  if (n->Pmax >= P) return HELM_OK;
+  hipFree(n->n2);
+  hipFree(n->part);
+  if (n->hn2) hipHostFree(n->hn2);
+  n->n2 = nullptr;
+  n->part = nullptr;
+  n->hn2 = nullptr;
+  n->Pmax = 0;
+  LCHECK(hipMalloc(&n->n2, 3 * 8 * (size_t)P + 256));
+  n->sc = n->n2 + P;
+  n->os = n->sc + P;
+  LCHECK(hipMalloc(&n->part, 16 * (size_t)(gram_part_elems(P) + P)));
+  n->Gs = n->part + gram_part_elems(P);
+  n->bad = reinterpret_cast<int*>(n->os + P);
+  LCHECK(hipHostMalloc(&n->hn2, 8 * (size_t)P));
+  n->Pmax = P;
+  return HELM_OK;
+}
+
+static void column_scales(Net* n, int P, const void* f, hipStream_t s) {
+  launch_colnorm2(n->pf, n->Nc, P, P, f, n->part, n->Gs, n->n2, s);
+  hipLaunchKernelGGL(k_net_scales, g1(P), dim3(256), 0, s, P, n->Nc, n->H2, (const double*)n->n2, n->sc, n->os);
+}
+
+template <class S>
+static void apply_t(Net* n, int P, const S* f, S* out, hipStream_t s) {
+  for (int c0 = 0; c0 < P; c0 += n->Bmax) {
+    const int nb = std::min(n->Bmax, P - c0);
+    hipLaunchKernelGGL(k_net_input<S>, g1((int64_t)nb * n->V), dim3(256), 0, s, P, c0, nb, n->D, n->box, f,
+                       (const double*)n->sc, (const float*)n->dgn, n->x0);
+    run_forward(n, nb, s);
+    hipLaunchKernelGGL(k_net_output<S>, g1(n->Nc * nb), dim3(256), 0, s, P, c0, nb, n->D, n->box,
+                       (const float*)n->out, (const double*)n->os, out, n->bad);
+  }
+}
+
+bool apply(Net* n, int P, const void* f, void* out, hipStream_t s) {
+  if (!n->bound || ensure_cols(n, P) != HELM_OK) return false;
+  column_scales(n, P, f, s);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, n->bad);
+  if (n->pf == P64)
+    apply_t(n, P, static_cast<const c128*>(f), static_cast<c128*>(out), s);
+  else
+    apply_t(n, P, static_cast<const c64*>(f), static_cast<c64*>(out), s);
+  if (hipMemcpyAsync(n->hbad, n->bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  return *n->hbad == 0;
+}
+
+helm_status capture_begin(Net* n, int max_pairs) {
+  if (!n->bound) return fail(HELM_ERR_INVALID_ARG, "network is not bound to a coarsest grid");
+  if (max_pairs < 1 || max_pairs > 1 << 20) return fail(HELM_ERR_INVALID_ARG, "max_pairs must be 1..2^20");
+  hipFree(n->xs);
+  hipFree(n->ts);
+  n->xs = nullptr;
+  n->ts = nullptr;
+  n->cap_max = n->cap_n = 0;
+  n->cap_seen = 0;
+  LCHECK(hipMalloc(&n->xs, 8 * n->V * (size_t)max_pairs));
+  LCHECK(hipMalloc(&n->ts, 8 * n->V * (size_t)max_pairs));
+  n->cap_max = max_pairs;
+  return HELM_OK;
+}
+
+template <class S>
+static void capture_t(Net* n, int P, const S* f, const S* e, hipStream_t s) {
+  for (int c = 0; c < P; ++c) {
+    const double v = n->hn2[c];
+    if (!(v > 0.0) || !std::isfinite(v)) continue;  // padding, converged or broken column
+    int64_t slot;
+    if (n->cap_n < n->cap_max) {
+      slot = n->cap_n++;
+    } else {
+      std::uniform_int_distribution<int64_t> u(0, n->cap_seen);
+      slot = u(n->rng);
+    }
+    ++n->cap_seen;
+    if (slot >= n->cap_max) continue;
+    hipLaunchKernelGGL(k_capture<S>, g1(n->V), dim3(256), 0, s, P, c, n->D, n->box, f, e, (const double*)n->sc,
+                       1.0 / n->H2, (const float*)n->dgn, slot, n->xs, n->ts);
+  }
+}
+
+void capture(Net* n, int P, const void* f, const void* e, hipStream_t s) {
+  if (!n->bound || !n->cap_max || ensure_cols(n, P) != HELM_OK) return;
+  column_scales(n, P, f, s);
+  if (hipMemcpyAsync(n->hn2, n->n2, 8 * (size_t)P, hipMemcpyDeviceToHost, s) != hipSuccess) return;
+  if (hipStreamSynchronize(s) != hipSuccess) return;
+  if (n->pf == P64)
+    capture_t(n, P, static_cast<const c128*>(f), static_cast<const c128*>(e), s);
+  else
+    capture_t(n, P, static_cast<const c64*>(f), static_cast<const c64*>(e), s);
+}
+
+int64_t pairs(const Net* n) { return n->cap_n; }
+
+helm_status pool_read(Net* n, int64_t i, float* x, float* t, hipStream_t s) {
+  if (i < 0 || i >= n->cap_n) return fail(HELM_ERR_INVALID_ARG, "pool index %lld outside 0..%d", (long long)i, n->cap_n - 1);
+  if (!x || !t) return fail(HELM_ERR_INVALID_ARG, "null buffer");
+  hipLaunchKernelGGL(k_bf16_to_f32, g1(4 * n->V), dim3(256), 0, s, 4 * n->V, (const bf16*)(n->xs + 4 * n->V * i), x);
+  LCHECK(hipMemcpyAsync(t, n->ts + 2 * n->V * i, 8 * n->V, hipMemcpyDeviceToDevice, s));
+  LCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
+helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double* hist, hipStream_t s) {
+  if (steps < 1 || batch < 1 || batch > n->Bmax || !(lr > 0.0))
+    return fail(HELM_ERR_INVALID_ARG, "steps >= 1, batch 1..%d and lr > 0 are required", n->Bmax);
+  if (n->cap_n < 1) return fail(HELM_ERR_INVALID_ARG, "no training pairs captured");
+  helm_status st = ensure_backward(n);
+  if (st != HELM_OK) return st;
+  hipFree(n->idx);
+  hipFree(n->rot);
+  hipFree(n->hist);
+  n->idx = nullptr;
+  n->rot = nullptr;
+  n->hist = nullptr;
+  LCHECK(hipMalloc(&n->idx, 4 * (size_t)steps * batch));
+  LCHECK(hipMalloc(&n->rot, 8 * (size_t)steps * batch));
+  LCHECK(hipMalloc(&n->hist, 4 * (size_t)steps));
+  std::vector<int> idx((size_t)steps * batch);
+  std::vector<float> rot(2 * idx.size());
+  std::mt19937_64 rng(seed);
+  std::uniform_int_distribution<int> u(0, n->cap_n - 1);
+  std::uniform_real_distribution<double> ph(0.0, 2.0 * M_PI);
+  for (size_t k = 0; k < idx.size(); ++k) {
+    idx[k] = u(rng);
+    const double a = ph(rng);
+    rot[2 * k] = (float)std::cos(a);
+    rot[2 * k + 1] = (float)std::sin(a);
+  }
+  LCHECK(hipMemcpyAsync(n->idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, s));
+  LCHECK(hipMemcpyAsync(n->rot, rot.data(), 4 * rot.size(), hipMemcpyHostToDevice, s));
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int64_t BV = (int64_t)batch * n->V;
+  for (int k = 0; k < steps; ++k) {
+    hipLaunchKernelGGL(k_gather_samples, g1(BV), dim3(256), 0, s, batch, (const int*)(n->idx + (size_t)k * batch),
+                       (const float*)(n->rot + (size_t)2 * k * batch), n->V, (const bf16*)n->xs, (const float*)n->ts,
+                       n->x0, n->tgt);
+    run_forward(n, batch, s);
+    run_loss_backward(n, batch, n->mask, n->hist + k, s);
+    ++n->adam_t;
+    const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+    hipLaunchKernelGGL(k_adam, g1(n->np), dim3(256), 0, s, n->np, n->p, (const float*)n->g, n->am, n->av, (float)lr,
+                       b1, b2, eps, c1, c2);
+    pack_weights(n, s);
+  }
+  std::vector<float> h(steps);
+  LCHECK(hipMemcpyAsync(h.data(), n->hist, 4 * (size_t)steps, hipMemcpyDeviceToHost, s));
+  LCHECK(hipStreamSynchronize(s));
+  LCHECK(hipGetLastError());
+  if (hist)
+    for (int k = 0; k < steps; ++k) hist[k] = h[k];
+  return HELM_OK;
+}
+
 }  // namespace learned
 }  // namespace helm
