@@ -688,7 +688,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   c->nc = c->lv[c->L - 1].npts;
   if (c->coarse == HELM_COARSE_LU) {
     const int64_t n = c->nc;
-    if (n > 24000) return bail(fail(HELM_ERR_UNSUPPORTED, "coarsest grid has %lld unknowns (> 24000)", (long long)n));
+    if (n > 32768) return bail(fail(HELM_ERR_UNSUPPORTED, "coarsest grid has %lld unknowns (> 32768)", (long long)n));
     const int nb = 32;  // pivot block held in LDS by one workgroup
     c128* work = nullptr;
     if (hipMalloc(&c->Minv64, 16 * n * n) != hipSuccess ||

@@ -143,7 +143,321 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
     }
 }
 
+// LDS-tiled form for Cin % 16 == 0: a workgroup owns an 8x8x4 block of
+// output voxels of one sample. Per chunk of 16 input channels it stages the
+// 10x10x6 input halo (16 B per voxel and half chunk) and, one z-plane of taps
+// at a time, the weights of 9 taps in LDS; the 27 tap products then read
+// only LDS. Wave w owns output plane z = w of the block (four 16-voxel M
+// tiles) and all NT*16 output channels. Tiles are numbered so that
+// consecutive tiles of a sample land on one XCD (shared halo in its L2).
+constexpr int CT_X = 8, CT_Y = 8, CT_Z = 4;
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_V = CH_X * CH_Y * CH_Z;
+constexpr int CCH = 16;
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
+                                                   int64_t per) {
+  extern __shared__ uint4 lds_u4[];
+  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH]
+  bf16* ws = xs + CH_V * CCH;                  // [9][N][CCH]
+  constexpr int N = NT * 16;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup leaves together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ml = lane & 15, kg = lane >> 4;
+  const int D = a.D;
+  int64_t r = t;
+  const int tx = (int)(r % ntx);
+  r /= ntx;
+  const int ty = (int)(r % nty);
+  r /= nty;
+  const int tz = (int)(r % ntz);
+  const int64_t b = r / ntz;
+  const int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
+  const int64_t sbase = b * (int64_t)D * D * D;
+  int hb[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int q = (wave * 4 + mt) * 16 + ml;
+    hb[mt] = (q % CT_X + 1) + CH_X * ((q / CT_X) % CT_Y + 1 + CH_Y * (q / (CT_X * CT_Y) + 1));
+  }
+  float4_ acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = float4_{0.f, 0.f, 0.f, 0.f};
+  const int sgn = a.flip ? -1 : 1;
+  for (int c0 = 0; c0 < a.Cin; c0 += CCH) {
+    for (int pz = 0; pz < 3; ++pz) {
+      __syncthreads();
+      if (pz == 0) {
+        for (int e = threadIdx.x; e < CH_V * 2; e += 256) {
+          const int hv = e >> 1, half = e & 1;
+          const int gx = x0 + hv % CH_X - 1, gy = y0 + (hv / CH_X) % CH_Y - 1, gz = z0 + hv / (CH_X * CH_Y) - 1;
+          uint4 val{0u, 0u, 0u, 0u};
+          if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
+            val = *reinterpret_cast<const uint4*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi +
+                                                  a.offi + c0 + half * 8);
+          lds_u4[hv * 2 + half] = val;
+        }
+      }
+      // weights of the taps of this plane: rows (tap, n), 16 channels each
+      for (int e = threadIdx.x; e < 9 * N * 2; e += 256) {
+        const int row = e >> 1, half = e & 1;
+        const int tap = pz * 9 + row / N, n = row % N;
+        lds_u4[CH_V * 2 + e] =
+            *reinterpret_cast<const uint4*>(a.W + ((int64_t)tap * N + n) * a.Cin + c0 + half * 8);
+      }
+      __syncthreads();
+#pragma unroll 3
+      for (int tt = 0; tt < 9; ++tt) {
+        const int tap = pz * 9 + tt;
+        const int toff = sgn * ((tap % 3 - 1) + CH_X * ((tap / 3) % 3 - 1 + CH_Y * (tap / 9 - 1)));
+        short4_ Bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          Bv[nt] = *reinterpret_cast<const short4_*>(ws + (tt * N + nt * 16 + ml) * CCH + kg * 4);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const short4_ A = *reinterpret_cast<const short4_*>(xs + (hb[mt] + toff) * CCH + kg * 4);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv[nt], acc[mt][nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = (wave * 4 + mt) * 16 + 4 * kg + j;
+      const int gx = x0 + q % CT_X, gy = y0 + (q / CT_X) % CT_Y, gz = z0 + q / (CT_X * CT_Y);
+      if (gx >= D || gy >= D || gz >= D) continue;
+      const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + ml;
+        float rv = acc[mt][nt][j] + (a.bias ? a.bias[n] : 0.f);
+        if (a.relu && !(rv > 0.f)) rv = 0.f;
+        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) rv = 0.f;
+        a.out[v * a.ldo + a.offo + n] = f2bf(rv);
+      }
+    }
+}
+
+// Same tiling with plane reuse, for NT <= 2 (all 27 taps of weights fit in
+// LDS next to the halo). Wave w owns a 16-voxel xy patch (rows 2w, 2w+1 of
+// the 8x8 block) through all 4 output planes. For each in-plane tap offset it
+// walks the 6 halo planes once: every input fragment it reads from LDS feeds
+// the MFMAs of up to 3 output planes (one per z tap), which halves the LDS
+// reads of the plain form.
+template <int NT, int FLIP>
+__global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
+                                                  int64_t per) {
+  extern __shared__ uint4 lds_u4[];
+  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH]
+  bf16* ws = xs + CH_V * CCH;                  // [27][N][CCH]
+  constexpr int N = NT * 16;
+  constexpr int SG = FLIP ? -1 : 1;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup leaves together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ml = lane & 15, kg = lane >> 4;
+  const int D = a.D;
+  int64_t r = t;
+  const int tx = (int)(r % ntx);
+  r /= ntx;
+  const int ty = (int)(r % nty);
+  r /= nty;
+  const int tz = (int)(r % ntz);
+  const int64_t b = r / ntz;
+  const int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
+  const int64_t sbase = b * (int64_t)D * D * D;
+  const int qa = wave * 16 + ml;  // my A row: xy voxel of the patch
+  const int hxy = (qa % CT_X + 1) + CH_X * (qa / CT_X + 1);
+  float4_ acc[CT_Z][NT];
+#pragma unroll
+  for (int z = 0; z < CT_Z; ++z)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[z][nt] = float4_{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < a.Cin; c0 += CCH) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < CH_V * 2; e += 256) {
+      const int hv = e >> 1, half = e & 1;
+      const int gx = x0 + hv % CH_X - 1, gy = y0 + (hv / CH_X) % CH_Y - 1, gz = z0 + hv / (CH_X * CH_Y) - 1;
+      uint4 val{0u, 0u, 0u, 0u};
+      if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
+        val = *reinterpret_cast<const uint4*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi +
+                                              a.offi + c0 + half * 8);
+      lds_u4[hv * 2 + half] = val;
+    }
+    for (int e = threadIdx.x; e < 27 * N * 2; e += 256) {
+      const int row = e >> 1, half = e & 1;  // row = tap * N + n
+      lds_u4[CH_V * 2 + e] = *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int txy = 0; txy < 9; ++txy) {
+      const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
+      const int hoff = SG * dxt + CH_X * (SG * dyt);
+      short4_ Bt[3][NT];  // z taps dz = -1, 0, 1
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          Bt[k][nt] = *reinterpret_cast<const short4_*>(ws + ((txy + 9 * k) * N + nt * 16 + ml) * CCH + kg * 4);
+#pragma unroll
+      for (int p = 0; p < CH_Z; ++p) {
+        const short4_ A = *reinterpret_cast<const short4_*>(xs + (hxy + hoff + CH_X * CH_Y * p) * CCH + kg * 4);
+#pragma unroll
+        for (int z = 0; z < CT_Z; ++z) {
+          const int dzin = p - 1 - z;  // input plane offset seen from output plane z
+          if (dzin < -1 || dzin > 1) continue;
+          const int k = SG * dzin + 1;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[z][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bt[k][nt], acc[z][nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < CT_Z; ++z)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = wave * 16 + 4 * kg + j;
+      const int gx = x0 + q % CT_X, gy = y0 + q / CT_X, gz = z0 + z;
+      if (gx >= D || gy >= D || gz >= D) continue;
+      const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + ml;
+        float rv = acc[z][nt][j] + (a.bias ? a.bias[n] : 0.f);
+        if (a.relu && !(rv > 0.f)) rv = 0.f;
+        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) rv = 0.f;
+        a.out[v * a.ldo + a.offo + n] = f2bf(rv);
+      }
+    }
+}
+
+template <int NT, int FLIP>
+static void conv3_zr_launch(const ConvArgs& a, hipStream_t s) {
+  const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
+  const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
+  const int64_t per = (ntiles + 7) / 8;
+  const size_t lds = sizeof(bf16) * (CH_V * CCH + 27 * NT * 16 * CCH);
+  hipLaunchKernelGGL((k_conv3_zr<NT, FLIP>), dim3((unsigned)(8 * per)), dim3(256), lds, s, a, ntx, nty, ntz, ntiles,
+                     per);
+}
+
+// First layer (4 input channels): one 16-wide K chunk of the MFMA covers
+// four taps of 4 channels each (lane group kg takes tap 4c + kg), so the
+// halo (8 B per voxel) and all 27 taps of weights sit in LDS at once.
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3_c4(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
+                                                  int64_t per) {
+  constexpr int N = NT * 16;
+  __shared__ uint2 xs4[CH_V];
+  __shared__ uint2 ws4[27 * N];
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup leaves together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ml = lane & 15, kg = lane >> 4;
+  const int D = a.D;
+  int64_t r = t;
+  const int tx = (int)(r % ntx);
+  r /= ntx;
+  const int ty = (int)(r % nty);
+  r /= nty;
+  const int tz = (int)(r % ntz);
+  const int64_t b = r / ntz;
+  const int x0 = tx * CT_X, y0 = ty * CT_Y, z0 = tz * CT_Z;
+  const int64_t sbase = b * (int64_t)D * D * D;
+  for (int e = threadIdx.x; e < CH_V; e += 256) {
+    const int gx = x0 + e % CH_X - 1, gy = y0 + (e / CH_X) % CH_Y - 1, gz = z0 + e / (CH_X * CH_Y) - 1;
+    uint2 val{0u, 0u};
+    if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
+      val = *reinterpret_cast<const uint2*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi + a.offi);
+    xs4[e] = val;
+  }
+  for (int e = threadIdx.x; e < 27 * N; e += 256) ws4[e] = *reinterpret_cast<const uint2*>(a.W + (int64_t)e * 4);
+  __syncthreads();
+  int hb[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int q = (wave * 4 + mt) * 16 + ml;
+    hb[mt] = (q % CT_X + 1) + CH_X * ((q / CT_X) % CT_Y + 1 + CH_Y * (q / (CT_X * CT_Y) + 1));
+  }
+  float4_ acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = float4_{0.f, 0.f, 0.f, 0.f};
+  const int sgn = a.flip ? -1 : 1;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    const int tap = 4 * c + kg;
+    const bool ok = tap < 27;
+    const int toff = ok ? sgn * ((tap % 3 - 1) + CH_X * ((tap / 3) % 3 - 1 + CH_Y * (tap / 9 - 1))) : 0;
+    short4_ Bv[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      Bv[nt] = ok ? __builtin_bit_cast(short4_, ws4[tap * N + nt * 16 + ml]) : short4_{0, 0, 0, 0};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const short4_ A = ok ? __builtin_bit_cast(short4_, xs4[hb[mt] + toff]) : short4_{0, 0, 0, 0};
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = (wave * 4 + mt) * 16 + 4 * kg + j;
+      const int gx = x0 + q % CT_X, gy = y0 + (q / CT_X) % CT_Y, gz = z0 + q / (CT_X * CT_Y);
+      if (gx >= D || gy >= D || gz >= D) continue;
+      const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + ml;
+        float rv = acc[mt][nt][j] + (a.bias ? a.bias[n] : 0.f);
+        if (a.relu && !(rv > 0.f)) rv = 0.f;
+        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) rv = 0.f;
+        a.out[v * a.ldo + a.offo + n] = f2bf(rv);
+      }
+    }
+}
+
+template <int NT>
+static void conv3_lds_launch(const ConvArgs& a, hipStream_t s) {
+  const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
+  const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
+  const int64_t per = (ntiles + 7) / 8;
+  const size_t lds = sizeof(bf16) * (CH_V * CCH + 9 * NT * 16 * CCH);
+  hipLaunchKernelGGL(k_conv3_lds<NT>, dim3((unsigned)(8 * per)), dim3(256), lds, s, a, ntx, nty, ntz, ntiles, per);
+}
+
 static void conv3(const ConvArgs& a, hipStream_t s) {
+  if (a.Cin == 4 && a.N == 16 && a.ldi == 4 && a.offi == 0) {
+    const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
+    const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
+    const int64_t per = (ntiles + 7) / 8;
+    hipLaunchKernelGGL(k_conv3_c4<1>, dim3((unsigned)(8 * per)), dim3(256), 0, s, a, ntx, nty, ntz, ntiles, per);
+    return;
+  }
+  if (a.Cin % CCH == 0) {
+    switch (a.N / 16) {
+      case 1: a.flip ? conv3_zr_launch<1, 1>(a, s) : conv3_zr_launch<1, 0>(a, s); return;
+      case 2: a.flip ? conv3_zr_launch<2, 1>(a, s) : conv3_zr_launch<2, 0>(a, s); return;
+      case 3: conv3_lds_launch<3>(a, s); return;
+      case 4: conv3_lds_launch<4>(a, s); return;
+      case 6: conv3_lds_launch<6>(a, s); return;
+      default: fatal_combo("conv3 output channels");
+    }
+  }
   const int64_t total = (int64_t)a.B * a.D * a.D * a.D;
   const dim3 gr((unsigned)((total + 127) / 128));
   switch (a.N / 16) {
@@ -246,54 +560,84 @@ __global__ __launch_bounds__(256) void k_bias_grad(int64_t total, int Cout, cons
 // ---------------------------------------------------------------------------
 // Pooling, upsampling, skip gradients (channels last, slices of wider buffers)
 // ---------------------------------------------------------------------------
+// Eight channels (16 B) per thread; every channel count, stride and slice
+// offset here is a multiple of 8.
+__device__ inline void ld8(const bf16* p, float f[8]) {
+  const uint4 w = *reinterpret_cast<const uint4*>(p);
+  const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[2 * k] = b2f((bf16)(u[k] & 0xffffu));
+    f[2 * k + 1] = b2f((bf16)(u[k] >> 16));
+  }
+}
+__device__ inline void st8(bf16* p, const float f[8]) {
+  uint32_t u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+  *reinterpret_cast<uint4*>(p) = uint4{u[0], u[1], u[2], u[3]};
+}
+__device__ inline int64_t child(int D, int x, int y, int z, int k) {
+  return (2 * x + (k & 1)) + (int64_t)D * ((2 * y + ((k >> 1) & 1)) + (int64_t)D * (2 * z + (k >> 2)));
+}
+
+// out [B][d^3] (row stride ldo) = 2x average pooling of the slice (ldi, offi) of in [B][D^3].
 __global__ void k_pool2(int B, int D, int C, const bf16* __restrict__ in, int ldi, int offi, bf16* __restrict__ out,
                         int ldo) {
-  const int d = D / 2;
+  const int d = D / 2, G = C / 8;
   const int64_t Vd = (int64_t)d * d * d;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)B * Vd * C) return;
-  const int c = (int)(t % C);
-  const int64_t bv = t / C, b = bv / Vd, v = bv % Vd;
+  if (t >= (int64_t)B * Vd * G) return;
+  const int c = (int)(t % G) * 8;
+  const int64_t bv = t / G, b = bv / Vd, v = bv % Vd;
   const int x = (int)(v % d), y = (int)((v / d) % d), z = (int)(v / ((int64_t)d * d));
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8];
   for (int k = 0; k < 8; ++k) {
-    const int64_t iv = (2 * x + (k & 1)) + (int64_t)D * ((2 * y + ((k >> 1) & 1)) + (int64_t)D * (2 * z + (k >> 2)));
-    s += b2f(in[(b * D * D * D + iv) * ldi + offi + c]);
+    ld8(in + (b * D * D * D + child(D, x, y, z, k)) * ldi + offi + c, f);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += f[e];
   }
-  out[bv * ldo + c] = f2bf(0.125f * s);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) s[e] *= 0.125f;
+  st8(out + bv * ldo + c, s);
 }
 
 // out slice [B][(2d)^3][C] at (ldo, offo) = nearest upsampling of in [B][d^3][C]
 __global__ void k_up2(int B, int d, int C, const bf16* __restrict__ in, bf16* __restrict__ out, int ldo, int offo) {
-  const int D = 2 * d;
+  const int D = 2 * d, G = C / 8;
   const int64_t VD = (int64_t)D * D * D;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)B * VD * C) return;
-  const int c = (int)(t % C);
-  const int64_t bv = t / C, b = bv / VD, v = bv % VD;
+  if (t >= (int64_t)B * VD * G) return;
+  const int c = (int)(t % G) * 8;
+  const int64_t bv = t / G, b = bv / VD, v = bv % VD;
   const int x = (int)(v % D), y = (int)((v / D) % D), z = (int)(v / ((int64_t)D * D));
   const int64_t iv = (x / 2) + (int64_t)d * ((y / 2) + (int64_t)d * (z / 2));
-  out[bv * ldo + offo + c] = in[(b * d * d * d + iv) * C + c];
+  *reinterpret_cast<uint4*>(out + bv * ldo + offo + c) =
+      *reinterpret_cast<const uint4*>(in + (b * d * d * d + iv) * C + c);
 }
 
 // out [B][d^3][C] = (sum over the 8 children of the gradient slice) masked
 // by (act > 0) where act is [B][d^3][C].
 __global__ void k_up2_bwd(int B, int d, int C, const bf16* __restrict__ g, int ldg, int offg,
                           const bf16* __restrict__ act, bf16* __restrict__ out) {
-  const int D = 2 * d;
+  const int D = 2 * d, G = C / 8;
   const int64_t Vd = (int64_t)d * d * d;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)B * Vd * C) return;
-  const int c = (int)(t % C);
-  const int64_t bv = t / C, b = bv / Vd, v = bv % Vd;
+  if (t >= (int64_t)B * Vd * G) return;
+  const int c = (int)(t % G) * 8;
+  const int64_t bv = t / G, b = bv / Vd, v = bv % Vd;
   const int x = (int)(v % d), y = (int)((v / d) % d), z = (int)(v / ((int64_t)d * d));
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, f[8], a[8];
   for (int k = 0; k < 8; ++k) {
-    const int64_t iv = (2 * x + (k & 1)) + (int64_t)D * ((2 * y + ((k >> 1) & 1)) + (int64_t)D * (2 * z + (k >> 2)));
-    s += b2f(g[(b * D * D * D + iv) * ldg + offg + c]);
+    ld8(g + (b * D * D * D + child(D, x, y, z, k)) * ldg + offg + c, f);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += f[e];
   }
-  if (!(b2f(act[bv * C + c]) > 0.f)) s = 0.f;
-  out[bv * C + c] = f2bf(s);
+  ld8(act + bv * C + c, a);
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (!(a[e] > 0.f)) s[e] = 0.f;
+  st8(out + bv * C + c, s);
 }
 
 // Gradient of a skip activation s (= a slice of a concat buffer): the
@@ -302,17 +646,21 @@ __global__ void k_up2_bwd(int B, int d, int C, const bf16* __restrict__ g, int l
 __global__ void k_skip_grad(int B, int D, int C, const bf16* __restrict__ gcat, int ldc, int offc,
                             const bf16* __restrict__ gpool, const bf16* __restrict__ s, int lds, int offs,
                             bf16* __restrict__ out) {
-  const int d = D / 2;
+  const int d = D / 2, G = C / 8;
   const int64_t VD = (int64_t)D * D * D;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)B * VD * C) return;
-  const int c = (int)(t % C);
-  const int64_t bv = t / C, b = bv / VD, v = bv % VD;
+  if (t >= (int64_t)B * VD * G) return;
+  const int c = (int)(t % G) * 8;
+  const int64_t bv = t / G, b = bv / VD, v = bv % VD;
   const int x = (int)(v % D), y = (int)((v / D) % D), z = (int)(v / ((int64_t)D * D));
   const int64_t pv = (x / 2) + (int64_t)d * ((y / 2) + (int64_t)d * (z / 2));
-  float r = b2f(gcat[bv * ldc + offc + c]) + 0.125f * b2f(gpool[(b * d * d * d + pv) * C + c]);
-  if (!(b2f(s[bv * lds + offs + c]) > 0.f)) r = 0.f;
-  out[bv * C + c] = f2bf(r);
+  float gc[8], gp[8], sv[8], r[8];
+  ld8(gcat + bv * ldc + offc + c, gc);
+  ld8(gpool + (b * d * d * d + pv) * C + c, gp);
+  ld8(s + bv * lds + offs + c, sv);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = sv[e] > 0.f ? gc[e] + 0.125f * gp[e] : 0.f;
+  st8(out + bv * C + c, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,16 +1210,16 @@ static void run_forward(Net* n, int B, hipStream_t s) {
   const int64_t BV = (int64_t)B * n->V;
   conv_fwd(n, 0, B, D, n->x0, 4, 0, n->a1, 16, 0, s);
   conv_fwd(n, 1, B, D, n->a1, 16, 0, n->c1, 48, 32, s);  // s1 -> second slice of c1
-  hipLaunchKernelGGL(k_pool2, g1(BV / 8 * 16), dim3(256), 0, s, B, D, 16, (const bf16*)n->c1, 48, 32, n->p1, 16);
+  hipLaunchKernelGGL(k_pool2, g1(BV / 8 * 2), dim3(256), 0, s, B, D, 16, (const bf16*)n->c1, 48, 32, n->p1, 16);
   conv_fwd(n, 2, B, d2, n->p1, 16, 0, n->a2, 32, 0, s);
   conv_fwd(n, 3, B, d2, n->a2, 32, 0, n->c2, 96, 64, s);  // s2 -> second slice of c2
-  hipLaunchKernelGGL(k_pool2, g1(BV / 64 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->c2, 96, 64, n->p2, 32);
+  hipLaunchKernelGGL(k_pool2, g1(BV / 64 * 4), dim3(256), 0, s, B, d2, 32, (const bf16*)n->c2, 96, 64, n->p2, 32);
   conv_fwd(n, 4, B, d4, n->p2, 32, 0, n->a4, 64, 0, s);
   conv_fwd(n, 5, B, d4, n->a4, 64, 0, n->a5, 64, 0, s);
-  hipLaunchKernelGGL(k_up2, g1(BV / 8 * 64), dim3(256), 0, s, B, d4, 64, (const bf16*)n->a5, n->c2, 96, 0);
+  hipLaunchKernelGGL(k_up2, g1(BV / 8 * 8), dim3(256), 0, s, B, d4, 64, (const bf16*)n->a5, n->c2, 96, 0);
   conv_fwd(n, 6, B, d2, n->c2, 96, 0, n->a6, 32, 0, s);
   conv_fwd(n, 7, B, d2, n->a6, 32, 0, n->a7, 32, 0, s);
-  hipLaunchKernelGGL(k_up2, g1(BV * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->a7, n->c1, 48, 0);
+  hipLaunchKernelGGL(k_up2, g1(BV * 4), dim3(256), 0, s, B, d2, 32, (const bf16*)n->a7, n->c1, 48, 0);
   conv_fwd(n, 8, B, D, n->c1, 48, 0, n->a8, 16, 0, s);
   conv_fwd(n, 9, B, D, n->a8, 16, 0, n->a9, 16, 0, s);
   hipLaunchKernelGGL(k_head_fwd, g1(BV), dim3(256), 0, s, BV, (const bf16*)n->a9, (const float*)(n->p + n->np - 34),
@@ -929,14 +1277,14 @@ static void run_loss_backward(Net* n, int B, const uint8_t* mask, float* loss_ds
   conv_bwd_data(n, 9, B, D, n->g9, n->g8, 16, n->a8, s);
   conv_bwd_weight(n, 8, B, D, n->c1, 48, 0, n->g8, s);
   conv_bwd_data(n, 8, B, D, n->g8, n->gc1, 48, nullptr, s);
-  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 8 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc1, 48, 0,
+  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 8 * 4), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc1, 48, 0,
                      (const bf16*)n->a7, n->g7);
   // decoder, half resolution
   conv_bwd_weight(n, 7, B, d2, n->a6, 32, 0, n->g7, s);
   conv_bwd_data(n, 7, B, d2, n->g7, n->g6, 32, n->a6, s);
   conv_bwd_weight(n, 6, B, d2, n->c2, 96, 0, n->g6, s);
   conv_bwd_data(n, 6, B, d2, n->g6, n->gc2, 96, nullptr, s);
-  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 64 * 64), dim3(256), 0, s, B, d4, 64, (const bf16*)n->gc2, 96, 0,
+  hipLaunchKernelGGL(k_up2_bwd, g1(BV / 64 * 8), dim3(256), 0, s, B, d4, 64, (const bf16*)n->gc2, 96, 0,
                      (const bf16*)n->a5, n->g5);
   // bottom
   conv_bwd_weight(n, 5, B, d4, n->a4, 64, 0, n->g5, s);
@@ -944,14 +1292,14 @@ static void run_loss_backward(Net* n, int B, const uint8_t* mask, float* loss_ds
   conv_bwd_weight(n, 4, B, d4, n->p2, 32, 0, n->g4, s);
   conv_bwd_data(n, 4, B, d4, n->g4, n->gp2, 32, nullptr, s);
   // encoder, half resolution: s2 feeds the pool and the skip
-  hipLaunchKernelGGL(k_skip_grad, g1(BV / 8 * 32), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc2, 96, 64,
+  hipLaunchKernelGGL(k_skip_grad, g1(BV / 8 * 4), dim3(256), 0, s, B, d2, 32, (const bf16*)n->gc2, 96, 64,
                      (const bf16*)n->gp2, (const bf16*)n->c2, 96, 64, n->g3);
   conv_bwd_weight(n, 3, B, d2, n->a2, 32, 0, n->g3, s);
   conv_bwd_data(n, 3, B, d2, n->g3, n->g2, 32, n->a2, s);
   conv_bwd_weight(n, 2, B, d2, n->p1, 16, 0, n->g2, s);
   conv_bwd_data(n, 2, B, d2, n->g2, n->gp1, 16, nullptr, s);
   // encoder, full resolution: s1 feeds the pool and the skip
-  hipLaunchKernelGGL(k_skip_grad, g1(BV * 16), dim3(256), 0, s, B, D, 16, (const bf16*)n->gc1, 48, 32,
+  hipLaunchKernelGGL(k_skip_grad, g1(BV * 2), dim3(256), 0, s, B, D, 16, (const bf16*)n->gc1, 48, 32,
                      (const bf16*)n->gp1, (const bf16*)n->c1, 48, 32, n->g1);
   conv_bwd_weight(n, 1, B, D, n->a1, 16, 0, n->g1, s);
   conv_bwd_data(n, 1, B, D, n->g1, n->g0, 16, n->a1, s);
