@@ -106,6 +106,10 @@ typedef struct {
   int32_t warm_start;  /* 1: U holds an initial guess */
   int32_t reorth;      /* 0: one block Gram-Schmidt pass; 1: always two; 2: a second
                           pass only where the norm fell below half (block size 1) */
+  int32_t graph;       /* 1: run each cycle from a HIP graph captured on first use per
+                          (block width, buffers) and replayed afterwards; results are
+                          bitwise those of the eager launches. Ignored while kernel
+                          timing (helm_profile_enable) or pair capture is on. */
 } helm_solve_opts;
 
 typedef struct {
@@ -136,6 +140,21 @@ helm_status helm_workspace_size(helm_handle h, int32_t nrhs, int32_t restart, si
 helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U, double tol,
                              const helm_solve_opts* opts, void* workspace, size_t ws_bytes,
                              helm_solve_info* info, void* stream);
+
+/* Solve k independent instances concurrently (uneven sizes welcome): instance
+ * i is helm_solve_block(hs[i], nrhs[i], Q[i], U[i], tol, opts) on a stream
+ * owned by hs[i] (created on first use, default priority), driven by a pool of
+ * min(k, max_threads) host threads (max_threads <= 0: 16). The handles must be
+ * distinct. Work queued on `stream` before the call is visible to every
+ * instance, and `stream` waits for all of them. Q[i], U[i]: DEVICE complex128
+ * [nrhs[i]][N_i]; infos: HOST [k] or NULL (each entry as for
+ * helm_solve_block); status: HOST [k] or NULL, per-instance results. Returns
+ * the first non-OK instance status (its message prefixed with the index), or
+ * HELM_OK. Results are bitwise those of solving the instances one by one. */
+helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nrhs, const void* const* Q,
+                             void* const* U, double tol, const helm_solve_opts* opts,
+                             helm_solve_info* infos, int32_t* status, int32_t max_threads,
+                             void* stream);
 
 /* relres[s] = ||q_s - H u_s|| / ||q_s|| in FP64 (0 for a zero q_s).
  * Q, U: DEVICE complex128 [nrhs][N]; relres: HOST [nrhs]. */
@@ -214,8 +233,9 @@ const char* helm_last_error(void);
  * A network is used by helm_setup with coarse = HELM_COARSE_LEARNED and
  * net = a blob from helm_net_save (3D only). With coarse_iters = k > 0 the
  * network's correction is the initial guess of k GMRES steps on the coarsest
- * grid. A non-finite output makes that coarsest solve fall back to
- * max(k, 20) GMRES steps from zero (counted in info.fallback_used). */
+ * grid. An output that is not finite, or beyond 1e4 in the normalised units
+ * e / (H^2 rms(r)), makes that coarsest solve fall back to max(k, 20) GMRES
+ * steps from zero (counted in info.fallback_used). */
 typedef struct helm_net_s* helm_net;
 /* Number of FP32 parameters. */
 int64_t helm_net_nparams(void);

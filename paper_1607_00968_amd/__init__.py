@@ -23,7 +23,7 @@ __all__ = [
     "HelmError", "lib", "LIBPATH", "Handle", "helm_setup", "helm_solve_block",
     "helm_profile_enable", "helm_profile_read", "KERNEL_CLASSES",
     "helm_residual", "helm_apply", "helm_precond", "helm_level_stencil",
-    "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "ABI_SYMBOLS",
+    "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "helm_solve_batch", "ABI_SYMBOLS",
     "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture",
 ]
 
@@ -39,7 +39,7 @@ CYCLE = {"V": 0, "W": 1, "K": 2}
 
 ABI_SYMBOLS = (
     "helm_setup_desc_default", "helm_setup", "helm_destroy", "helm_workspace_size",
-    "helm_solve_block", "helm_residual", "helm_apply", "helm_precond",
+    "helm_solve_block", "helm_solve_batch", "helm_residual", "helm_apply", "helm_precond",
     "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
     "helm_profile_enable", "helm_profile_read", "helm_fine_tile", "helm_set_fine_tile",
     "helm_status_string", "helm_last_error",
@@ -71,7 +71,7 @@ class SetupDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_cycles", C.c_int32), ("block_size", C.c_int32),
-                ("warm_start", C.c_int32), ("reorth", C.c_int32)]
+                ("warm_start", C.c_int32), ("reorth", C.c_int32), ("graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -99,6 +99,7 @@ def lib():
         L.helm_solve_block.argtypes = [P, I, P, P, D, C.POINTER(SolveOpts), P, C.c_size_t,
                                        C.POINTER(SolveInfo), P]
         L.helm_residual.argtypes = [P, I, P, P, P, P]
+        L.helm_solve_batch.argtypes = [I, P, P, P, P, D, C.POINTER(SolveOpts), P, P, I, P]
         L.helm_apply.argtypes = [P, I, I, P, P, P]
         L.helm_precond.argtypes = [P, I, P, P, P]
         L.helm_level_dims.argtypes = [P, I, P]
@@ -223,13 +224,13 @@ def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:
 
 
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
-                     warm_start=False, reorth=True, workspace=None, stream=None) -> dict:
+                     warm_start=False, reorth=True, workspace=None, stream=None, graph=False) -> dict:
     """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ..."""
     nrhs = Q.shape[0]
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
         raise ValueError("Q and U must both be [nrhs, N]")
-    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(bool(reorth)))
+    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), int(bool(graph)))
     rel = np.zeros(nrhs)
     conv = np.zeros(nrhs, np.int32)
     info = SolveInfo()
@@ -242,6 +243,39 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
     return {"status": st, "cycles": info.cycles, "restarts": info.restarts,
             "converged_all": bool(info.converged_all), "fallback_used": int(info.fallback_used),
             "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool)}
+
+
+def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, block_size=1, reorth=0,
+                     graph=False, max_threads=16, stream=None) -> list:
+    """Solve independent instances concurrently (one stream and one host
+    thread of a pool per instance). Returns one dict per instance, as
+    helm_solve_block does, plus "status"."""
+    k = len(handles)
+    if not (len(Qs) == len(Us) == k) or k == 0:
+        raise ValueError("need one Q and one U per handle")
+    hs = (C.c_void_p * k)(*[h.ptr for h in handles])
+    nr = (C.c_int32 * k)(*[int(q.shape[0]) for q in Qs])
+    for h, q, u in zip(handles, Qs, Us):
+        _dev_block(q, "Q")
+        _dev_block(u, "U")
+        if u.shape != q.shape or q.shape[1] != h.N:
+            raise ValueError("Q and U must both be [nrhs, N] of their instance")
+    qp = (C.c_void_p * k)(*[q.data_ptr() for q in Qs])
+    up = (C.c_void_p * k)(*[u.data_ptr() for u in Us])
+    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), int(bool(graph)))
+    infos = (SolveInfo * k)()
+    rel = [np.zeros(int(q.shape[0])) for q in Qs]
+    conv = [np.zeros(int(q.shape[0]), np.int32) for q in Qs]
+    for i in range(k):
+        infos[i].relres = rel[i].ctypes.data
+        infos[i].converged = conv[i].ctypes.data
+    st = (C.c_int32 * k)()
+    _check(lib().helm_solve_batch(k, hs, nr, qp, up, float(tol), C.byref(o), infos, st, int(max_threads),
+                                  _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
+    return [{"status": st[i], "cycles": infos[i].cycles, "restarts": infos[i].restarts,
+             "converged_all": bool(infos[i].converged_all), "fallback_used": int(infos[i].fallback_used),
+             "t_solve_ms": infos[i].t_solve_ms, "relres": rel[i], "converged": conv[i].astype(bool)}
+            for i in range(k)]
 
 
 def helm_residual(hd: Handle, Q, U, stream=None) -> np.ndarray:

@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -100,6 +102,20 @@ struct helm_ctx {
   learned::Net* net = nullptr;
   int64_t fallbacks = 0;            // learned coarsest solves replaced by GMRES
   learned::Net* cap = nullptr;      // pool receiving coarsest (f, e) pairs
+  // cycles captured as HIP graphs, keyed by block width and buffers
+  struct CycleGraph {
+    int P;
+    const void* f;
+    void* out;
+    void* tmp;
+    hipGraphExec_t exec;
+  };
+  uint64_t graph_net_gen = 0;     // network scratch generation the graphs were taken with
+  std::vector<CycleGraph> graphs;
+  hipStream_t gstream = nullptr;  // capture stream (never executes work itself)
+  hipStream_t bstream = nullptr;  // this handle's stream inside helm_solve_batch
+  bool capturing = false;         // a cycle is being recorded into a graph
+  bool force_fallback = false;    // redo a cycle with the GMRES coarsest fallback
   // cached per-solve field allocation
   int fieldsP = 0;
   void* fieldmem = nullptr;
@@ -186,8 +202,16 @@ static void level_op(helm_ctx* c, int l, int mode, int P, const void* u, const v
   }
 }
 
+__global__ void k_zero_u4(int64_t n, uint4* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = uint4{0u, 0u, 0u, 0u};
+}
+
+// A fill kernel rather than a memset node, so that the cycle can be captured
+// into a HIP graph; field sizes are multiples of 16 B (P % 4 == 0).
 static void zero_field(helm_ctx* c, int l, int P, void* u, hipStream_t s) {
-  hipMemsetAsync(u, 0, psize(field_prec(c, l)) * c->lv[l].npts * P, s);
+  const int64_t n = (int64_t)psize(field_prec(c, l)) * c->lv[l].npts * P / 16;
+  hipLaunchKernelGGL(k_zero_u4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, static_cast<uint4*>(u));
 }
 
 static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s);
@@ -280,7 +304,7 @@ static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, int k, hi
     launch_cg_hcol(P, j, k, Gc, hn2, H, sc, s);
     launch_scale_cols(p, N, P, P, sc, vec(j + 1), vec(j + 1), s);
   }
-  launch_cg_ls(P, k, H, b2, Yc, s);
+  launch_cg_ls(P, k, H, b2, Gc, Yc, s);  // Gc (2 (k+1) P entries) is free after the loop
   launch_block_update(1, p, p, N, P, P, 1, k, vl, Yc, out, s);
 }
 
@@ -307,7 +331,16 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
   } else if (c->coarse == HELM_COARSE_GMRES) {
     coarse_gmres(c, P, f, out, c->coarse_iters, s);
   } else if (c->coarse == HELM_COARSE_LEARNED && c->net) {
-    if (!learned::apply(c->net, P, f, out, s)) {
+    bool ok = false;
+    if (c->capturing) {
+      // inside a graph: no host check here; the caller reads the network's
+      // non-finite count after the replay and redoes the cycle if needed
+      learned::apply_async(c->net, P, f, out, s);
+      ok = true;
+    } else if (!c->force_fallback) {
+      ok = learned::apply(c->net, P, f, out, s);
+    }
+    if (!ok) {
       ++c->fallbacks;
       coarse_gmres(c, P, f, out, coarse_gmres_cap(c), s);
     } else if (c->coarse_iters > 0) {
@@ -334,6 +367,61 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
   if (c->cap && (c->coarse == HELM_COARSE_LU || c->coarse == HELM_COARSE_GMRES)) learned::capture(c->cap, P, f, out, s);
 }
 
+static void clear_graphs(helm_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// One cycle f -> out on level 0. With `graph`, the kernel sequence of this
+// (block width, buffers) is captured once into a HIP graph on a private
+// stream and replayed on s afterwards; the cycle has no host synchronisation
+// or memset inside, so the replay runs exactly the kernels of the eager path.
+// The learned correction's non-finite check happens after the replay: if it
+// fired, the cycle is run again eagerly with the GMRES fallback.
+static helm_status run_cycle(helm_ctx* c, int P, const void* f, void* out, void* tmp, bool graph, hipStream_t s) {
+  if (!graph) {
+    cycle_rec(c, 0, P, f, out, tmp, s);
+    return HELM_OK;
+  }
+  const bool net = c->coarse == HELM_COARSE_LEARNED && c->net;
+  if (net) {
+    helm_status st = learned::prepare(c->net, P);
+    if (st != HELM_OK) return st;
+    if (learned::scratch_gen(c->net) != c->graph_net_gen) {
+      clear_graphs(c);
+      c->graph_net_gen = learned::scratch_gen(c->net);
+    }
+  }
+  hipGraphExec_t exec = nullptr;
+  for (const auto& g : c->graphs)
+    if (g.P == P && g.f == f && g.out == out && g.tmp == tmp) exec = g.exec;
+  if (!exec) {
+    if (c->graphs.size() >= 64) clear_graphs(c);
+    if (!c->gstream) HCHECK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HCHECK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    cycle_rec(c, 0, P, f, out, tmp, c->gstream);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    HCHECK(hipStreamEndCapture(c->gstream, &g));
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HCHECK(e);
+    c->graphs.push_back({P, f, out, tmp, exec});
+  }
+  HCHECK(hipGraphLaunch(exec, s));
+  if (net) {
+    const int bad = learned::bad_count(c->net, s);
+    if (bad < 0) return fail(HELM_ERR_DEVICE, "reading the network's non-finite count failed");
+    if (bad > 0) {
+      c->force_fallback = true;
+      cycle_rec(c, 0, P, f, out, tmp, s);
+      c->force_fallback = false;
+    }
+  }
+  return HELM_OK;
+}
+
 static learned::Coarse coarse_view(const helm_ctx* c) {
   const Level& L = c->lv[c->L - 1];
   learned::Coarse g;
@@ -353,6 +441,7 @@ static int padP(int nrhs) { return (nrhs + 3) / 4 * 4; }
 
 static helm_status ensure_fields(helm_ctx* c, int P) {
   if (c->fieldsP >= P && c->fieldmem) return HELM_OK;
+  clear_graphs(c);
   if (c->fieldmem) {
     hipFree(c->fieldmem);
     c->fieldmem = nullptr;
@@ -425,6 +514,7 @@ static void tune_cache_store(const std::string& key, FineTile t, double ms) {
 
 static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
   if (c->dim != 3 || c->tileP == P) return HELM_OK;
+  clear_graphs(c);  // captured cycles hold the previous tile's kernels
   c->tileP = P;
   c->tile = FineTile{4, 32};
   const char* en = std::getenv("HELM_AUTOTUNE");
@@ -544,6 +634,10 @@ const char* helm_last_error(void) { return g_err.c_str(); }
 
 static void free_ctx(helm_ctx* c) {
   if (!c) return;
+  (void)hipDeviceSynchronize();
+  clear_graphs(c);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  if (c->bstream) (void)hipStreamDestroy(c->bstream);
   for (int l = 0; l < c->L; ++l) {
     Level& L = c->lv[l];
     hipFree(L.dH);
@@ -767,6 +861,7 @@ helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]) {
 helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]) {
   if (!h || !tile || nrhs < 1 || nrhs > 256) return fail(HELM_ERR_INVALID_ARG, "bad argument");
   if (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4) || tile[1] < 1) return fail(HELM_ERR_INVALID_ARG, "bad tile");
+  clear_graphs(h);
   h->tileP = padP(nrhs);
   h->tile = FineTile{tile[0], tile[1]};
   return HELM_OK;
@@ -966,7 +1061,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   helm_status st = check_block(h, nrhs, Q, U);
   if (st != HELM_OK) return st;
   if (!(tol > 0) || !std::isfinite(tol)) return fail(HELM_ERR_INVALID_ARG, "tol must be > 0");
-  helm_solve_opts o{5, 1000, 0, 0, 2};
+  helm_solve_opts o{5, 1000, 0, 0, 2, 0};
   if (opts) o = *opts;
   const int m = o.restart;
   if (m < 1 || m >= MAXPTR) return fail(HELM_ERR_INVALID_ARG, "restart must be 1..%d", MAXPTR - 1);
@@ -985,10 +1080,13 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
   set_fine_tile(c->tile);
   const int64_t fallbacks0 = c->fallbacks;
+  // graphs need a cycle without host work: no per-kernel timing, no pair capture
+  const bool graph = o.graph != 0 && !c->prof && !c->cap;
   const WsLayout w = ws_layout(c, P, m, pb);
   char* base = static_cast<char*>(workspace);
   if (!base) {
     if (c->wsbytes < w.end) {
+      clear_graphs(c);
       hipFree(c->ws);
       c->ws = nullptr;
       c->wsbytes = 0;
@@ -1121,10 +1219,15 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       // Z_j = cycle(V_j)
       const Level& Lz = c->lv[0];
       if (pz == P64 || pv == P32) {
-        cycle_rec(c, 0, P, V[j], Z[j], Lz.U1, s);
+        st = run_cycle(c, P, V[j], Z[j], Lz.U1, graph, s);
       } else {
         launch_convert(P64, P32, N * P, V[j], Lz.F, s);
-        cycle_rec(c, 0, P, Lz.F, Z[j], Lz.U1, s);
+        st = run_cycle(c, P, Lz.F, Z[j], Lz.U1, graph, s);
+      }
+      if (st != HELM_OK) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return st;
       }
       ++cycles;
       // W = H Z_j (FP64)
@@ -1357,4 +1460,67 @@ helm_status helm_net_train(helm_net n, int32_t steps, int32_t batch, double lr, 
                            void* stream) {
   if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
   return learned::train(n->n, steps, batch, lr, seed, hist, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Independent instances solved concurrently: each handle works on a stream of
+// its own, driven by one of a pool of host threads (every solve synchronises
+// its own stream once per Arnoldi step, so a thread per active instance keeps
+// the GPU fed with the other instances' kernels meanwhile).
+// ---------------------------------------------------------------------------
+helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nrhs, const void* const* Q,
+                             void* const* U, double tol, const helm_solve_opts* opts, helm_solve_info* infos,
+                             int32_t* status, int32_t max_threads, void* stream) {
+  if (k < 1 || !hs || !nrhs || !Q || !U) return fail(HELM_ERR_INVALID_ARG, "bad batch arguments");
+  for (int i = 0; i < k; ++i) {
+    if (!hs[i]) return fail(HELM_ERR_INVALID_ARG, "null handle at %d", i);
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(HELM_ERR_INVALID_ARG, "handle %d appears twice (instances need their own)", i);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HCHECK(hipGetDevice(&dev));
+  for (int i = 0; i < k; ++i)
+    if (!hs[i]->bstream) HCHECK(hipStreamCreateWithFlags(&hs[i]->bstream, hipStreamNonBlocking));
+  // inputs written on the caller's stream are visible to every instance
+  hipEvent_t ready;
+  HCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HCHECK(hipEventRecord(ready, s));
+  for (int i = 0; i < k; ++i) HCHECK(hipStreamWaitEvent(hs[i]->bstream, ready, 0));
+  std::vector<helm_status> st(k, HELM_OK);
+  std::vector<std::string> msg(k);
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= k) break;
+      st[i] = helm_solve_block(hs[i], nrhs[i], Q[i], U[i], tol, opts, nullptr, 0, infos ? &infos[i] : nullptr,
+                               hs[i]->bstream);
+      if (st[i] != HELM_OK) msg[i] = g_err;
+    }
+  };
+  const int nt = std::max(1, std::min(k, max_threads > 0 ? max_threads : 16));
+  std::vector<std::thread> pool;
+  pool.reserve(nt);
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(ready);
+  // the caller's stream continues after every instance
+  for (int i = 0; i < k; ++i) {
+    hipEvent_t done;
+    HCHECK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HCHECK(hipEventRecord(done, hs[i]->bstream));
+    HCHECK(hipStreamWaitEvent(s, done, 0));
+    (void)hipEventDestroy(done);
+  }
+  helm_status first = HELM_OK;
+  for (int i = 0; i < k; ++i) {
+    if (status) status[i] = st[i];
+    if (st[i] != HELM_OK && first == HELM_OK) {
+      first = st[i];
+      g_err = "instance " + std::to_string(i) + ": " + msg[i];
+    }
+  }
+  return first;
 }

@@ -685,28 +685,23 @@ void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_inv_sqrt, dim3((P + 63) / 64), dim3(64), 0, s, P, b2, sc);
 }
 // Least squares min || beta e1 - H y || per column by Givens rotations;
-// y written in update layout Y[i][c] (pb = 1).
-__global__ void k_cg_ls(int P, int k, const c128* __restrict__ Hm, const double* __restrict__ b2,
+// y written in update layout Y[i][c] (pb = 1). The rotations are applied in
+// place to the column's Hessenberg in global memory (rotation j to rows j,
+// j+1 of every later column as soon as it is known) and the rotated
+// right-hand side lives in G[i][c]: no per-lane arrays, so the kernel needs no
+// scratch memory. Each entry sees the same rotations in the same order as a
+// column-by-column sweep.
+__global__ void k_cg_ls(int P, int k, c128* __restrict__ Hm, const double* __restrict__ b2, c128* __restrict__ G,
                         c128* __restrict__ Y) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P) return;
-  constexpr int KMAX = 48;
-  cx<double> h[KMAX + 1], g[KMAX + 1], cs[KMAX], sn[KMAX];
-  cx<double> R[KMAX * (KMAX + 1) / 2];  // packed upper triangle, column by column
-  const c128* H = Hm + (int64_t)c * (k + 1) * k;
+  c128* H = Hm + (int64_t)c * (k + 1) * k;  // column j, row i at H[j (k+1) + i]
   const double beta = sqrt(fmax(b2[c], 0.0));
-  for (int i = 0; i <= k; ++i) g[i] = {0.0, 0.0};
-  g[0] = {beta, 0.0};
+  for (int i = 0; i <= k; ++i) G[(int64_t)i * P + c] = c128{0.0, 0.0};
+  G[c] = c128{beta, 0.0};
   int steps = k;
   for (int j = 0; j < k; ++j) {
-    for (int i = 0; i <= j + 1; ++i) h[i] = tcx(H[(int64_t)j * (k + 1) + i]);
-    for (int i = 0; i < j; ++i) {  // previous rotations
-      const cx<double> a = h[i], b = h[i + 1];
-      // [c s; -conj(s) c] with c real
-      h[i] = cs[i] * a + sn[i] * b;
-      h[i + 1] = cx<double>{-sn[i].re, sn[i].im} * a + cs[i] * b;
-    }
-    const cx<double> a = h[j], b = h[j + 1];
+    const cx<double> a = tcx(H[(int64_t)j * (k + 1) + j]), b = tcx(H[(int64_t)j * (k + 1) + j + 1]);
     const double na = sqrt(a.re * a.re + a.im * a.im), nb = sqrt(b.re * b.re + b.im * b.im);
     const double r = sqrt(na * na + nb * nb);
     if (r == 0.0) {
@@ -714,31 +709,37 @@ __global__ void k_cg_ls(int P, int k, const c128* __restrict__ Hm, const double*
       break;
     }
     const cx<double> ph = na > 0.0 ? cx<double>{a.re / na, a.im / na} : cx<double>{1.0, 0.0};
-    cs[j] = {na / r, 0.0};
-    // s = ph * conj(b) / r so that the rotated entry below vanishes
-    sn[j] = {(ph.re * b.re + ph.im * b.im) / r, (ph.im * b.re - ph.re * b.im) / r};
-    h[j] = {ph.re * r, ph.im * r};
-    const cx<double> gj = g[j];
-    g[j] = cs[j] * gj;
-    g[j + 1] = cx<double>{-sn[j].re, sn[j].im} * gj;
-    for (int i = 0; i <= j; ++i) R[j * (j + 1) / 2 + i] = h[i];
+    // [c s; -conj(s) c] with c real and s = ph * conj(b) / r, so that the
+    // rotated entry below the diagonal vanishes
+    const cx<double> cs = {na / r, 0.0};
+    const cx<double> sn = {(ph.re * b.re + ph.im * b.im) / r, (ph.im * b.re - ph.re * b.im) / r};
+    const cx<double> msn = {-sn.re, sn.im};
+    H[(int64_t)j * (k + 1) + j] = fcx(cx<double>{ph.re * r, ph.im * r});
+    for (int l = j + 1; l < k; ++l) {
+      c128* col = H + (int64_t)l * (k + 1);
+      const cx<double> u = tcx(col[j]), w = tcx(col[j + 1]);
+      col[j] = fcx(cs * u + sn * w);
+      col[j + 1] = fcx(msn * u + cs * w);
+    }
+    const cx<double> gj = tcx(G[(int64_t)j * P + c]);
+    G[(int64_t)j * P + c] = fcx(cs * gj);
+    G[(int64_t)(j + 1) * P + c] = fcx(msn * gj);
     if (nb == 0.0) {  // happy breakdown: exact in this space
       steps = j + 1;
       break;
     }
   }
-  cx<double> y[KMAX];
   for (int i = steps - 1; i >= 0; --i) {
-    cx<double> s = g[i];
-    for (int l = i + 1; l < steps; ++l) s = s - R[l * (l + 1) / 2 + i] * y[l];
-    const cx<double> d = R[i * (i + 1) / 2 + i];
+    cx<double> sum = tcx(G[(int64_t)i * P + c]);
+    for (int l = i + 1; l < steps; ++l) sum = sum - tcx(H[(int64_t)l * (k + 1) + i]) * tcx(Y[(int64_t)l * P + c]);
+    const cx<double> d = tcx(H[(int64_t)i * (k + 1) + i]);
     const double dd = d.re * d.re + d.im * d.im;
-    y[i] = {(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd};
+    Y[(int64_t)i * P + c] = fcx(cx<double>{(sum.re * d.re + sum.im * d.im) / dd, (sum.im * d.re - sum.re * d.im) / dd});
   }
-  for (int i = 0; i < k; ++i) Y[(int64_t)i * P + c] = i < steps ? fcx(y[i]) : c128{0.0, 0.0};
+  for (int i = steps; i < k; ++i) Y[(int64_t)i * P + c] = c128{0.0, 0.0};
 }
-void launch_cg_ls(int P, int k, const c128* H, const double* b2, c128* Y, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_ls, dim3((P + 63) / 64), dim3(64), 0, s, P, k, H, b2, Y);
+void launch_cg_ls(int P, int k, c128* H, const double* b2, c128* G, c128* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_ls, dim3((P + 63) / 64), dim3(64), 0, s, P, k, H, b2, G, Y);
 }
 
 }  // namespace helm

@@ -117,6 +117,8 @@ void launch_lazy_y(int P, int k, const double* nu, c128* Y, hipStream_t s);
 // Fixed-step per-column GMRES helpers for the coarsest grid.
 void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s);
 void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);
-void launch_cg_ls(int P, int k, const c128* H, const double* b2, c128* Y, hipStream_t s);
+// Per-column least squares of the fixed-step GMRES: H ((k+1) x k per column)
+// is rotated in place; G is scratch of (k+1) * P complex.
+void launch_cg_ls(int P, int k, c128* H, const double* b2, c128* G, c128* Y, hipStream_t s);
 
 }  // namespace helm

@@ -826,7 +826,7 @@ __global__ void k_net_input(int P, int c0, int nb, int D, Box bx, const S* __res
 }
 
 // e[n][c0 + b] = os[c0 + b] (out[b][v][0] + i out[b][v][1]); counts
-// non-finite outputs in *bad.
+// non-finite or implausibly large outputs in *bad.
 template <class S>
 __global__ void k_net_output(int P, int c0, int nb, int D, Box bx, const float* __restrict__ out,
                              const double* __restrict__ os, S* __restrict__ e, int* __restrict__ bad) {
@@ -838,7 +838,9 @@ __global__ void k_net_output(int P, int c0, int nb, int D, Box bx, const float* 
   const int x = (int)(n % bx.nx), y = (int)((n / bx.nx) % bx.ny), z = (int)(n / ((int64_t)bx.nx * bx.ny));
   const int64_t v = (int64_t)b * D * D * D + x + (int64_t)D * (y + (int64_t)D * z);
   const float o0 = out[2 * v], o1 = out[2 * v + 1];
-  if (!isfinite(o0) || !isfinite(o1)) atomicAdd(bad, 1);
+  // targets e / (H^2 rms) are of order one: an output beyond 1e4 in these
+  // units is as useless as a non-finite one and is counted with them
+  if (!(fabsf(o0) <= 1e4f) || !(fabsf(o1) <= 1e4f)) atomicAdd(bad, 1);
   using E = decltype(e->re);
   e[n * P + c0 + b] = S{(E)(os[c0 + b] * o0), (E)(os[c0 + b] * o1)};
 }
@@ -984,6 +986,7 @@ struct Net {
   c128* part = nullptr;
   c128* Gs = nullptr;
   int Pmax = 0;
+  uint64_t scratch_gen = 0;  // bumped whenever the per-column scratch moves
   int* bad = nullptr;
   int* hbad = nullptr;     // pinned
   double* hn2 = nullptr;   // pinned [Pmax]
@@ -1378,6 +1381,7 @@ static helm_status ensure_cols(Net* n, int P) {
   n->bad = reinterpret_cast<int*>(n->os + P);
   LCHECK(hipHostMalloc(&n->hn2, 8 * (size_t)P));
   n->Pmax = P;
+  ++n->scratch_gen;
   return HELM_OK;
 }
 
@@ -1398,17 +1402,33 @@ static void apply_t(Net* n, int P, const S* f, S* out, hipStream_t s) {
   }
 }
 
-bool apply(Net* n, int P, const void* f, void* out, hipStream_t s) {
-  if (!n->bound || ensure_cols(n, P) != HELM_OK) return false;
+helm_status prepare(Net* n, int P) {
+  if (!n->bound) return fail(HELM_ERR_INVALID_ARG, "network is not bound to a coarsest grid");
+  return ensure_cols(n, P);
+}
+
+void apply_async(Net* n, int P, const void* f, void* out, hipStream_t s) {
   column_scales(n, P, f, s);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, n->bad);
   if (n->pf == P64)
     apply_t(n, P, static_cast<const c128*>(f), static_cast<c128*>(out), s);
   else
     apply_t(n, P, static_cast<const c64*>(f), static_cast<c64*>(out), s);
-  if (hipMemcpyAsync(n->hbad, n->bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
-  if (hipStreamSynchronize(s) != hipSuccess) return false;
-  return *n->hbad == 0;
+}
+
+uint64_t scratch_gen(const Net* n) { return n->scratch_gen; }
+
+int bad_count(Net* n, hipStream_t s) {
+  if (!n->bad) return 0;
+  if (hipMemcpyAsync(n->hbad, n->bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  return *n->hbad;
+}
+
+bool apply(Net* n, int P, const void* f, void* out, hipStream_t s) {
+  if (!n->bound || ensure_cols(n, P) != HELM_OK) return false;
+  apply_async(n, P, f, out, s);
+  return bad_count(n, s) == 0;
 }
 
 helm_status capture_begin(Net* n, int max_pairs) {

@@ -50,8 +50,18 @@ helm_status loss_grad(Net* n, int B, const float* x, const float* target, const 
 // Binds the network to a coarsest grid (input channels, scales, mask).
 helm_status bind(Net* n, const Coarse& g, hipStream_t s);
 // out = network correction for the P columns of f ([Nc][P] fields of the
-// bound precision). Returns false when an output is not finite (host sync).
+// bound precision). Returns false when an output is not finite or beyond 1e4 in
+// the normalised units (host sync).
 bool apply(Net* n, int P, const void* f, void* out, hipStream_t s);
+// The same without the host check (for graph capture): scratch for P columns
+// must exist (prepare), and the non-finite count stays on the device until
+// bad_count reads it (synchronises s; -1 on a device error).
+helm_status prepare(Net* n, int P);
+void apply_async(Net* n, int P, const void* f, void* out, hipStream_t s);
+int bad_count(Net* n, hipStream_t s);
+// Changes whenever prepare/apply move the per-column scratch (captured graphs
+// that reference it are then stale).
+uint64_t scratch_gen(const Net* n);
 
 // Training pairs (f, e = exact coarsest solution) of the bound grid, kept by
 // reservoir sampling in a pool of max_pairs volumes.

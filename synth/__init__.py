@@ -216,4 +216,33 @@ def config(k: int, n: int | None = None, nsrc: tuple | None = None,
     raise ValueError(k)
 
 
+def batch_instances(count: int = 48, seed: int = 4000, sizes_2d=None, sizes_3d=None,
+                    ppw: tuple = (8.0, 12.0)) -> list:
+    """Independent uneven instances (the batched workload), one seed each.
+
+    Instance k uses seed ``seed + k``. The first half are 2D with n drawn from
+    64, 96, ..., 512 cells, the second half 3D with n from 64, 96, 128, 160.
+    Each has 4-8 random layers (3D: plus the 10% smooth perturbation),
+    ``ppw`` points per wavelength (default 8-12), a 16-cell (2D) or 12-cell
+    (3D) absorbing layer and 1-32 surface sources spread along x; FGMRES(5).
+    The cycle depth keeps at least 4 points per wavelength on every smoothed
+    level: 3 levels from 8 points per wavelength up, 2 below.
+    """
+    sizes_2d = sizes_2d or list(range(64, 513, 32))
+    sizes_3d = sizes_3d or [64, 96, 128, 160]
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng(seed + k)
+        dim = 2 if k < count // 2 else 3
+        n = int(rng.choice(sizes_2d if dim == 2 else sizes_3d))
+        nl = int(rng.integers(4, 9))
+        w = float(rng.uniform(*ppw))
+        nsrc = int(rng.integers(1, 33))
+        v = layered_model(dim, n, seed + k, nlayers=nl, pert=0.0 if dim == 2 else 0.1)
+        width = 16 if dim == 2 else 12
+        grid = (nsrc,) if dim == 2 else (nsrc, 1)
+        out.append(_make(dim, n, v, width, w, grid, f"batch{k}", 3 if w >= 8.0 else 2, 5))
+    return out
+
+
 CONFIGS = (1, 2, 3)
