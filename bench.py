@@ -129,7 +129,8 @@ def run_batch(args, pk, synth, np, torch):
     t_setup = time.perf_counter() - t0
     note(f"setup done in {t_setup:.1f} s")
     Us = [torch.zeros_like(Q) for Q in Qs]
-    opts = dict(tol=1e-6, restart=5, max_cycles=args.max_cycles, block_size=1, reorth=0)
+    # the 2D 512^2 instances at 8-10 points per wavelength need up to ~2500 cycles
+    opts = dict(tol=1e-6, restart=5, max_cycles=max(args.max_cycles, 5000), block_size=1, reorth=0)
     pk.helm_solve_batch(hs, Qs, Us, max_threads=args.threads, **opts)  # warm-up: tiles, buffers
     torch.cuda.synchronize()
     note("warm-up batch done")

@@ -187,8 +187,11 @@ helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* 
  * autotuner if this width has not been tuned (timing each candidate on the
  * handle's buffers; cached in the JSON-lines file named by HELM_TUNE_CACHE;
  * HELM_AUTOTUNE=0 keeps the default) and returns the choice;
- * helm_set_fine_tile forces one (ry in {1,2,4}, zc >= 1). Results are
- * bitwise identical for every tile. */
+ * helm_set_fine_tile forces one (ry in {1,2,4}: rows per lane of the
+ * register-blocked kernel; ry = 16 or 8: the LDS-blocked kernel on 16 x 16 or
+ * 16 x 8 tiles, used where the block width is a multiple of 128 B of
+ * right-hand sides;
+ * zc >= 1). Results are bitwise identical for every tile. */
 helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]);
 helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]);
 

@@ -494,7 +494,7 @@ static bool tune_cache_lookup(const std::string& key, FineTile* t) {
     char k[200];
     int ry, zc;
     if (std::sscanf(line, " {\"key\": \"%199[^\"]\", \"ry\": %d, \"zc\": %d", k, &ry, &zc) == 3 && key == k &&
-        (ry == 1 || ry == 2 || ry == 4) && zc > 0) {
+        (ry == 1 || ry == 2 || ry == 4 || ry == 8 || ry == 16) && zc > 0) {
       *t = FineTile{ry, zc};
       found = true;  // the last entry for a key wins
     }
@@ -532,13 +532,15 @@ static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
   hipEvent_t a, b;
   HCHECK(hipEventCreate(&a));
   HCHECK(hipEventCreate(&b));
-  const int rys[3] = {1, 2, 4};
+  // rows per lane of the register-blocked kernel, or 8 / 16: the LDS-blocked
+  // kernel on 16 x 8 / 16 x 16 tiles (k_fine_t16)
+  const int rys[5] = {1, 2, 4, 8, 16};
   const int zcs[3] = {16, 32, 64};
   double best = 1e30;
   FineTile bt = c->tile;
   const bool was = c->prof;
   c->prof = false;
-  for (int ri = 0; ri < 3; ++ri)
+  for (int ri = 0; ri < 5; ++ri)
     for (int zi = 0; zi < 3; ++zi) {
       set_fine_tile(FineTile{rys[ri], zcs[zi]});
       level_op(c, 0, 2, P, L.U0, L.F, L.U1, s);  // warm-up
@@ -860,7 +862,8 @@ helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]) {
 
 helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]) {
   if (!h || !tile || nrhs < 1 || nrhs > 256) return fail(HELM_ERR_INVALID_ARG, "bad argument");
-  if (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4) || tile[1] < 1) return fail(HELM_ERR_INVALID_ARG, "bad tile");
+  if (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4 || tile[0] == 8 || tile[0] == 16) || tile[1] < 1)
+    return fail(HELM_ERR_INVALID_ARG, "bad tile");
   clear_graphs(h);
   h->tileP = padP(nrhs);
   h->tile = FineTile{tile[0], tile[1]};

@@ -11,6 +11,8 @@
 //  - damped Jacobi (section 5.3), residual, full-weighting restriction and
 //    d-linear prolongation (section "Solving the Helmholtz equation for
 //    multiple right hand sides").
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -445,6 +447,168 @@ static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 25
 // Tile shape of the 3D marching kernel (set by the host's autotuner):
 // y rows per lane and z planes per chunk. Every shape computes each output
 // from the same loads in the same order, so results are bitwise identical.
+// ---------------------------------------------------------------------------
+// 3D fine-level operator, 2.5D blocking through LDS: a workgroup of 64*TY
+// lanes owns a 16 x TY tile of grid columns (TY = 16 or 8) for one group of
+// CG right-hand sides (128 B per point: 16 complex64 or 8 complex128) and
+// walks a chunk of z planes. Lane (point q, slot sl) keeps u(z-1), u(z+1) of
+// its CG/4 columns in registers; plane z of the tile and its one-point ring
+// are staged in LDS, so every in-plane neighbour comes from LDS and u is read
+// from memory (18 (TY+2)) / (16 TY) times per plane (1.27 at TY = 16, 1.41 at
+// TY = 8) instead of once per neighbouring tile in L2. The sums are formed in
+// the order of k_fine_zm, so the results are bitwise those of every other
+// tile shape. Modes APPLY, RESID, JAC.
+// ---------------------------------------------------------------------------
+constexpr int TB = 16;  // tile edge along x (points)
+
+template <class S, class T, int MODE, int TY>
+__global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
+                                                      const S* __restrict__ f, S* __restrict__ out,
+                                                      const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw,
+                                                      T ihx, T ihy, T ihz) {
+  constexpr int CG = 128 / (int)sizeof(S);  // columns per group
+  constexpr int K = CG / 4;                  // columns per lane
+  constexpr int HX = TB + 2, HY = TY + 2;
+  constexpr int RING = 2 * HX + 2 * TY;     // ring points
+  // Slot-major LDS: the 32 B of a lane's columns for point p sit at
+  // sm_slot[sl] + 32 p, with the four slot planes 256-B aligned plus 0, 16,
+  // 128, 144 B, so the 16 lanes of one 128-bit LDS pass (4 points x 4 slots)
+  // hit 16 distinct 16-B bank groups.
+  constexpr int NPT = HX * HY;
+  constexpr int PSR = (NPT * 32 + 255) / 256 * 256;
+  __shared__ __attribute__((aligned(256))) unsigned char smraw[4 * PSR + 256];
+  const int64_t t0 = (int64_t)(blockIdx.x % 8) * zt.per + blockIdx.x / 8;
+  if (t0 >= zt.ntiles) return;  // whole workgroup leaves together
+  int64_t t = t0;
+  const int yb = (int)(t % nyb);
+  t /= nyb;
+  const int xb = (int)(t % zt.nxb);
+  t /= zt.nxb;
+  const int zc = (int)(t % zt.nzc);
+  const int cgi = (int)(t / zt.nzc);
+  const int q = threadIdx.x >> 2, sl = threadIdx.x & 3;
+  const int px = q % TB, py = q / TB;
+  const int x = xb * TB + px, y = yb * TY + py;
+  const bool inb = x < g.nx && y < g.ny;
+  const int c = cgi * CG + sl * K;
+  const int z0 = zc * zt.zc;
+  const int z1 = z0 + zt.zc < g.nz ? z0 + zt.zc : g.nz;
+  const int64_t plane = (int64_t)g.nx * g.ny, sz = plane * g.P;
+  // ring point of this lane (lanes 0 .. 4*RING-1): halo coordinates (hx, hy)
+  const int rp = threadIdx.x >> 2;
+  int hx, hy;
+  if (rp < HX) {
+    hx = rp;
+    hy = 0;
+  } else if (rp < 2 * HX) {
+    hx = rp - HX;
+    hy = HY - 1;
+  } else if (rp < 2 * HX + TY) {
+    hx = 0;
+    hy = rp - 2 * HX + 1;
+  } else {
+    hx = HX - 1;
+    hy = rp - 2 * HX - TY + 1;
+  }
+  const int rx = xb * TB + hx - 1, ry = yb * TY + hy - 1;
+  const bool ring = rp < RING;
+  const bool rin = ring && rx >= 0 && rx < g.nx && ry >= 0 && ry < g.ny;
+  const int64_t icol = (int64_t)y * g.nx + x;    // own (x, y) column index
+  const int64_t rcol = (int64_t)ry * g.nx + rx;  // ring (x, y) column index
+  // TY = 8 prefetches one plane ahead (u(z+2), the ring of z+1, f(z+1) are
+  // in flight while plane z is computed); TY = 16 keeps the registers low
+  constexpr bool PF = TY == 8;
+  cx<T> um[K], uc[K], un[K], unn[K], rc[K], rn[K], fc[K], fn[K];
+  const S* up = u + ((int64_t)z0 * plane + icol) * g.P + c;
+  const S* rpp = u + ((int64_t)z0 * plane + rcol) * g.P + c;
+  const S* fp = f + ((int64_t)z0 * plane + icol) * g.P + c;
+  ldKz<K, S, T>(up - sz, inb && z0 > 0, um);
+  ldKz<K, S, T>(up, inb, uc);
+  if (PF) {
+    ldKz<K, S, T>(up + sz, inb && z0 + 1 < g.nz, un);
+    ldKz<K, S, T>(rpp, rin, rc);
+    if (MODE != 0) ldKz<K, S, T>(fp, inb, fc);
+  }
+  cx<T>* sm = reinterpret_cast<cx<T>*>(smraw + sl * PSR + (sl & 1) * 16 + (sl >> 1) * 128);
+  const int me = ((py + 1) * HX + px + 1) * K;  // own point, in units of cx<T>
+  const int ro = (hy * HX + hx) * K;
+  constexpr int RX = K, RYS = HX * K;           // x and y neighbour strides
+  for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
+    if (PF) {
+      const bool more = z + 1 < z1;
+      ldKz<K, S, T>(up + 2 * sz, inb && z + 2 < g.nz, unn);
+      ldKz<K, S, T>(rpp + sz, rin && more, rn);
+      if (MODE != 0) ldKz<K, S, T>(fp + sz, inb && more, fn);
+    } else {
+      ldKz<K, S, T>(up + sz, inb && z + 1 < g.nz, un);
+      ldKz<K, S, T>(rpp, rin, rc);
+    }
+    if (ring) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) sm[ro + k] = rc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) sm[me + k] = uc[k];
+    __syncthreads();
+    if (inb) {
+      const int64_t ir = (int64_t)z * plane + icol;
+      const cx<T> d = dg[ir];
+      cx<T> acc[K], sum[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc[k] = d * uc[k];
+        sum[k] = ihz * (um[k] + un[k]) + ihy * (sm[me - RYS + k] + sm[me + RYS + k]);
+        sum[k] = sum[k] + ihx * sm[me - RX + k];
+        sum[k] = sum[k] + ihx * sm[me + RX + k];
+        acc[k] = acc[k] - sum[k];
+      }
+      const int64_t o = ir * g.P + c;
+      if (MODE == 0) {
+        stK<K, S, T>(out + o, acc);
+      } else {
+        if (!PF) ldK<K, S, T>(f + o, fc);
+        cx<T> res[K];
+        if (MODE == 1) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = fc[k] - acc[k];
+        } else {
+          const cx<T> w = dw[ir];
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fc[k] - acc[k]);
+        }
+        stK<K, S, T>(out + o, res);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      um[k] = uc[k];
+      uc[k] = un[k];
+      if (PF) {
+        un[k] = unn[k];
+        rc[k] = rn[k];
+        fc[k] = fn[k];
+      }
+    }
+  }
+}
+
+template <class S, class T, int MODE, int TY>
+static void fine_t16_launch(const Geo& g, const void* u, const void* f, void* out, const void* dg, const void* dw,
+                            const double ih[3], int zc, hipStream_t s) {
+  constexpr int CG = 128 / (int)sizeof(S);
+  ZTiles zt;
+  zt.nxb = (g.nx + TB - 1) / TB;
+  const int nyb = (g.ny + TY - 1) / TY;
+  zt.zc = zc;
+  zt.nzc = (g.nz + zt.zc - 1) / zt.zc;
+  zt.ntiles = (int64_t)zt.nxb * nyb * zt.nzc * (g.P / CG);
+  zt.per = (int)((zt.ntiles + 7) / 8);
+  hipLaunchKernelGGL((k_fine_t16<S, T, MODE, TY>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(64 * TY), 0, s, g,
+                     zt, nyb, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
+                     (T)ih[1], (T)ih[2]);
+}
+
 static thread_local FineTile g_tile = {4, 32};
 void set_fine_tile(FineTile t) { g_tile = t; }
 FineTile get_fine_tile() { return g_tile; }
@@ -475,6 +639,17 @@ static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, v
     // at 5-6 waves per SIMD); otherwise the tuned shape
     const int ry = sizeof(SO) > sizeof(SU) || (sizeof(T) == 8 && K >= 2) ? 1 : g_tile.ry;
     const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
+    if constexpr (std::is_same<SU, SF>::value && std::is_same<SU, SO>::value &&
+                  ((std::is_same<SU, c64>::value && std::is_same<T, float>::value) ||
+                   (std::is_same<SU, c128>::value && std::is_same<T, double>::value))) {
+      if ((ry == 16 || ry == 8) && g.P % (128 / (int)sizeof(SU)) == 0 && MODE != 3) {
+        if (ry == 16)
+          fine_t16_launch<SU, T, MODE, 16>(g, u, f, out, dg, dw, ih, zc, s);
+        else
+          fine_t16_launch<SU, T, MODE, 8>(g, u, f, out, dg, dw, ih, zc, s);
+        return;
+      }
+    }
     if (ry == 1)
       fine_zm_launch<SU, SF, SO, T, MODE, 1>(g, L, u, f, out, dg, dw, ih, zc, s);
     else if (ry == 2)

@@ -244,19 +244,23 @@ def test_not_converged_reports_last_iterate():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fine_tile_choices_are_bitwise_identical(precision):
-    """Every tile shape of the 3D marching kernel computes each output from the
-    same loads in the same order: the cycle output must not change by a bit."""
+@pytest.mark.parametrize("nrhs", [6, 16])
+def test_fine_tile_choices_are_bitwise_identical(precision, nrhs):
+    """Every tile shape of the 3D finest-level kernels (register-blocked rows,
+    or the LDS-blocked 16 x 16 / 16 x 8 tiles where the block holds whole 128 B column
+    groups: 16 RHS in mixed, 8 in FP64) computes each output from the same
+    values in the same order: the cycle output must not change by a bit. The
+    47^3 grid leaves ragged x/y tiles and z chunks."""
     p = synth.config(2, n=48, nsrc=(3, 2), levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
-    F = dev(crand(6, p.N))
+    F = dev(crand(nrhs, p.N))
     outs = []
-    for ry, zc in [(1, 16), (2, 32), (4, 64), (4, 7)]:
-        pk.helm_set_fine_tile(hd, 6, ry, zc)
+    for ry, zc in [(1, 16), (2, 32), (4, 64), (4, 7), (16, 16), (16, 7), (16, 64), (8, 32), (8, 5)]:
+        pk.helm_set_fine_tile(hd, nrhs, ry, zc)
         Z = torch.empty_like(F)
         pk.helm_precond(hd, F, Z)
         outs.append(host(Z))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    ry, zc = pk.helm_fine_tile(hd, 6)
-    assert ry in (1, 2, 4) and zc >= 1
+    ry, zc = pk.helm_fine_tile(hd, nrhs)
+    assert ry in (1, 2, 4, 8, 16) and zc >= 1
