@@ -43,6 +43,11 @@ def fine_sweep_bytes(prec, N, P):
     return N * (3 * s * P + 2 * coef)
 
 
+def note(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def committed_traffic(precision, n, nrhs, tile):
     """HBM bytes per launch of the finest-level sweep from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel
@@ -112,9 +117,6 @@ def run_batch(args, pk, synth, np, torch):
     3D 64^3-160^3, 1-32 sources each), mixed precision, solved concurrently by
     helm_solve_batch; the same instances solved one after another are timed
     beside it. Returns the JSON line's dict."""
-    def note(msg):
-        print(f"[batch] {msg}", file=sys.stderr, flush=True)
-
     probs = synth.batch_instances()
     note(f"{len(probs)} instances generated")
     hs, Qs = [], []
@@ -226,7 +228,9 @@ def main():
     p = synth.config(3, n=args.n)
     net_blob, net_info = None, None
     if args.coarse == "learned":
+        note(f"training the coarsest-grid network on a {args.train_n}^3 instance")
         net_blob, net_info = train_coarse_net(args, pk, synth, np, torch)
+        note(f"trained in {net_info['train_s']} s, loss {net_info['loss_first']} -> {net_info['loss_last']}")
     t0 = time.perf_counter()
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision=args.precision, coarse=args.coarse, coarse_iters=args.coarse_iters,
@@ -241,8 +245,10 @@ def main():
         return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
                                    block_size=args.block_size, reorth=args.reorth)
 
+    note("tuned; warm-up")
     for _ in range(args.warmup):
         step()
+    note("timed steps")
     torch.cuda.synchronize()
     pk.helm_profile_enable(hd, True)
     torch.cuda.synchronize()
@@ -294,8 +300,10 @@ def main():
     if net_info is not None:
         out["config"]["coarse_net"] = net_info
     if not args.no_fp64_compare and args.precision == "mixed":
+        note(f"{value:.3f} RHS/s; FP64 comparison")
         out["config"]["fp64_compare"] = fp64_compare(args, p, Q, pk, torch)
     if not args.no_cpu_baseline:
+        note("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, cycles[0], args.cpu_iters)
     print(json.dumps(out), flush=True)
 
