@@ -244,10 +244,17 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   } else {
     zero_field(c, l, P, a, s);
   }
-  level_op(c, l, 1, P, a, f, L.Rr, s);
   Level& C = c->lv[l + 1];
   const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
-  {
+  bool fused = false;
+  if (l == 0 && c->dim == 3) {
+    // residual and restriction in one pass (counted as the fine residual)
+    Prof pr(c, HELM_K_FINE_RESID, s);
+    const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+    fused = launch_resid_restrict(pf, pc, pt, L.geo(P), C.geo(P), a, f, C.F, diag, L.ih, s);
+  }
+  if (!fused) {
+    level_op(c, l, 1, P, a, f, L.Rr, s);
     Prof pr(c, HELM_K_TRANSFER, s);
     launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
   }

@@ -25,6 +25,11 @@ struct FineTile {
   int ry, zc;
 };
 void set_fine_tile(FineTile t);
+// Fused 3D finest-level residual f - M u and full-weighting restriction into
+// the coarse field rc (bitwise equal to the two separate kernels). Runs and
+// returns true only for the LDS-blocked tiles and supported precisions.
+bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* u, const void* f,
+                           void* rc, const void* dg, const double ih[3], hipStream_t s);
 FineTile get_fine_tile();
 // mode: 0 apply (out = A u), 1 residual (out = f - A u),
 //       2 Jacobi (out = u + dw (f - A u)), 3 zero-guess Jacobi (out = dw f).

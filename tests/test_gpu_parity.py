@@ -244,23 +244,38 @@ def test_not_converged_reports_last_iterate():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("nrhs", [6, 16])
+@pytest.mark.parametrize("nrhs", [6, 16, 64])
 def test_fine_tile_choices_are_bitwise_identical(precision, nrhs):
     """Every tile shape of the 3D finest-level kernels (register-blocked rows,
-    or the LDS-blocked 16 x 16 / 16 x 8 tiles where the block holds whole 128 B column
-    groups: 16 RHS in mixed, 8 in FP64) computes each output from the same
-    values in the same order: the cycle output must not change by a bit. The
-    47^3 grid leaves ragged x/y tiles and z chunks."""
+    or the LDS-blocked 16 x 16 / 16 x 8 tiles where the block holds whole
+    128 B column groups: 16 RHS in mixed, 8 in FP64; with those tiles the
+    residual and the restriction run fused) computes each output from the
+    same values in the same order: the cycle output must not change by a
+    bit. Each tile gets a fresh handle (no buffer keeps values of another
+    tile's run); inputs are dense random and sparse point sources (the
+    benchmark's right-hand sides). The 47^3 grid leaves ragged x/y tiles,
+    coarse tiles and z chunks."""
     p = synth.config(2, n=48, nsrc=(3, 2), levels=3)
-    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
     F = dev(crand(nrhs, p.N))
+    S = np.zeros((nrhs, p.N), complex)
+    for c in range(nrhs):
+        S[c, (37 * c + 11) % p.N] = 1e6 * (1 + 1j) / (c + 1)
+        S[c, (c * 48 * 48) % p.N] = -2e6  # on the first planes and faces
+    S = dev(S)
     outs = []
     for ry, zc in [(1, 16), (2, 32), (4, 64), (4, 7), (16, 16), (16, 7), (16, 64), (8, 32), (8, 5)]:
+        hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
         pk.helm_set_fine_tile(hd, nrhs, ry, zc)
-        Z = torch.empty_like(F)
-        pk.helm_precond(hd, F, Z)
-        outs.append(host(Z))
+        res = []
+        for X in (F, S):
+            Z = torch.empty_like(X)
+            pk.helm_precond(hd, X, Z)
+            res.append(host(Z))
+        outs.append(res)
+        del hd
     for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
     ry, zc = pk.helm_fine_tile(hd, nrhs)
     assert ry in (1, 2, 4, 8, 16) and zc >= 1
