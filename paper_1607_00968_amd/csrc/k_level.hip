@@ -821,6 +821,119 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
                      (T)ih[2]);
 }
 
+// ---------------------------------------------------------------------------
+// 3D Galerkin-level operator (27-point stencil), z-marching through LDS: a
+// 256-lane workgroup owns an 8 x 8 tile of grid columns for one 128-byte group
+// of right-hand sides (32 BF16 pairs, 16 complex64 or 8 complex128) and a
+// chunk of z planes. The planes z-1, z, z+1 of the tile with its one-point
+// ring sit in a three-plane LDS ring in storage precision; each step loads
+// only plane z+2's tile. The 27 products are accumulated in the order of
+// k_gal, so results are bitwise those of k_gal. Modes APPLY, RESID, JAC.
+// ---------------------------------------------------------------------------
+constexpr int GT = 8;            // tile edge
+constexpr int GH = GT + 2;       // with the ring
+constexpr int GZC = 16;          // planes per chunk
+
+template <class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_gal_lds(Geo g, int ncg, int nxb, int nyb, int nzc, int64_t ntiles, int per,
+                                                 const S* __restrict__ u, const S* __restrict__ f,
+                                                 S* __restrict__ out, const cx<T>* __restrict__ st,
+                                                 const cx<T>* __restrict__ dw) {
+  constexpr int CB = 128;                          // bytes per point and group
+  constexpr int CG = CB / (int)sizeof(S);          // columns per group
+  constexpr int K = CG / 4;                        // columns per lane
+  constexpr int U16 = CB / 16;                     // 16-byte units per point and group
+  constexpr int R = St<S>::R;                      // columns per 16-byte unit
+  __shared__ uint4 sp[3][GH * GH * U16];
+  const int64_t t0 = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t0 >= ntiles) return;  // whole workgroup leaves together
+  int64_t t = t0;
+  const int cgi = (int)(t % ncg);
+  t /= ncg;
+  const int yb = (int)(t % nyb);
+  t /= nyb;
+  const int xb = (int)(t % nxb);
+  const int zci = (int)(t / nxb);
+  const int z0 = zci * GZC, z1 = z0 + GZC < g.nz ? z0 + GZC : g.nz;
+  const int q = threadIdx.x >> 2, sl = threadIdx.x & 3;
+  const int px = q % GT, py = q / GT;
+  const int x = xb * GT + px, y = yb * GT + py;
+  const bool inb = x < g.nx && y < g.ny;
+  const int c = cgi * CG + sl * K;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  // loads one plane's tile (with the ring) into LDS buffer b; zero outside the grid
+  auto load_plane = [&](int zz, int b) {
+    for (int e = threadIdx.x; e < GH * GH * U16; e += 256) {
+      const int hp = e / U16, w = e - hp * U16;
+      const int gx = xb * GT + hp % GH - 1, gy = yb * GT + hp / GH - 1;
+      uint4 val{0u, 0u, 0u, 0u};
+      if (zz >= 0 && zz < g.nz && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny)
+        val = *reinterpret_cast<const uint4*>(u + ((int64_t)zz * plane + (int64_t)gy * g.nx + gx) * g.P + cgi * CG +
+                                              w * R);
+      sp[b][e] = val;
+    }
+  };
+  load_plane(z0 - 1, (z0 + 2) % 3);
+  load_plane(z0, z0 % 3);
+  const int me = ((py + 1) * GH + px + 1) * U16 + sl * (K / R);
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 1, (z + 1) % 3);
+    __syncthreads();
+    if (inb) {
+      const int64_t i = (int64_t)z * plane + (int64_t)y * g.nx + x;
+      const cx<T>* spn = st + i * 27;
+      cx<T> acc[K], nb[K], uc[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] = {(T)0, (T)0};
+#pragma unroll 3
+      for (int o = 0; o < 27; ++o) {
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        const uint4* src = &sp[(z + oz + 3) % 3][me + (oy * GH + ox) * U16];
+#pragma unroll
+        for (int k = 0; k < K; k += R) ld16<T>(reinterpret_cast<const S*>(src + k / R), nb + k);
+        if (o == 13) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) uc[k] = nb[k];
+        }
+        const cx<T> a = spn[o];
+#pragma unroll
+        for (int k = 0; k < K; ++k) cfma(acc[k], a, nb[k]);
+      }
+      const int64_t base = i * g.P + c;
+      if (MODE == 0) {
+        stK<K, S, T>(out + base, acc);
+      } else {
+        cx<T> fv[K], res[K];
+        ldK<K, S, T>(f + base, fv);
+        if (MODE == 1) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = fv[k] - acc[k];
+        } else {
+          const cx<T> w = dw[i];
+#pragma unroll
+          for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
+        }
+        stK<K, S, T>(out + base, res);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class S, class T, int MODE>
+static bool gal_lds_launch(const Geo& g, const void* u, const void* f, void* out, const void* st, const void* dw,
+                           hipStream_t s) {
+  constexpr int CG = 128 / (int)sizeof(S);
+  if (g.P % CG != 0) return false;
+  const int ncg = g.P / CG;
+  const int nxb = (g.nx + GT - 1) / GT, nyb = (g.ny + GT - 1) / GT, nzc = (g.nz + GZC - 1) / GZC;
+  const int64_t ntiles = (int64_t)ncg * nxb * nyb * nzc;
+  const int per = (int)((ntiles + 7) / 8);
+  hipLaunchKernelGGL((k_gal_lds<S, T, MODE>), dim3((unsigned)(8 * (int64_t)per)), dim3(256), 0, s, g, ncg, nxb, nyb,
+                     nzc, ntiles, per, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)st, (const cx<T>*)dw);
+  return true;
+}
+
 static thread_local FineTile g_tile = {4, 32};
 void set_fine_tile(FineTile t) { g_tile = t; }
 FineTile get_fine_tile() { return g_tile; }
@@ -949,6 +1062,17 @@ static void gal_dispatch(int dim, const Geo& g, const void* u, const void* f, vo
 template <class S, class T>
 static void gal_mode(int mode, int dim, const Geo& g, const void* u, const void* f, void* out, const void* st,
                      const void* dw, hipStream_t s) {
+  // the LDS-blocked family of tiles also takes the LDS form of the 27-point
+  // stencil (bitwise the same results)
+  if (dim == 3 && (g_tile.ry == 8 || g_tile.ry == 16) && mode != 3) {
+    bool ran = false;
+    switch (mode) {
+      case 0: ran = gal_lds_launch<S, T, 0>(g, u, f, out, st, dw, s); break;
+      case 1: ran = gal_lds_launch<S, T, 1>(g, u, f, out, st, dw, s); break;
+      default: ran = gal_lds_launch<S, T, 2>(g, u, f, out, st, dw, s); break;
+    }
+    if (ran) return;
+  }
   switch (mode) {
     case 0: gal_dispatch<S, T, 0>(dim, g, u, f, out, st, dw, s); break;
     case 1: gal_dispatch<S, T, 1>(dim, g, u, f, out, st, dw, s); break;
