@@ -207,6 +207,7 @@ enum {
   HELM_K_GRAM,           /* block Gram products and column norms */
   HELM_K_UPDATE,         /* block updates W -= V H, V = W R^-1, X += Z Y */
   HELM_K_FINE_SWEEP0,    /* the first (zero initial guess) sweep on the finest level */
+  HELM_K_FINE_PROSWEEP,  /* the first post-smoothing sweep with the prolongation fused in */
   HELM_K_NCLASS
 };
 typedef struct {

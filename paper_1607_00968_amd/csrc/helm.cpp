@@ -266,11 +266,22 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
     cycle_rec(c, l + 1, P, c->kbuf[l + 1], C.U1, C.F, s);
     field_axpy(c, l + 1, P, C.U1, C.U0, s);
   }
-  {
+  int k0 = 0;
+  if (l == 0 && c->dim == 3 && npost >= 1) {
+    // prolongation and correction fused into the first post-smoothing sweep:
+    // b = JAC(a + P e); a itself is not updated (the next sweep overwrites it)
+    Prof pr(c, HELM_K_FINE_PROSWEEP, s);
+    const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+    if (launch_prolong_sweep(pc, pf, pt, L.geo(P), C.geo(P), C.U0, a, f, b, diag, level_dw(c, 0), L.ih, s)) {
+      std::swap(a, b);
+      k0 = 1;
+    }
+  }
+  if (k0 == 0) {
     Prof pr(c, HELM_K_TRANSFER, s);
     launch_prolong_add(pc, pf, pt, c->dim, L.geo(P), C.geo(P), C.U0, a, s);
   }
-  for (int k = 0; k < npost; ++k) {
+  for (int k = k0; k < npost; ++k) {
     level_op(c, l, 2, P, a, f, b, s);
     std::swap(a, b);
   }

@@ -463,11 +463,64 @@ static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 25
 // ---------------------------------------------------------------------------
 constexpr int TB = 16;  // tile edge along x (points)
 
-template <class S, class T, int MODE, int TY>
+// Parents of fine index i along one axis in registers (the order and weights
+// of parents(): the lower parent first).
+struct Par {
+  int p0, p1, n;
+  float w0, w1;
+};
+__device__ inline Par par_of(int i, int nc) {
+  Par r;
+  if (i & 1) {
+    r.p0 = (i - 1) >> 1;
+    r.w0 = 1.f;
+    r.p1 = r.p0;
+    r.w1 = 0.f;
+    r.n = 1;
+    return r;
+  }
+  const bool lo = i / 2 - 1 >= 0, hi = i / 2 < nc;
+  r.p0 = lo ? i / 2 - 1 : i / 2;
+  r.p1 = i / 2;
+  r.w0 = r.w1 = 0.5f;
+  r.n = (lo ? 1 : 0) + (hi ? 1 : 0);
+  return r;
+}
+
+// u with the coarse-grid correction added on the fly (PRO): value of u + P e
+// at fine point (x, y, z), the terms in the order of k_prolong_add.
+template <int K, class S, class SC, class T, int PRO>
+__device__ inline void ld_u(const S* p, bool ok, int x, int y, int z, const SC* ec, const Geo& gc, int c, cx<T>* o) {
+  ldKz<K, S, T>(p, ok, o);
+  if (!PRO || !ok) return;
+  const Par ax = par_of(x, gc.nx), ay = par_of(y, gc.ny), az = par_of(z, gc.nz);
+  cx<T> v[K];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    if (a >= az.n) break;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (b >= ay.n) break;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (e >= ax.n) break;
+        const float wx = e ? ax.w1 : ax.w0, wy = b ? ay.w1 : ay.w0, wz = a ? az.w1 : az.w0;
+        const T w = (T)(wx * wy * wz);
+        const int cx_ = e ? ax.p1 : ax.p0, cy_ = b ? ay.p1 : ay.p0, cz_ = a ? az.p1 : az.p0;
+        const int64_t ci = ((int64_t)cz_ * gc.ny + cy_) * gc.nx + cx_;
+        ldK<K, SC, T>(ec + ci * gc.P + c, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) o[k] = o[k] + w * v[k];
+      }
+    }
+  }
+}
+
+template <class S, class T, int MODE, int TY, class SC = S, int PRO = 0>
 __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
                                                       const S* __restrict__ f, S* __restrict__ out,
                                                       const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw,
-                                                      T ihx, T ihy, T ihz) {
+                                                      T ihx, T ihy, T ihz, const SC* __restrict__ ec, Geo gc) {
   constexpr int CG = 128 / (int)sizeof(S);  // columns per group
   constexpr int K = CG / 4;                  // columns per lane
   constexpr int HX = TB + 2, HY = TY + 2;
@@ -524,11 +577,11 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   const S* up = u + ((int64_t)z0 * plane + icol) * g.P + c;
   const S* rpp = u + ((int64_t)z0 * plane + rcol) * g.P + c;
   const S* fp = f + ((int64_t)z0 * plane + icol) * g.P + c;
-  ldKz<K, S, T>(up - sz, inb && z0 > 0, um);
-  ldKz<K, S, T>(up, inb, uc);
+  ld_u<K, S, SC, T, PRO>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, c, um);
+  ld_u<K, S, SC, T, PRO>(up, inb, x, y, z0, ec, gc, c, uc);
   if (PF) {
-    ldKz<K, S, T>(up + sz, inb && z0 + 1 < g.nz, un);
-    ldKz<K, S, T>(rpp, rin, rc);
+    ld_u<K, S, SC, T, PRO>(up + sz, inb && z0 + 1 < g.nz, x, y, z0 + 1, ec, gc, c, un);
+    ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z0, ec, gc, c, rc);
     if (MODE != 0) ldKz<K, S, T>(fp, inb, fc);
   }
   cx<T>* sm = reinterpret_cast<cx<T>*>(smraw + sl * PSR + (sl & 1) * 16 + (sl >> 1) * 128);
@@ -538,12 +591,12 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
     if (PF) {
       const bool more = z + 1 < z1;
-      ldKz<K, S, T>(up + 2 * sz, inb && z + 2 < g.nz, unn);
-      ldKz<K, S, T>(rpp + sz, rin && more, rn);
+      ld_u<K, S, SC, T, PRO>(up + 2 * sz, inb && z + 2 < g.nz, x, y, z + 2, ec, gc, c, unn);
+      ld_u<K, S, SC, T, PRO>(rpp + sz, rin && more, rx, ry, z + 1, ec, gc, c, rn);
       if (MODE != 0) ldKz<K, S, T>(fp + sz, inb && more, fn);
     } else {
-      ldKz<K, S, T>(up + sz, inb && z + 1 < g.nz, un);
-      ldKz<K, S, T>(rpp, rin, rc);
+      ld_u<K, S, SC, T, PRO>(up + sz, inb && z + 1 < g.nz, x, y, z + 1, ec, gc, c, un);
+      ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z, ec, gc, c, rc);
     }
     if (ring) {
 #pragma unroll
@@ -595,9 +648,10 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   }
 }
 
-template <class S, class T, int MODE, int TY>
+template <class S, class T, int MODE, int TY, class SC = S, int PRO = 0>
 static void fine_t16_launch(const Geo& g, const void* u, const void* f, void* out, const void* dg, const void* dw,
-                            const double ih[3], int zc, hipStream_t s) {
+                            const double ih[3], int zc, hipStream_t s, const void* ec = nullptr,
+                            const Geo& gc = Geo{}) {
   constexpr int CG = 128 / (int)sizeof(S);
   ZTiles zt;
   zt.nxb = (g.nx + TB - 1) / TB;
@@ -606,9 +660,9 @@ static void fine_t16_launch(const Geo& g, const void* u, const void* f, void* ou
   zt.nzc = (g.nz + zt.zc - 1) / zt.zc;
   zt.ntiles = (int64_t)zt.nxb * nyb * zt.nzc * (g.P / CG);
   zt.per = (int)((zt.ntiles + 7) / 8);
-  hipLaunchKernelGGL((k_fine_t16<S, T, MODE, TY>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(64 * TY), 0, s, g,
-                     zt, nyb, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
-                     (T)ih[1], (T)ih[2]);
+  hipLaunchKernelGGL((k_fine_t16<S, T, MODE, TY, SC, PRO>), dim3((unsigned)(8 * (int64_t)zt.per)), dim3(64 * TY),
+                     0, s, g, zt, nyb, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)dg, (const cx<T>*)dw,
+                     (T)ih[0], (T)ih[1], (T)ih[2], (const SC*)ec, gc);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,6 +991,35 @@ static bool gal_lds_launch(const Geo& g, const void* u, const void* f, void* out
 static thread_local FineTile g_tile = {4, 32};
 void set_fine_tile(FineTile t) { g_tile = t; }
 FineTile get_fine_tile() { return g_tile; }
+
+bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& gc, const void* ec, const void* u,
+                          const void* f, void* out, const void* dg, const void* dw, const double ih[3],
+                          hipStream_t s) {
+  // with the LDS-blocked tiles only (the register-blocked family keeps the
+  // separate prolongation, and the tile-identity test compares the two)
+  if (g_tile.ry != 8 && g_tile.ry != 16) return false;
+  static const bool off = [] {
+    const char* e = std::getenv("HELM_FUSE");
+    return e && std::strcmp(e, "0") == 0;
+  }();
+  if (off) return false;
+  const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
+  if (pf == P32 && pc == PBF && pt == P32 && gf.P % 16 == 0) {
+    if (g_tile.ry == 16)
+      fine_t16_launch<c64, float, 2, 16, cbf, 1>(gf, u, f, out, dg, dw, ih, zc, s, ec, gc);
+    else
+      fine_t16_launch<c64, float, 2, 8, cbf, 1>(gf, u, f, out, dg, dw, ih, zc, s, ec, gc);
+    return true;
+  }
+  if (pf == P64 && pc == P64 && pt == P64 && gf.P % 8 == 0) {
+    if (g_tile.ry == 16)
+      fine_t16_launch<c128, double, 2, 16, c128, 1>(gf, u, f, out, dg, dw, ih, zc, s, ec, gc);
+    else
+      fine_t16_launch<c128, double, 2, 8, c128, 1>(gf, u, f, out, dg, dw, ih, zc, s, ec, gc);
+    return true;
+  }
+  return false;
+}
 
 bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* u, const void* f,
                            void* rc, const void* dg, const double ih[3], hipStream_t s) {

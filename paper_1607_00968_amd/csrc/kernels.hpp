@@ -30,6 +30,12 @@ void set_fine_tile(FineTile t);
 // returns true only for the LDS-blocked tiles and supported precisions.
 bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* u, const void* f,
                            void* rc, const void* dg, const double ih[3], hipStream_t s);
+// First post-smoothing sweep of the 3D finest level with the coarse-grid
+// correction fused in: out = JAC(u + P ec) (bitwise the prolongation followed
+// by the sweep). Runs and returns true only for the LDS-blocked tiles.
+bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& gc, const void* ec, const void* u,
+                          const void* f, void* out, const void* dg, const void* dw, const double ih[3],
+                          hipStream_t s);
 FineTile get_fine_tile();
 // mode: 0 apply (out = A u), 1 residual (out = f - A u),
 //       2 Jacobi (out = u + dw (f - A u)), 3 zero-guess Jacobi (out = dw f).
