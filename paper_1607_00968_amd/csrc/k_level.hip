@@ -463,6 +463,8 @@ static inline dim3 grid1(int64_t threads) { return dim3((unsigned)((threads + 25
 // ---------------------------------------------------------------------------
 constexpr int TB = 16;  // tile edge along x (points)
 
+template <class T, class E> __device__ inline cx<T> wid(const cx<E>& v) { return cx<T>{(T)v.re, (T)v.im}; }
+
 // Parents of fine index i along one axis in registers (the order and weights
 // of parents(): the lower parent first).
 struct Par {
@@ -584,8 +586,11 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
     ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z0, ec, gc, c, rc);
     if (MODE != 0) ldKz<K, S, T>(fp, inb, fc);
   }
-  cx<T>* sm = reinterpret_cast<cx<T>*>(smraw + sl * PSR + (sl & 1) * 16 + (sl >> 1) * 128);
-  const int me = ((py + 1) * HX + px + 1) * K;  // own point, in units of cx<T>
+  // the tile holds values in storage precision (32 B per lane and point);
+  // widening them to T on the way out of LDS is exact
+  using LE = typename std::conditional<sizeof(S) == 8, float, double>::type;
+  cx<LE>* sm = reinterpret_cast<cx<LE>*>(smraw + sl * PSR + (sl & 1) * 16 + (sl >> 1) * 128);
+  const int me = ((py + 1) * HX + px + 1) * K;  // own point, in units of cx<LE>
   const int ro = (hy * HX + hx) * K;
   constexpr int RX = K, RYS = HX * K;           // x and y neighbour strides
   for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
@@ -600,10 +605,10 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
     }
     if (ring) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) sm[ro + k] = rc[k];
+      for (int k = 0; k < K; ++k) sm[ro + k] = cx<LE>{(LE)rc[k].re, (LE)rc[k].im};
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) sm[me + k] = uc[k];
+    for (int k = 0; k < K; ++k) sm[me + k] = cx<LE>{(LE)uc[k].re, (LE)uc[k].im};
     __syncthreads();
     if (inb) {
       const int64_t ir = (int64_t)z * plane + icol;
@@ -612,9 +617,9 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         acc[k] = d * uc[k];
-        sum[k] = ihz * (um[k] + un[k]) + ihy * (sm[me - RYS + k] + sm[me + RYS + k]);
-        sum[k] = sum[k] + ihx * sm[me - RX + k];
-        sum[k] = sum[k] + ihx * sm[me + RX + k];
+        sum[k] = ihz * (um[k] + un[k]) + ihy * (wid<T>(sm[me - RYS + k]) + wid<T>(sm[me + RYS + k]));
+        sum[k] = sum[k] + ihx * wid<T>(sm[me - RX + k]);
+        sum[k] = sum[k] + ihx * wid<T>(sm[me + RX + k]);
         acc[k] = acc[k] - sum[k];
       }
       const int64_t o = ir * g.P + c;
@@ -886,10 +891,10 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
 // ---------------------------------------------------------------------------
 constexpr int GT = 8;            // tile edge
 constexpr int GH = GT + 2;       // with the ring
-constexpr int GZC = 16;          // planes per chunk
+constexpr int GZC = 16;          // planes per chunk (fewer on small grids)
 
 template <class S, class T, int MODE>
-__global__ __launch_bounds__(256) void k_gal_lds(Geo g, int ncg, int nxb, int nyb, int nzc, int64_t ntiles, int per,
+__global__ __launch_bounds__(256) void k_gal_lds(Geo g, int ncg, int nxb, int nyb, int zc, int64_t ntiles, int per,
                                                  const S* __restrict__ u, const S* __restrict__ f,
                                                  S* __restrict__ out, const cx<T>* __restrict__ st,
                                                  const cx<T>* __restrict__ dw) {
@@ -908,7 +913,7 @@ __global__ __launch_bounds__(256) void k_gal_lds(Geo g, int ncg, int nxb, int ny
   t /= nyb;
   const int xb = (int)(t % nxb);
   const int zci = (int)(t / nxb);
-  const int z0 = zci * GZC, z1 = z0 + GZC < g.nz ? z0 + GZC : g.nz;
+  const int z0 = zci * zc, z1 = z0 + zc < g.nz ? z0 + zc : g.nz;
   const int q = threadIdx.x >> 2, sl = threadIdx.x & 3;
   const int px = q % GT, py = q / GT;
   const int x = xb * GT + px, y = yb * GT + py;
@@ -980,11 +985,16 @@ static bool gal_lds_launch(const Geo& g, const void* u, const void* f, void* out
   constexpr int CG = 128 / (int)sizeof(S);
   if (g.P % CG != 0) return false;
   const int ncg = g.P / CG;
-  const int nxb = (g.nx + GT - 1) / GT, nyb = (g.ny + GT - 1) / GT, nzc = (g.nz + GZC - 1) / GZC;
+  const int nxb = (g.nx + GT - 1) / GT, nyb = (g.ny + GT - 1) / GT;
+  // shorter z-chunks on small grids, so that the launch still has about six
+  // workgroups per compute unit (the result does not depend on the chunking)
+  int zc = GZC;
+  while (zc > 4 && (int64_t)ncg * nxb * nyb * ((g.nz + zc - 1) / zc) < 1536) zc /= 2;
+  const int nzc = (g.nz + zc - 1) / zc;
   const int64_t ntiles = (int64_t)ncg * nxb * nyb * nzc;
   const int per = (int)((ntiles + 7) / 8);
   hipLaunchKernelGGL((k_gal_lds<S, T, MODE>), dim3((unsigned)(8 * (int64_t)per)), dim3(256), 0, s, g, ncg, nxb, nyb,
-                     nzc, ntiles, per, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)st, (const cx<T>*)dw);
+                     zc, ntiles, per, (const S*)u, (const S*)f, (S*)out, (const cx<T>*)st, (const cx<T>*)dw);
   return true;
 }
 
@@ -1072,11 +1082,15 @@ static void fine_dispatch(int dim, const Geo& g, const void* u, const void* f, v
     // at 5-6 waves per SIMD); otherwise the tuned shape
     const int ry = sizeof(SO) > sizeof(SU) || (sizeof(T) == 8 && K >= 2) ? 1 : g_tile.ry;
     const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
+    // the LDS-blocked tiles; also for the FP64-arithmetic apply of c64 fields
+    // (the outer W = H Z), whose tile stays in storage precision in LDS
     if constexpr (std::is_same<SU, SF>::value && std::is_same<SU, SO>::value &&
                   ((std::is_same<SU, c64>::value && std::is_same<T, float>::value) ||
-                   (std::is_same<SU, c128>::value && std::is_same<T, double>::value))) {
-      if ((ry == 16 || ry == 8) && g.P % (128 / (int)sizeof(SU)) == 0 && MODE != 3) {
-        if (ry == 16)
+                   (std::is_same<SU, c128>::value && std::is_same<T, double>::value) ||
+                   (std::is_same<SU, c64>::value && std::is_same<T, double>::value && MODE == 0))) {
+      const int rt = g_tile.ry;
+      if ((rt == 16 || rt == 8) && g.P % (128 / (int)sizeof(SU)) == 0 && MODE != 3) {
+        if (rt == 16)
           fine_t16_launch<SU, T, MODE, 16>(g, u, f, out, dg, dw, ih, zc, s);
         else
           fine_t16_launch<SU, T, MODE, 8>(g, u, f, out, dg, dw, ih, zc, s);
