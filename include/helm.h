@@ -110,6 +110,15 @@ typedef struct {
                           (block width, buffers) and replayed afterwards; results are
                           bitwise those of the eager launches. Ignored while kernel
                           timing (helm_profile_enable) or pair capture is on. */
+  double learned_rate; /* learned coarsest correction only: the calibrated per-cycle
+                          residual reduction factor rho of the plain cycle (0 < rho < 1,
+                          e.g. tol^(1/cycles) of a solve with the LU or GMRES coarsest
+                          solver); 0 turns the check off. At every restart the solve
+                          measures its own factor, (max_s relres_s now / at the previous
+                          restart)^(1 / cycles in between); when that is above sqrt(rho),
+                          i.e. the solve would need more than twice the calibrated
+                          cycles, the coarsest solves switch to the GMRES fallback for
+                          the rest of the solve (info.rate_switch). */
 } helm_solve_opts;
 
 typedef struct {
@@ -121,6 +130,8 @@ typedef struct {
   double t_solve_ms;    /* device time of the solve (hip events) */
   double* relres;       /* HOST [nrhs] or NULL: final FP64 ||q_s - H u_s|| / ||q_s|| */
   int32_t* converged;   /* HOST [nrhs] or NULL */
+  int32_t rate_switch;  /* cycles done when the learned_rate check switched to the
+                           fallback, or -1 */
 } helm_solve_info;
 
 /* Build the hierarchy: fine coefficients, Galerkin operators per level
@@ -239,7 +250,8 @@ const char* helm_last_error(void);
  * network's correction is the initial guess of k GMRES steps on the coarsest
  * grid. An output that is not finite, or beyond 1e4 in the normalised units
  * e / (H^2 rms(r)), makes that coarsest solve fall back to max(k, 20) GMRES
- * steps from zero (counted in info.fallback_used). */
+ * steps from zero (counted in info.fallback_used); so does every coarsest
+ * solve after the per-cycle rate check of helm_solve_opts.learned_rate fired. */
 typedef struct helm_net_s* helm_net;
 /* Number of FP32 parameters. */
 int64_t helm_net_nparams(void);

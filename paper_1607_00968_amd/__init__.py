@@ -71,13 +71,14 @@ class SetupDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_cycles", C.c_int32), ("block_size", C.c_int32),
-                ("warm_start", C.c_int32), ("reorth", C.c_int32), ("graph", C.c_int32)]
+                ("warm_start", C.c_int32), ("reorth", C.c_int32), ("graph", C.c_int32),
+                ("learned_rate", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("restarts", C.c_int32), ("converged_all", C.c_int32),
                 ("fallback_used", C.c_int32), ("t_solve_ms", C.c_double),
-                ("relres", C.c_void_p), ("converged", C.c_void_p)]
+                ("relres", C.c_void_p), ("converged", C.c_void_p), ("rate_switch", C.c_int32)]
 
 
 _lib = None
@@ -224,13 +225,17 @@ def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:
 
 
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
-                     warm_start=False, reorth=True, workspace=None, stream=None, graph=False) -> dict:
-    """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ..."""
+                     warm_start=False, reorth=True, workspace=None, stream=None, graph=False,
+                     learned_rate=0.0) -> dict:
+    """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ...
+    learned_rate: the plain cycle's calibrated per-cycle reduction factor for
+    the learned coarsest correction's rate check (0 = off)."""
     nrhs = Q.shape[0]
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
         raise ValueError("Q and U must both be [nrhs, N]")
-    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), int(bool(graph)))
+    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), int(bool(graph)),
+                  float(learned_rate))
     rel = np.zeros(nrhs)
     conv = np.zeros(nrhs, np.int32)
     info = SolveInfo()
@@ -242,11 +247,12 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
                                        C.byref(info), _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
     return {"status": st, "cycles": info.cycles, "restarts": info.restarts,
             "converged_all": bool(info.converged_all), "fallback_used": int(info.fallback_used),
-            "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool)}
+            "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool),
+            "rate_switch": int(info.rate_switch)}
 
 
 def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, block_size=1, reorth=0,
-                     graph=False, max_threads=16, stream=None) -> list:
+                     graph=False, max_threads=16, stream=None, learned_rate=0.0) -> list:
     """Solve independent instances concurrently (one stream and one host
     thread of a pool per instance). Returns one dict per instance, as
     helm_solve_block does, plus "status"."""
@@ -262,7 +268,7 @@ def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, bloc
             raise ValueError("Q and U must both be [nrhs, N] of their instance")
     qp = (C.c_void_p * k)(*[q.data_ptr() for q in Qs])
     up = (C.c_void_p * k)(*[u.data_ptr() for u in Us])
-    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), int(bool(graph)))
+    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), int(bool(graph)), float(learned_rate))
     infos = (SolveInfo * k)()
     rel = [np.zeros(int(q.shape[0])) for q in Qs]
     conv = [np.zeros(int(q.shape[0]), np.int32) for q in Qs]
@@ -274,7 +280,8 @@ def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, bloc
                                   _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
     return [{"status": st[i], "cycles": infos[i].cycles, "restarts": infos[i].restarts,
              "converged_all": bool(infos[i].converged_all), "fallback_used": int(infos[i].fallback_used),
-             "t_solve_ms": infos[i].t_solve_ms, "relres": rel[i], "converged": conv[i].astype(bool)}
+             "t_solve_ms": infos[i].t_solve_ms, "relres": rel[i], "converged": conv[i].astype(bool),
+             "rate_switch": int(infos[i].rate_switch)}
             for i in range(k)]
 
 

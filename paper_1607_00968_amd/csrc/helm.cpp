@@ -116,6 +116,7 @@ struct helm_ctx {
   hipStream_t bstream = nullptr;  // this handle's stream inside helm_solve_batch
   bool capturing = false;         // a cycle is being recorded into a graph
   bool force_fallback = false;    // redo a cycle with the GMRES coarsest fallback
+  bool rate_fallback = false;     // the rate check switched this solve to the fallback
   // cached per-solve field allocation
   int fieldsP = 0;
   void* fieldmem = nullptr;
@@ -355,7 +356,7 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
       // non-finite count after the replay and redoes the cycle if needed
       learned::apply_async(c->net, P, f, out, s);
       ok = true;
-    } else if (!c->force_fallback) {
+    } else if (!c->force_fallback && !c->rate_fallback) {
       ok = learned::apply(c->net, P, f, out, s);
     }
     if (!ok) {
@@ -1082,8 +1083,10 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   helm_status st = check_block(h, nrhs, Q, U);
   if (st != HELM_OK) return st;
   if (!(tol > 0) || !std::isfinite(tol)) return fail(HELM_ERR_INVALID_ARG, "tol must be > 0");
-  helm_solve_opts o{5, 1000, 0, 0, 2, 0};
+  helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0};
   if (opts) o = *opts;
+  if (!(o.learned_rate >= 0.0 && o.learned_rate < 1.0))
+    return fail(HELM_ERR_INVALID_ARG, "learned_rate must be in [0, 1)");
   const int m = o.restart;
   if (m < 1 || m >= MAXPTR) return fail(HELM_ERR_INVALID_ARG, "restart must be 1..%d", MAXPTR - 1);
   const int pb = o.block_size <= 0 ? nrhs : o.block_size;
@@ -1102,7 +1105,13 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   set_fine_tile(c->tile);
   const int64_t fallbacks0 = c->fallbacks;
   // graphs need a cycle without host work: no per-kernel timing, no pair capture
-  const bool graph = o.graph != 0 && !c->prof && !c->cap;
+  bool graph = o.graph != 0 && !c->prof && !c->cap;
+  // per-cycle rate check of the learned coarsest correction: the block's
+  // factor between restarts against sqrt of the calibrated plain factor
+  const bool rate_check = o.learned_rate > 0.0 && c->coarse == HELM_COARSE_LEARNED && c->net;
+  c->rate_fallback = false;
+  int rate_switch = -1, rate_cycles0 = 0;
+  double rate_res0 = 0.0;
   const WsLayout w = ws_layout(c, P, m, pb);
   char* base = static_cast<char*>(workspace);
   if (!base) {
@@ -1203,6 +1212,22 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     if (all) {
       converged = true;
       break;
+    }
+    if (rate_check && !c->rate_fallback) {
+      double worst = 0.0;
+      for (int cidx = 0; cidx < Pa; ++cidx) worst = std::max(worst, relres[cidx]);
+      if (cycles > rate_cycles0 && rate_res0 > 0.0) {
+        const double rho = std::pow(worst / rate_res0, 1.0 / (cycles - rate_cycles0));
+        if (rho > std::sqrt(o.learned_rate)) {
+          // the rest of the solve runs the GMRES fallback on the coarsest grid
+          // (eagerly: captured graphs hold the network's path)
+          c->rate_fallback = true;
+          rate_switch = cycles;
+          graph = false;
+        }
+      }
+      rate_res0 = worst;
+      rate_cycles0 = cycles;
     }
     if (cycles >= o.max_cycles || breakdown) break;
     restarts += cycles > 0;
@@ -1338,11 +1363,13 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     info->converged_all = converged ? 1 : 0;
     info->fallback_used = (int32_t)(c->fallbacks - fallbacks0);
     info->t_solve_ms = ms;
+    info->rate_switch = rate_switch;
     for (int cidx = 0; cidx < nrhs; ++cidx) {
       if (info->relres) info->relres[cidx] = relres[cidx];
       if (info->converged) info->converged[cidx] = relres[cidx] <= tol;
     }
   }
+  c->rate_fallback = false;
   if (!converged) return fail(HELM_ERR_NOT_CONVERGED, "not converged after %d cycles", cycles);
   return HELM_OK;
 }

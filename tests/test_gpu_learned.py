@@ -238,6 +238,44 @@ def test_learned_coarse_solve_converges_and_falls_back():
     assert info["converged_all"] and info["fallback_used"] == info["cycles"]
 
 
+def test_rate_check_switches_poor_network_to_fallback():
+    """The per-cycle rate check (learned_rate): an untrained network used alone
+    is a poor coarsest solver. Calibrated with the LU coarsest solver's
+    per-cycle factor rho, the check fires at a restart (the solve's own factor
+    is above sqrt(rho)), every later coarsest solve is a GMRES fallback, and
+    the solve converges; with the check off the network keeps running. The
+    graph form gives the same result (the switch turns capture off)."""
+    p, hd = coarse_problem(32, 3, precision="mixed")
+    Q = torch.from_numpy(np.ascontiguousarray(p.Q[:4])).cuda()
+    U = torch.zeros_like(Q)
+    ref = pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=5, block_size=1, max_cycles=600)
+    assert ref["converged_all"] and ref["rate_switch"] == -1
+    rho = float(ref["relres"].max()) ** (1.0 / ref["cycles"])
+    nu = pk.helm_level_dims(hd, 2)
+    D = (max(nu) + 3) // 4 * 4
+    blob = pk.helm_net_create(D, 8, seed=11).save()
+    hl = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                       precision="mixed", coarse="learned", net=blob, coarse_iters=0)
+    Uoff = torch.zeros_like(Q)
+    off = pk.helm_solve_block(hl, Q, Uoff, tol=1e-6, restart=5, block_size=1, max_cycles=300)
+    assert off["rate_switch"] == -1
+    Uon = torch.zeros_like(Q)
+    on = pk.helm_solve_block(hl, Q, Uon, tol=1e-6, restart=5, block_size=1, max_cycles=600, learned_rate=rho)
+    print("LU cycles", ref["cycles"], "rho", rho, "off", off["cycles"], off["converged_all"],
+          "on", on["cycles"], "switch at", on["rate_switch"])
+    assert on["converged_all"] and pk.helm_residual(hl, Q, Uon).max() <= 1e-6
+    assert on["rate_switch"] > 0
+    assert on["fallback_used"] >= on["cycles"] - on["rate_switch"]
+    assert (not off["converged_all"]) or on["cycles"] < off["cycles"]
+    Ug = torch.zeros_like(Q)
+    g = pk.helm_solve_block(hl, Q, Ug, tol=1e-6, restart=5, block_size=1, max_cycles=600, learned_rate=rho,
+                            graph=True)
+    assert g["cycles"] == on["cycles"] and g["rate_switch"] == on["rate_switch"]
+    assert torch.equal(Ug, Uon)
+    with pytest.raises(pk.HelmError):
+        pk.helm_solve_block(hl, Q, Ug, tol=1e-6, learned_rate=1.5)
+
+
 def test_learned_guess_beats_gmres_from_zero():
     """The gain test: on a 64^3 layered model (coarsest grid 15^3), k = 4
     GMRES steps started from the trained network's correction need clearly
