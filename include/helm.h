@@ -106,10 +106,17 @@ typedef struct {
   int32_t warm_start;  /* 1: U holds an initial guess */
   int32_t reorth;      /* 0: one block Gram-Schmidt pass; 1: always two; 2: a second
                           pass only where the norm fell below half (block size 1) */
-  int32_t graph;       /* 1: run each cycle from a HIP graph captured on first use per
-                          (block width, buffers) and replayed afterwards; results are
-                          bitwise those of the eager launches. Ignored while kernel
-                          timing (helm_profile_enable) or pair capture is on. */
+  int32_t graph;       /* execution form of the cycle. 0: eager launches. 1: a HIP graph
+                          captured on first use per (block width, buffers) and replayed
+                          afterwards; results are bitwise those of the eager launches.
+                          2: one cooperative launch of a persistent kernel per cycle that
+                          runs the cycle's steps with grid-wide barriers between them
+                          (V-cycle with the LU coarsest solver only, else
+                          HELM_ERR_INVALID_ARG; not in helm_solve_batch); in 2D its
+                          results are bitwise those of the eager launches, in 3D they
+                          differ by rounding (the eager path uses the tiled and fused
+                          kernels there). 1 and 2 are ignored while kernel timing
+                          (helm_profile_enable) or pair capture is on. */
   double learned_rate; /* learned coarsest correction only: the calibrated per-cycle
                           residual reduction factor rho of the plain cycle (0 < rho < 1,
                           e.g. tol^(1/cycles) of a solve with the LU or GMRES coarsest

@@ -224,6 +224,16 @@ def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:
     return b.value
 
 
+def _form(graph) -> int:
+    """Execution form of the cycle: False/0 eager, True/1 HIP graph,
+    "persistent"/2 the cooperative persistent kernel."""
+    if graph == "persistent":
+        return 2
+    if isinstance(graph, bool):
+        return int(graph)
+    return int(graph)
+
+
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
                      warm_start=False, reorth=True, workspace=None, stream=None, graph=False,
                      learned_rate=0.0) -> dict:
@@ -234,7 +244,7 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
         raise ValueError("Q and U must both be [nrhs, N]")
-    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), int(bool(graph)),
+    o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), _form(graph),
                   float(learned_rate))
     rel = np.zeros(nrhs)
     conv = np.zeros(nrhs, np.int32)
@@ -268,7 +278,7 @@ def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, bloc
             raise ValueError("Q and U must both be [nrhs, N] of their instance")
     qp = (C.c_void_p * k)(*[q.data_ptr() for q in Qs])
     up = (C.c_void_p * k)(*[u.data_ptr() for u in Us])
-    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), int(bool(graph)), float(learned_rate))
+    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), _form(graph), float(learned_rate))
     infos = (SolveInfo * k)()
     rel = [np.zeros(int(q.shape[0])) for q in Qs]
     conv = [np.zeros(int(q.shape[0]), np.int32) for q in Qs]

@@ -112,6 +112,18 @@ struct helm_ctx {
   };
   uint64_t graph_net_gen = 0;     // network scratch generation the graphs were taken with
   std::vector<CycleGraph> graphs;
+  // persistent cycles: the recorded phases of a cycle per (block width, buffers)
+  struct CyclePlan {
+    int P;
+    const void* f;
+    void* out;
+    void* tmp;
+    Phase* d;  // device copy of the phases
+    int nph, grid;
+  };
+  std::vector<CyclePlan> plans;
+  std::vector<Phase>* plan = nullptr;  // set while a cycle is being recorded
+  bool plan_bad = false;               // the recorded cycle has a step the persistent kernel lacks
   hipStream_t gstream = nullptr;  // capture stream (never executes work itself)
   hipStream_t bstream = nullptr;  // this handle's stream inside helm_solve_batch
   bool capturing = false;         // a cycle is being recorded into a graph
@@ -189,6 +201,27 @@ __global__ void k_add_c128(int64_t n, const c128* __restrict__ x, c128* __restri
 
 // One relaxation-family launch on level l (mode as launch_fine).
 static void level_op(helm_ctx* c, int l, int mode, int P, const void* u, const void* f, void* out, hipStream_t s) {
+  if (c->plan) {
+    const Level& L = c->lv[l];
+    Phase q{};
+    q.op = l == 0 ? PH_FINE : PH_GAL;
+    q.mode = mode;
+    q.pa = field_prec(c, l);
+    q.pb = comp_prec(c);
+    q.g = L.geo(P);
+    q.u = u;
+    q.f = f;
+    q.out = out;
+    if (l == 0) {
+      q.c0 = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+      for (int a = 0; a < 3; ++a) q.ih[a] = L.ih[a];
+    } else {
+      q.c0 = level_st(c, l);
+    }
+    q.c1 = level_dw(c, l);
+    c->plan->push_back(q);
+    return;
+  }
   Prof pr(c,
           l == 0 ? (mode == 1 ? HELM_K_FINE_RESID : (mode == 3 ? HELM_K_FINE_SWEEP0 : HELM_K_FINE_SWEEP))
                  : HELM_K_COARSE_SWEEP,
@@ -212,6 +245,14 @@ __global__ void k_zero_u4(int64_t n, uint4* __restrict__ p) {
 // into a HIP graph; field sizes are multiples of 16 B (P % 4 == 0).
 static void zero_field(helm_ctx* c, int l, int P, void* u, hipStream_t s) {
   const int64_t n = (int64_t)psize(field_prec(c, l)) * c->lv[l].npts * P / 16;
+  if (c->plan) {
+    Phase q{};
+    q.op = PH_ZERO;
+    q.out = u;
+    q.n = n;
+    c->plan->push_back(q);
+    return;
+  }
   hipLaunchKernelGGL(k_zero_u4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, static_cast<uint4*>(u));
 }
 
@@ -248,7 +289,7 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   Level& C = c->lv[l + 1];
   const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
   bool fused = false;
-  if (l == 0 && c->dim == 3) {
+  if (l == 0 && c->dim == 3 && !c->plan) {
     // residual and restriction in one pass (counted as the fine residual)
     Prof pr(c, HELM_K_FINE_RESID, s);
     const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
@@ -256,11 +297,24 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   }
   if (!fused) {
     level_op(c, l, 1, P, a, f, L.Rr, s);
-    Prof pr(c, HELM_K_TRANSFER, s);
-    launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
+    if (c->plan) {
+      Phase q{};
+      q.op = PH_RESTRICT;
+      q.pa = pf;
+      q.pb = pc;
+      q.g = L.geo(P);
+      q.gc = C.geo(P);
+      q.u = L.Rr;
+      q.out = C.F;
+      c->plan->push_back(q);
+    } else {
+      Prof pr(c, HELM_K_TRANSFER, s);
+      launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
+    }
   }
   cycle_rec(c, l + 1, P, C.F, C.U0, C.U1, s);
   if (c->cycle == HELM_CYCLE_W && l + 1 < c->L - 1) {
+    if (c->plan) c->plan_bad = true;
     // W-cycle: a second coarse cycle on the residual of the first result,
     // e <- e + B(F - M e); F is free again and serves as ping-pong buffer.
     level_op(c, l + 1, 1, P, C.U0, C.F, c->kbuf[l + 1], s);
@@ -268,7 +322,7 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
     field_axpy(c, l + 1, P, C.U1, C.U0, s);
   }
   int k0 = 0;
-  if (l == 0 && c->dim == 3 && npost >= 1) {
+  if (l == 0 && c->dim == 3 && npost >= 1 && !c->plan) {
     // prolongation and correction fused into the first post-smoothing sweep:
     // b = JAC(a + P e); a itself is not updated (the next sweep overwrites it)
     Prof pr(c, HELM_K_FINE_PROSWEEP, s);
@@ -278,7 +332,17 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
       k0 = 1;
     }
   }
-  if (k0 == 0) {
+  if (k0 == 0 && c->plan) {
+    Phase q{};
+    q.op = PH_PROLONG;
+    q.pa = pc;
+    q.pb = pf;
+    q.g = L.geo(P);
+    q.gc = C.geo(P);
+    q.u = C.U0;
+    q.out = a;
+    c->plan->push_back(q);
+  } else if (k0 == 0) {
     Prof pr(c, HELM_K_TRANSFER, s);
     launch_prolong_add(pc, pf, pt, c->dim, L.geo(P), C.geo(P), C.U0, a, s);
   }
@@ -342,6 +406,23 @@ static size_t coarse_gmres_bytes(const helm_ctx* c, int P) {
 
 static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s) {
   const int l = c->L - 1;
+  if (c->plan) {
+    // the persistent cycle has the dense inverse (one GEMM) only
+    if (c->coarse != HELM_COARSE_LU) {
+      c->plan_bad = true;
+      return;
+    }
+    Phase q{};
+    q.op = PH_GEMM;
+    q.pa = c->precision == HELM_FP64 ? P64 : P32;
+    q.g.P = P;
+    q.n = c->nc;
+    q.u = f;
+    q.out = out;
+    q.c0 = c->precision == HELM_FP64 ? (const void*)c->Minv64 : (const void*)c->Minv32;
+    c->plan->push_back(q);
+    return;
+  }
   if (c->coarse == HELM_COARSE_LU) {
     if (c->precision == HELM_FP64)
       launch_gemm(P64, c->nc, P, c->nc, c128{1, 0}, c->Minv64, c->nc, f, P, c128{0, 0}, out, P, s);
@@ -389,16 +470,65 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
 static void clear_graphs(helm_ctx* c) {
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   c->graphs.clear();
+  for (auto& p : c->plans) (void)hipFree(p.d);
+  c->plans.clear();
 }
 
-// One cycle f -> out on level 0. With `graph`, the kernel sequence of this
+// One cycle f -> out as one cooperative launch of the persistent kernel. The
+// cycle's launches are recorded once per (block width, buffers) as phases
+// (the generic kernels' work items; the fused 3D forms are left out) and
+// copied to the device.
+static helm_status run_persist(helm_ctx* c, int P, const void* f, void* out, void* tmp, hipStream_t s) {
+  helm_ctx::CyclePlan* pl = nullptr;
+  for (auto& q : c->plans)
+    if (q.P == P && q.f == f && q.out == out && q.tmp == tmp) pl = &q;
+  if (!pl) {
+    std::vector<Phase> ph;
+    c->plan = &ph;
+    c->plan_bad = false;
+    cycle_rec(c, 0, P, f, out, tmp, s);
+    c->plan = nullptr;
+    if (c->plan_bad)
+      return fail(HELM_ERR_INVALID_ARG, "the persistent cycle needs a V-cycle with the LU coarsest solver");
+    const bool mixed = c->precision != HELM_FP64;
+    const int gmax = persist_grid(c->dim, mixed);
+    if (gmax < 1) return fail(HELM_ERR_DEVICE, "the device cannot run the cooperative cycle kernel");
+    int64_t need = 1;  // workgroups the widest phase can use
+    auto cols = [](int p) { return p == P64 ? 1 : (p == P32 ? 2 : 4); };  // columns per 16-byte unit
+    for (const Phase& q : ph) {
+      int64_t items = 0;
+      const int k2 = std::max(cols(q.pa), cols(q.pb));
+      if (q.op == PH_FINE || q.op == PH_GAL) items = q.g.npts * q.g.P / cols(q.pa);
+      else if (q.op == PH_PROLONG) items = q.g.npts * q.g.P / k2;
+      else if (q.op == PH_RESTRICT) items = q.gc.npts * q.gc.P / k2;
+      else if (q.op == PH_ZERO) items = q.n;
+      else if (q.op == PH_GEMM) items = 256 * ((q.n + 63) / 64) * ((q.g.P + 63) / 64);
+      need = std::max(need, (items + 255) / 256);
+    }
+    helm_ctx::CyclePlan np{P, f, out, tmp, nullptr, (int)ph.size(), (int)std::min<int64_t>(need, gmax)};
+    HCHECK(hipMalloc(&np.d, sizeof(Phase) * ph.size()));
+    const hipError_t e = hipMemcpy(np.d, ph.data(), sizeof(Phase) * ph.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(np.d);
+      HCHECK(e);
+    }
+    c->plans.push_back(np);
+    pl = &c->plans.back();
+  }
+  HCHECK(launch_cycle_persist(c->dim, c->precision != HELM_FP64, pl->d, pl->nph, pl->grid, s));
+  return HELM_OK;
+}
+
+// One cycle f -> out on level 0: eager launches (form 0), a HIP graph
+// (form 1) or the persistent kernel (form 2). With a graph, the kernel sequence of this
 // (block width, buffers) is captured once into a HIP graph on a private
 // stream and replayed on s afterwards; the cycle has no host synchronisation
 // or memset inside, so the replay runs exactly the kernels of the eager path.
 // The learned correction's non-finite check happens after the replay: if it
 // fired, the cycle is run again eagerly with the GMRES fallback.
-static helm_status run_cycle(helm_ctx* c, int P, const void* f, void* out, void* tmp, bool graph, hipStream_t s) {
-  if (!graph) {
+static helm_status run_cycle(helm_ctx* c, int P, const void* f, void* out, void* tmp, int form, hipStream_t s) {
+  if (form == 2) return run_persist(c, P, f, out, tmp, s);
+  if (form != 1) {
     cycle_rec(c, 0, P, f, out, tmp, s);
     return HELM_OK;
   }
@@ -1104,8 +1234,10 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
   set_fine_tile(c->tile);
   const int64_t fallbacks0 = c->fallbacks;
-  // graphs need a cycle without host work: no per-kernel timing, no pair capture
-  bool graph = o.graph != 0 && !c->prof && !c->cap;
+  if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");
+  // graphs and the persistent kernel need a cycle without host work: no
+  // per-kernel timing, no pair capture
+  int graph = (c->prof || c->cap) ? 0 : o.graph;
   // per-cycle rate check of the learned coarsest correction: the block's
   // factor between restarts against sqrt of the calibrated plain factor
   const bool rate_check = o.learned_rate > 0.0 && c->coarse == HELM_COARSE_LEARNED && c->net;
@@ -1223,7 +1355,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
           // (eagerly: captured graphs hold the network's path)
           c->rate_fallback = true;
           rate_switch = cycles;
-          graph = false;
+          graph = 0;
         }
       }
       rate_res0 = worst;
@@ -1520,6 +1652,10 @@ helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nr
                              void* const* U, double tol, const helm_solve_opts* opts, helm_solve_info* infos,
                              int32_t* status, int32_t max_threads, void* stream) {
   if (k < 1 || !hs || !nrhs || !Q || !U) return fail(HELM_ERR_INVALID_ARG, "bad batch arguments");
+  // cooperative launches on concurrent streams could each hold part of the
+  // device while waiting for the rest of their grid
+  if (opts && opts->graph == 2)
+    return fail(HELM_ERR_INVALID_ARG, "the persistent cycle (graph 2) is not available in a concurrent batch");
   for (int i = 0; i < k; ++i) {
     if (!hs[i]) return fail(HELM_ERR_INVALID_ARG, "null handle at %d", i);
     for (int j = 0; j < i; ++j)

@@ -15,8 +15,11 @@
 #include <cstring>
 #include <type_traits>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tile_gemm.hpp"
 
 namespace helm {
 
@@ -55,14 +58,15 @@ template <int K, class S, class T> __device__ inline void stK(S* p, const cx<T>*
 //   JAC   : out = u + w D^-1 (f - A u)      (dw = w / diag)
 //   JAC0  : out = w D^-1 f                  (first sweep from u = 0)
 // ---------------------------------------------------------------------------
+// One work item (K columns of one point) of the fine-level family; the
+// kernels below and the persistent cycle both run it, t < npts * P / K.
 template <int DIM, class SU, class SF, class SO, class T, int MODE>
-__global__ __launch_bounds__(256) void k_fine(Geo g, const SU* __restrict__ u, const SF* __restrict__ f,
-                                              SO* __restrict__ out, const cx<T>* __restrict__ dg,
-                                              const cx<T>* __restrict__ dw, T ihx, T ihy, T ihz) {
+__device__ __forceinline__ void fine_item(const Geo& g, int64_t t, const SU* __restrict__ u,
+                                          const SF* __restrict__ f, SO* __restrict__ out,
+                                          const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw, T ihx, T ihy,
+                                          T ihz) {
   constexpr int K = kmax3<SU, SF, SO>();
   const int Pc = g.P / K;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.npts * Pc) return;
   const int64_t i = t / Pc;
   const int c = (int)(t - i * Pc) * K;
   const int64_t base = i * g.P + c;
@@ -125,6 +129,16 @@ __global__ __launch_bounds__(256) void k_fine(Geo g, const SU* __restrict__ u, c
     for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fv[k] - acc[k]);
   }
   stK<K, SO, T>(out + base, res);
+}
+
+template <int DIM, class SU, class SF, class SO, class T, int MODE>
+__global__ __launch_bounds__(256) void k_fine(Geo g, const SU* __restrict__ u, const SF* __restrict__ f,
+                                              SO* __restrict__ out, const cx<T>* __restrict__ dg,
+                                              const cx<T>* __restrict__ dw, T ihx, T ihy, T ihz) {
+  constexpr int K = kmax3<SU, SF, SO>();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.npts * (g.P / K)) return;
+  fine_item<DIM, SU, SF, SO, T, MODE>(g, t, u, f, out, dg, dw, ihx, ihy, ihz);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,14 +248,12 @@ __global__ __launch_bounds__(256) void k_fine_zm(Geo g, ZTiles zt, const SU* __r
 // Galerkin-level operator family (same modes), stencil [N][NS], NS = 3^DIM.
 // ---------------------------------------------------------------------------
 template <int DIM, class S, class T, int MODE>
-__global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, const S* __restrict__ f,
-                                             S* __restrict__ out, const cx<T>* __restrict__ st,
-                                             const cx<T>* __restrict__ dw) {
+__device__ __forceinline__ void gal_item(const Geo& g, int64_t t, const S* __restrict__ u, const S* __restrict__ f,
+                                         S* __restrict__ out, const cx<T>* __restrict__ st,
+                                         const cx<T>* __restrict__ dw) {
   constexpr int K = St<S>::R;
   constexpr int NS = DIM == 3 ? 27 : 9;
   const int Pc = g.P / K;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.npts * Pc) return;
   const int64_t i = t / Pc;
   const int c = (int)(t - i * Pc) * K;
   const int64_t base = i * g.P + c;
@@ -295,16 +307,24 @@ __global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, con
   stK<K, S, T>(out + base, res);
 }
 
+template <int DIM, class S, class T, int MODE>
+__global__ __launch_bounds__(256) void k_gal(Geo g, const S* __restrict__ u, const S* __restrict__ f,
+                                             S* __restrict__ out, const cx<T>* __restrict__ st,
+                                             const cx<T>* __restrict__ dw) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.npts * (g.P / St<S>::R)) return;
+  gal_item<DIM, S, T, MODE>(g, t, u, f, out, st, dw);
+}
+
 // ---------------------------------------------------------------------------
 // Full weighting: rc[I] = 2^-d sum_delta w(delta) rf[2I+1+delta],
 // w = prod over axes of (1 if delta_a == 0 else 1/2).
 // ---------------------------------------------------------------------------
 template <int DIM, class SI, class SO, class T>
-__global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const SI* __restrict__ rf, SO* __restrict__ rc) {
+__device__ __forceinline__ void restrict_item(const Geo& gf, const Geo& gc, int64_t t, const SI* __restrict__ rf,
+                                              SO* __restrict__ rc) {
   constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
   const int Pc = gc.P / K;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= gc.npts * Pc) return;
   const int64_t I = t / Pc;
   const int c = (int)(t - I * Pc) * K;
   int X, Y, Z;
@@ -332,6 +352,14 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const SI* __re
   stK<K, SO, T>(rc + I * gc.P + c, acc);
 }
 
+template <int DIM, class SI, class SO, class T>
+__global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const SI* __restrict__ rf, SO* __restrict__ rc) {
+  constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.npts * (gc.P / K)) return;
+  restrict_item<DIM, SI, SO, T>(gf, gc, t, rf, rc);
+}
+
 // ---------------------------------------------------------------------------
 // Prolongation and correction: uf += P ec. A fine index i has the coarse
 // parent (i-1)/2 with weight 1 when i is odd, else the parents i/2-1 and i/2
@@ -356,11 +384,10 @@ __device__ inline int parents(int i, int nc, int* p, float* w) {
 }
 
 template <int DIM, class SC, class SF, class T>
-__global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const SC* __restrict__ ec, SF* __restrict__ uf) {
+__device__ __forceinline__ void prolong_item(const Geo& gf, const Geo& gc, int64_t t, const SC* __restrict__ ec,
+                                             SF* __restrict__ uf) {
   constexpr int K = St<SC>::R > St<SF>::R ? St<SC>::R : St<SF>::R;
   const int Pc = gf.P / K;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= gf.npts * Pc) return;
   const int64_t i = t / Pc;
   const int c = (int)(t - i * Pc) * K;
   int x, y, z;
@@ -382,6 +409,14 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const SC* _
         for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * v[k];
       }
   stK<K, SF, T>(uf + i * gf.P + c, acc);
+}
+
+template <int DIM, class SC, class SF, class T>
+__global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, const SC* __restrict__ ec, SF* __restrict__ uf) {
+  constexpr int K = St<SC>::R > St<SF>::R ? St<SC>::R : St<SF>::R;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gf.npts * (gf.P / K)) return;
+  prolong_item<DIM, SC, SF, T>(gf, gc, t, ec, uf);
 }
 
 // ---------------------------------------------------------------------------
@@ -1254,6 +1289,162 @@ void launch_to_abi(Prec pi, int64_t N, int nrhs, int P, const void* src, void* d
   if (pi == P64) { hipLaunchKernelGGL((k_to_abi<c128>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (c128*)dst); return; }
   if (pi == P32) { hipLaunchKernelGGL((k_to_abi<c64>), gr, dim3(256), 0, s, N, nrhs, P, (const c64*)src, (c128*)dst); return; }
   { hipLaunchKernelGGL((k_to_abi<cbf>), gr, dim3(256), 0, s, N, nrhs, P, (const cbf*)src, (c128*)dst); return; }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent cycle. One cooperative launch runs the recorded phases of a
+// cycle in order: the items of a phase are dealt out grid-stride (GEMM tiles
+// one per workgroup in turn) and every workgroup waits at a grid barrier
+// before the next phase reads what the previous one wrote. Each phase runs
+// the per-item code of the stand-alone kernel, so the arithmetic is that of
+// the eager generic kernels.
+// ---------------------------------------------------------------------------
+template <int DIM, class S, class T>
+__device__ void ph_fine(const Phase& q, int64_t t0, int64_t gs) {
+  const int64_t n = q.g.npts * (q.g.P / St<S>::R);
+  const T hx = (T)q.ih[0], hy = (T)q.ih[1], hz = (T)q.ih[2];
+  const S* u = static_cast<const S*>(q.u);
+  const S* f = static_cast<const S*>(q.f);
+  S* o = static_cast<S*>(q.out);
+  const cx<T>* dg = static_cast<const cx<T>*>(q.c0);
+  const cx<T>* dw = static_cast<const cx<T>*>(q.c1);
+  switch (q.mode) {
+    case 0:
+      for (int64_t t = t0; t < n; t += gs) fine_item<DIM, S, S, S, T, 0>(q.g, t, u, f, o, dg, dw, hx, hy, hz);
+      break;
+    case 1:
+      for (int64_t t = t0; t < n; t += gs) fine_item<DIM, S, S, S, T, 1>(q.g, t, u, f, o, dg, dw, hx, hy, hz);
+      break;
+    case 2:
+      for (int64_t t = t0; t < n; t += gs) fine_item<DIM, S, S, S, T, 2>(q.g, t, u, f, o, dg, dw, hx, hy, hz);
+      break;
+    default:
+      for (int64_t t = t0; t < n; t += gs) fine_item<DIM, S, S, S, T, 3>(q.g, t, u, f, o, dg, dw, hx, hy, hz);
+      break;
+  }
+}
+
+template <int DIM, class S, class T>
+__device__ void ph_gal(const Phase& q, int64_t t0, int64_t gs) {
+  const int64_t n = q.g.npts * (q.g.P / St<S>::R);
+  const S* u = static_cast<const S*>(q.u);
+  const S* f = static_cast<const S*>(q.f);
+  S* o = static_cast<S*>(q.out);
+  const cx<T>* st = static_cast<const cx<T>*>(q.c0);
+  const cx<T>* dw = static_cast<const cx<T>*>(q.c1);
+  switch (q.mode) {
+    case 0: for (int64_t t = t0; t < n; t += gs) gal_item<DIM, S, T, 0>(q.g, t, u, f, o, st, dw); break;
+    case 1: for (int64_t t = t0; t < n; t += gs) gal_item<DIM, S, T, 1>(q.g, t, u, f, o, st, dw); break;
+    case 2: for (int64_t t = t0; t < n; t += gs) gal_item<DIM, S, T, 2>(q.g, t, u, f, o, st, dw); break;
+    default: for (int64_t t = t0; t < n; t += gs) gal_item<DIM, S, T, 3>(q.g, t, u, f, o, st, dw); break;
+  }
+}
+
+template <int DIM, class SI, class SO, class T>
+__device__ void ph_restrict(const Phase& q, int64_t t0, int64_t gs) {
+  constexpr int K = St<SI>::R > St<SO>::R ? St<SI>::R : St<SO>::R;
+  const int64_t n = q.gc.npts * (q.gc.P / K);
+  for (int64_t t = t0; t < n; t += gs)
+    restrict_item<DIM, SI, SO, T>(q.g, q.gc, t, static_cast<const SI*>(q.u), static_cast<SO*>(q.out));
+}
+
+template <int DIM, class SC, class SF, class T>
+__device__ void ph_prolong(const Phase& q, int64_t t0, int64_t gs) {
+  constexpr int K = St<SC>::R > St<SF>::R ? St<SC>::R : St<SF>::R;
+  const int64_t n = q.g.npts * (q.g.P / K);
+  for (int64_t t = t0; t < n; t += gs)
+    prolong_item<DIM, SC, SF, T>(q.g, q.gc, t, static_cast<const SC*>(q.u), static_cast<SF*>(q.out));
+}
+
+// out = A B for the coarsest level: A the n x n inverse, B and out [n][P]
+template <class S, class T>
+__device__ void ph_gemm(const Phase& q, cx<T> (&As)[GEMM_BK][GEMM_BM + 1], cx<T> (&Bs)[GEMM_BK][GEMM_BN + 1]) {
+  const int64_t M = q.n, N = q.g.P;
+  const int64_t gx = (N + GEMM_BN - 1) / GEMM_BN, ntiles = gx * ((M + GEMM_BM - 1) / GEMM_BM);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    gemm_tile<S, T>((unsigned)(tile % gx), (unsigned)(tile / gx), M, N, M, cx<T>{(T)1, (T)0},
+                    static_cast<const S*>(q.c0), M, static_cast<const S*>(q.u), N, cx<T>{(T)0, (T)0},
+                    static_cast<S*>(q.out), N, As, Bs);
+}
+
+template <int DIM, bool MIX>
+__global__ __launch_bounds__(256) void k_cycle_persist(const Phase* __restrict__ ph, int nph) {
+  using T = typename std::conditional<MIX, float, double>::type;
+  __shared__ cx<T> As[GEMM_BK][GEMM_BM + 1];
+  __shared__ cx<T> Bs[GEMM_BK][GEMM_BN + 1];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int p = 0; p < nph; ++p) {
+    const Phase q = ph[p];
+    if (q.op == PH_FINE) {
+      if constexpr (MIX) ph_fine<DIM, c64, float>(q, t0, gs);
+      else ph_fine<DIM, c128, double>(q, t0, gs);
+    } else if (q.op == PH_GAL) {
+      if constexpr (MIX) {
+        if (q.pa == PBF) ph_gal<DIM, cbf, float>(q, t0, gs);
+        else ph_gal<DIM, c64, float>(q, t0, gs);
+      } else {
+        ph_gal<DIM, c128, double>(q, t0, gs);
+      }
+    } else if (q.op == PH_RESTRICT) {
+      if constexpr (MIX) {
+        if (q.pa == P32 && q.pb == PBF) ph_restrict<DIM, c64, cbf, float>(q, t0, gs);
+        else if (q.pa == PBF && q.pb == PBF) ph_restrict<DIM, cbf, cbf, float>(q, t0, gs);
+        else if (q.pa == PBF && q.pb == P32) ph_restrict<DIM, cbf, c64, float>(q, t0, gs);
+        else ph_restrict<DIM, c64, c64, float>(q, t0, gs);
+      } else {
+        ph_restrict<DIM, c128, c128, double>(q, t0, gs);
+      }
+    } else if (q.op == PH_PROLONG) {
+      if constexpr (MIX) {
+        if (q.pa == PBF && q.pb == P32) ph_prolong<DIM, cbf, c64, float>(q, t0, gs);
+        else if (q.pa == PBF && q.pb == PBF) ph_prolong<DIM, cbf, cbf, float>(q, t0, gs);
+        else if (q.pa == P32 && q.pb == PBF) ph_prolong<DIM, c64, cbf, float>(q, t0, gs);
+        else ph_prolong<DIM, c64, c64, float>(q, t0, gs);
+      } else {
+        ph_prolong<DIM, c128, c128, double>(q, t0, gs);
+      }
+    } else if (q.op == PH_ZERO) {
+      uint4* o = static_cast<uint4*>(q.out);
+      for (int64_t t = t0; t < q.n; t += gs) o[t] = uint4{0u, 0u, 0u, 0u};
+    } else if (q.op == PH_GEMM) {
+      if constexpr (MIX) ph_gemm<c64, float>(q, As, Bs);
+      else ph_gemm<c128, double>(q, As, Bs);
+    }
+    grid.sync();
+  }
+}
+
+template <int DIM, bool MIX> static int persist_grid_t() {
+  static const int g = [] {
+    int dev = 0, cus = 0, nb = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cycle_persist<DIM, MIX>, 256, 0) != hipSuccess)
+      return 0;
+    return nb * cus;
+  }();
+  return g;
+}
+
+int persist_grid(int dim, bool mixed) {
+  if (dim == 3) return mixed ? persist_grid_t<3, true>() : persist_grid_t<3, false>();
+  return mixed ? persist_grid_t<2, true>() : persist_grid_t<2, false>();
+}
+
+template <int DIM, bool MIX>
+static hipError_t persist_launch(const Phase* ph, int nph, int grid, hipStream_t s) {
+  void* args[] = {(void*)&ph, (void*)&nph};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cycle_persist<DIM, MIX>), dim3((unsigned)grid),
+                                    dim3(256), args, 0, s);
+}
+
+hipError_t launch_cycle_persist(int dim, bool mixed, const Phase* ph, int nph, int grid, hipStream_t s) {
+  if (grid < 1 || grid > persist_grid(dim, mixed)) return hipErrorInvalidValue;
+  if (dim == 3) return mixed ? persist_launch<3, true>(ph, nph, grid, s) : persist_launch<3, false>(ph, nph, grid, s);
+  return mixed ? persist_launch<2, true>(ph, nph, grid, s) : persist_launch<2, false>(ph, nph, grid, s);
 }
 
 }  // namespace helm

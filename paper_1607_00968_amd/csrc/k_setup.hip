@@ -12,6 +12,7 @@
 //    a block of right-hand sides becomes one dense matrix product.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tile_gemm.hpp"
 
 namespace helm {
 
@@ -167,75 +168,16 @@ void launch_narrow(int64_t n, const c128* a, c64* b, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Complex GEMM, C = alpha A B + beta C, row-major. 64x64 tile per 256-thread
-// workgroup, each lane a 4x4 sub-tile (rows ty+16r, cols tx+16c), K staged
-// through LDS in steps of 8.
+// Complex GEMM, C = alpha A B + beta C, row-major: one 64x64 tile per
+// 256-thread workgroup (gemm_tile).
 // ---------------------------------------------------------------------------
 template <class S, class T>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, cx<T> alpha, const S* __restrict__ A,
                                               int64_t lda, const S* __restrict__ B, int64_t ldb, cx<T> beta,
                                               S* __restrict__ C, int64_t ldc) {
-  constexpr int BM = 64, BN = 64, BK = 8;
-  __shared__ cx<T> As[BK][BM + 1];
-  __shared__ cx<T> Bs[BK][BN + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-  cx<T> acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = {(T)0, (T)0};
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int idx = threadIdx.x + 256 * e;  // 512 = BM*BK
-      const int am = idx / BK, ak = idx % BK;
-      const int64_t gm = m0 + am, gk = k0 + ak;
-      cx<T> v = {(T)0, (T)0};
-      if (gm < M && gk < K) {
-        const S a = A[gm * lda + gk];
-        v = {(T)a.re, (T)a.im};
-      }
-      As[ak][am] = v;
-      const int bk = idx / BN, bn = idx % BN;
-      const int64_t hk = k0 + bk, hn = n0 + bn;
-      cx<T> w = {(T)0, (T)0};
-      if (hk < K && hn < N) {
-        const S b = B[hk * ldb + hn];
-        w = {(T)b.re, (T)b.im};
-      }
-      Bs[bk][bn] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      cx<T> a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cfma(acc[r][c], a[r], b[c]);
-    }
-    __syncthreads();
-  }
-  const bool bz = beta.re == (T)0 && beta.im == (T)0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t gm = m0 + ty + 16 * r, gn = n0 + tx + 16 * c;
-      if (gm < M && gn < N) {
-        cx<T> v = alpha * acc[r][c];
-        if (!bz) {
-          const S o = C[gm * ldc + gn];
-          v = v + beta * cx<T>{(T)o.re, (T)o.im};
-        }
-        C[gm * ldc + gn] = S{v.re, v.im};
-      }
-    }
+  __shared__ cx<T> As[GEMM_BK][GEMM_BM + 1];
+  __shared__ cx<T> Bs[GEMM_BK][GEMM_BN + 1];
+  gemm_tile<S, T>(blockIdx.x, blockIdx.y, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, As, Bs);
 }
 
 void launch_gemm(Prec p, int64_t M, int64_t N, int64_t K, c128 alpha, const void* A, int64_t lda, const void* B,

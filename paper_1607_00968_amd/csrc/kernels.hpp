@@ -132,4 +132,31 @@ void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);
 // is rotated in place; G is scratch of (k+1) * P complex.
 void launch_cg_ls(int P, int k, c128* H, const double* b2, c128* G, c128* Y, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Persistent cycle: the launches of one multigrid cycle recorded as phases
+// that one cooperative kernel runs in order, a grid-wide barrier after each.
+// Every phase runs the per-item code of the stand-alone kernel it replaces
+// (fine_item, gal_item, restrict_item, prolong_item, gemm_tile).
+// ---------------------------------------------------------------------------
+enum PhaseOp : int { PH_FINE = 0, PH_GAL = 1, PH_RESTRICT = 2, PH_PROLONG = 3, PH_ZERO = 4, PH_GEMM = 5 };
+struct Phase {
+  int op;            // PhaseOp
+  int mode;          // operator mode (FINE, GAL): 0 apply, 1 residual, 2 Jacobi, 3 Jacobi from zero
+  int pa, pb;        // Prec: field (FINE, GAL); in / out (RESTRICT); coarse / fine (PROLONG); GEMM storage
+  Geo g, gc;         // level (fine side of a transfer), coarse side of a transfer
+  const void* u;     // FINE/GAL: u; RESTRICT: fine residual; PROLONG: coarse correction; GEMM: B
+  const void* f;     // FINE/GAL: right-hand side
+  void* out;         // output (ZERO: the 16-byte units to clear; PROLONG: the fine field, updated)
+  const void* c0;    // FINE: diagonal; GAL: stencil; GEMM: A (the coarsest inverse)
+  const void* c1;    // FINE/GAL: w / diagonal
+  double ih[3];      // FINE: 1/h^2 per axis
+  int64_t n;         // ZERO: 16-byte units; GEMM: order of A
+};
+// Grid size of the persistent kernel for (dim, mixed): the workgroups that
+// are co-resident on the device (0 if the device cannot launch it).
+int persist_grid(int dim, bool mixed);
+// Runs the nph phases at ph (device memory) with a cooperative launch of
+// `grid` workgroups; returns the launch status.
+hipError_t launch_cycle_persist(int dim, bool mixed, const Phase* ph, int nph, int grid, hipStream_t s);
+
 }  // namespace helm
