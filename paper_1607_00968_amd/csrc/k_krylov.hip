@@ -115,10 +115,11 @@ __global__ __launch_bounds__(256) void k_gram_final(int nblk, int P, int pb, int
 
 int64_t gram_part_elems(int P) { return (int64_t)GRAM_BLOCKS * GRAM_MAXACC * P; }
 
-// Workgroups for a column reduction over N points: at least 32 loop trips
-// per lane (PT = 256/P points per trip), at most GRAM_BLOCKS.
+// Workgroups for a column reduction over N points: at least 8 loop trips
+// per lane (PT = 256/P points per trip), at most GRAM_BLOCKS, so that small
+// grids (the 47^3 coarsest level) still fill the device.
 static int part_blocks(int64_t N, int P) {
-  const int64_t pts = (int64_t)(256 / P) * 32;
+  const int64_t pts = (int64_t)(256 / P) * 8;
   int64_t nb = (N + pts - 1) / pts;
   if (nb > GRAM_BLOCKS) nb = GRAM_BLOCKS;
   return nb < 1 ? 1 : (int)nb;
