@@ -285,7 +285,10 @@ helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const floa
 /* Training pairs from a solver: until the next call, every coarsest solve of
  * `h` (3D; coarse must be LU or GMRES; its coarsest grid must fit D) stores
  * (input volume, exact-solve target) of each nonzero column into a pool of
- * max_pairs volumes held by n (reservoir sampling). max_pairs == 0 detaches. */
+ * max_pairs volumes held by n (reservoir sampling). max_pairs == 0 detaches;
+ * max_pairs < 0 attaches to h and keeps n's existing pool (h's coarsest grid
+ * must have the pool's dimensions), so that one pool holds the pairs of
+ * several problems. */
 helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs);
 int64_t helm_net_pairs(helm_net n);
 /* Copy pool entry i (0 <= i < helm_net_pairs): x DEVICE FP32 [D^3][4] (the

@@ -1622,6 +1622,13 @@ helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs) {
   if (h->dim != 3) return fail(HELM_ERR_UNSUPPORTED, "pairs are captured from 3D problems only");
   if (h->coarse != HELM_COARSE_LU && h->coarse != HELM_COARSE_GMRES)
     return fail(HELM_ERR_INVALID_ARG, "pairs need an LU or GMRES coarsest solve");
+  if (max_pairs < 0) {
+    // keep the pool: pairs of several problems with equal coarsest grids
+    helm_status st = learned::capture_continue(n->n, coarse_view(h), n->s);
+    if (st != HELM_OK) return st;
+    h->cap = n->n;
+    return HELM_OK;
+  }
   helm_status st = learned::bind(n->n, coarse_view(h), n->s);
   if (st != HELM_OK) return st;
   if ((st = learned::capture_begin(n->n, max_pairs)) != HELM_OK) return st;

@@ -993,6 +993,7 @@ struct Net {
   // pool of training pairs
   int cap_max = 0, cap_n = 0;
   int64_t cap_seen = 0;
+  Box cap_box{0, 0, 0};  // coarsest grid the pool's pairs live on
   bf16* xs = nullptr;
   float* ts = nullptr;
   std::mt19937_64 rng{12345};
@@ -1443,6 +1444,17 @@ helm_status capture_begin(Net* n, int max_pairs) {
   LCHECK(hipMalloc(&n->xs, 8 * n->V * (size_t)max_pairs));
   LCHECK(hipMalloc(&n->ts, 8 * n->V * (size_t)max_pairs));
   n->cap_max = max_pairs;
+  n->cap_box = n->box;
+  return HELM_OK;
+}
+
+helm_status capture_continue(Net* n, const Coarse& g, hipStream_t s) {
+  if (n->cap_max < 1) return fail(HELM_ERR_INVALID_ARG, "no pair pool to continue (start one with max_pairs > 0)");
+  helm_status st = bind(n, g, s);
+  if (st != HELM_OK) return st;
+  if (n->box.nx != n->cap_box.nx || n->box.ny != n->cap_box.ny || n->box.nz != n->cap_box.nz)
+    return fail(HELM_ERR_INVALID_ARG, "the pool holds %dx%dx%d coarsest grids, this handle has %dx%dx%d",
+                n->cap_box.nx, n->cap_box.ny, n->cap_box.nz, n->box.nx, n->box.ny, n->box.nz);
   return HELM_OK;
 }
 

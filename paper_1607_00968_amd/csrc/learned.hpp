@@ -66,6 +66,9 @@ uint64_t scratch_gen(const Net* n);
 // Training pairs (f, e = exact coarsest solution) of the bound grid, kept by
 // reservoir sampling in a pool of max_pairs volumes.
 helm_status capture_begin(Net* n, int max_pairs);
+// Binds to another coarsest grid of the same dimensions and keeps the pool
+// (pairs from several problems in one pool).
+helm_status capture_continue(Net* n, const Coarse& g, hipStream_t s);
 void capture(Net* n, int P, const void* f, const void* e, hipStream_t s);
 int64_t pairs(const Net* n);
 // Copy pool entry i: x [D^3][4] and target [D^3][2], device FP32.

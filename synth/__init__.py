@@ -216,6 +216,14 @@ def config(k: int, n: int | None = None, nsrc: tuple | None = None,
     raise ValueError(k)
 
 
+def train_config(j: int, n: int = 128, nsrc: tuple = (8, 4)) -> Problem:
+    """Training model j of the learned coarsest correction: the family of
+    configs 2-3 (8 layers + 10% smooth perturbation, 12-cell layer, 8 ppw,
+    3 levels) with seed 5000 + j, so that no training model is a benchmark
+    model; 32 surface sources (8x4)."""
+    return _make(3, n, layered_model(3, n, 5000 + j), 12, 8.0, nsrc, f"train{j}", 3, 5)
+
+
 def batch_instances(count: int = 48, seed: int = 4000, sizes_2d=None, sizes_3d=None,
                     ppw: tuple = (8.0, 12.0)) -> list:
     """Independent uneven instances (the batched workload), one seed each.

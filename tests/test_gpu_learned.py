@@ -198,6 +198,36 @@ def train_on(hd, p, net, nrhs=8, pairs=256, steps=150, batch=8, lr=2e-3, seed=0)
     return net.train(steps, batch, lr=lr, seed=seed)
 
 
+def test_capture_pool_spans_problems():
+    """max_pairs < 0 keeps the pool: the pairs of two separately seeded
+    training models end up in one pool; another coarsest size or a network
+    without a pool is refused."""
+    hs, ps = [], []
+    for j in (0, 1):
+        p = synth.train_config(j, n=32, nsrc=(2, 1))
+        ps.append(p)
+        hs.append(pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                                precision="mixed", coarse="lu"))
+    D = (max(pk.helm_level_dims(hs[0], 2)) + 3) // 4 * 4
+    net = pk.helm_net_create(D, 2, seed=4)
+    with pytest.raises(pk.HelmError):
+        pk.helm_net_capture(hs[0], net, -1)  # no pool yet
+    counts = []
+    for k, (p, hd) in enumerate(zip(ps, hs)):
+        pk.helm_net_capture(hd, net, 4096 if k == 0 else -1)
+        Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
+        info = pk.helm_solve_block(hd, Q, torch.zeros_like(Q), tol=1e-6, restart=5, block_size=1)
+        pk.helm_net_capture(hd, net, 0)
+        counts.append(net.pairs())
+        assert info["converged_all"]
+    assert 0 < counts[0] < counts[1] <= 4096, counts
+    big = synth.train_config(0, n=64, nsrc=(1, 1))
+    hb = pk.helm_setup(big.dim, big.n, big.h, big.m, big.gamma, big.omega, shift=big.shift, levels=3,
+                       precision="mixed", coarse="lu")
+    with pytest.raises(pk.HelmError):
+        pk.helm_net_capture(hb, net, -1)
+
+
 def test_training_lowers_loss():
     p, hd = coarse_problem(32, 3)
     nu = pk.helm_level_dims(hd, 2)
