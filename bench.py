@@ -99,6 +99,29 @@ def train_coarse_net(args, pk, synth, np, torch):
     return blob, info
 
 
+def train_in_child(args):
+    """Run the training in a child process (same interpreter, this script
+    with --train-only): all of its device memory (teacher hierarchies, the
+    pair pool, optimiser state) is returned to the driver before the solver
+    allocates its fields. Returns (blob, info)."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "net.bin")
+        cmd = [sys.executable, "-u", os.path.abspath(__file__), "--train-only", out, "--n", str(args.n),
+               "--precision", args.precision, "--restart", str(args.restart), "--train-n", str(args.train_n),
+               "--train-steps", str(args.train_steps), "--train-models", str(args.train_models),
+               "--train-pairs", str(args.train_pairs)]
+        r = subprocess.run(cmd)
+        if r.returncode != 0:
+            raise RuntimeError(f"training process failed with status {r.returncode}")
+        with open(out, "rb") as fh:
+            blob = fh.read()
+        with open(out + ".json") as fh:
+            info = json.load(fh)
+    return blob, info
+
+
 def fp64_compare(args, p, Q, pk, torch):
     """The plain FP64 GPU solver (GMRES(20) coarsest) on the same block: one
     untimed warm-up solve, then one timed solve."""
@@ -216,6 +239,10 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=2000,
                     help="cap on cycles per solve (profiling runs; a capped solve reports value 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-only", default=None, metavar="PATH",
+                    help="train the coarsest network, write its blob to PATH (and PATH.json) and exit")
+    ap.add_argument("--net", default=None, metavar="PATH",
+                    help="use the network blob at PATH (from --train-only) instead of training")
     args = ap.parse_args()
     if args.coarse_iters is None:
         args.coarse_iters = 12 if args.coarse == "learned" else 20
@@ -232,14 +259,28 @@ def main():
     import synth
     import paper_1607_00968_amd as pk
 
+    if args.train_only:
+        blob, info = train_coarse_net(args, pk, synth, np, torch)
+        with open(args.train_only, "wb") as fh:
+            fh.write(blob)
+        with open(args.train_only + ".json", "w") as fh:
+            json.dump(info, fh)
+        return
     if args.workload == "batch":
         print(json.dumps(run_batch(args, pk, synth, np, torch)), flush=True)
         return
     p = synth.config(3, n=args.n)
     net_blob, net_info = None, None
-    if args.coarse == "learned":
+    if args.coarse == "learned" and args.net:
+        with open(args.net, "rb") as fh:
+            net_blob = fh.read()
+        net_info = {"from": args.net}
+        if os.path.exists(args.net + ".json"):
+            with open(args.net + ".json") as fh:
+                net_info.update(json.load(fh))
+    elif args.coarse == "learned":
         note(f"training the coarsest-grid network on {args.train_models} models at {args.train_n}^3")
-        net_blob, net_info = train_coarse_net(args, pk, synth, np, torch)
+        net_blob, net_info = train_in_child(args)
         note(f"trained in {net_info['train_s']} s, loss {net_info['loss_first']} -> {net_info['loss_last']}")
     t0 = time.perf_counter()
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
