@@ -92,11 +92,15 @@ typedef struct {
                                   network's correction (0..48, 0 = network alone) */
   const void* net;             /* HOST weights blob for HELM_COARSE_LEARNED (or NULL) */
   size_t net_bytes;
+  int32_t coarse_restarts;     /* GMRES and learned coarsest solves: restarted GMRES,
+                                  this many cycles of coarse_iters steps, each on the
+                                  current coarsest residual (0..16; 0 and 1: one cycle).
+                                  The learned fallback stays max(k, 20) steps from zero. */
 } helm_setup_desc;
 
 /* Fill `d` with the paper's defaults: shift 0.2, 2+2 sweeps at 0.8, V-cycle,
- * FP64, LU coarsest (20 GMRES steps if HELM_COARSE_GMRES is chosen),
- * 3 levels. Geometry, m, gamma and omega are left zero. */
+ * FP64, LU coarsest (20 GMRES steps, one cycle, if HELM_COARSE_GMRES is
+ * chosen), 3 levels. Geometry, m, gamma and omega are left zero. */
 void helm_setup_desc_default(helm_setup_desc* d);
 
 typedef struct {

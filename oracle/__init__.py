@@ -71,6 +71,7 @@ def lib():
         L.orc_level_stencil.argtypes = [P, C.c_int, P]
         L.orc_vcycle.argtypes = [P, C.c_int, P, P]
         L.orc_coarse_solve.argtypes = [P, C.c_int, P, P]
+        L.orc_set_coarse_restarts.argtypes = [P, C.c_int]
         L.orc_block_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_int), P, P]
         L.orc_householder_qr.argtypes = [C.c_int64, C.c_int, P, P]
@@ -185,7 +186,7 @@ class Hierarchy:
     COARSE = {"lu": 0, "gmres": 1, "none": 2}
 
     def __init__(self, g, m, gamma, omega, beta, levels, nu_pre=None, nu_post=None, wjac=None,
-                 coarse="lu", coarse_iters=20):
+                 coarse="lu", coarse_iters=20, coarse_restarts=1):
         self.g = g
         self.levels = levels
         self._m, self._gamma = _d(m), _d(gamma)
@@ -204,6 +205,8 @@ class Hierarchy:
                                  int(coarse_iters))
         if not self.h:
             raise RuntimeError("oracle setup failed")
+        if coarse_restarts > 1:
+            lib().orc_set_coarse_restarts(self.h, int(coarse_restarts))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -352,6 +352,7 @@ void orc_band_free(orc_band* b) {
 struct orc_hier {
   int levels;
   int coarse_kind, coarse_iters;
+  int coarse_restarts; /* GMRES cycles of coarse_iters steps (restarted GMRES); 0 or 1: one */
   og_grid g[8];
   ozc* st[8];   /* st[0] = shifted fine operator as a stencil */
   int nu_pre[8], nu_post[8];
@@ -468,6 +469,8 @@ static void coarse_gmres(const og_grid* g, const ozc* st, int k, const ozc* f, o
   free(Hm);
 }
 
+void orc_set_coarse_restarts(orc_hier* H, int restarts) { H->coarse_restarts = restarts; }
+
 void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u) {
   const int l = H->levels - 1;
   const int64_t n = og_npts(&H->g[l]);
@@ -475,9 +478,27 @@ void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u) {
     memcpy(u, f, sizeof(ozc) * n * nrhs);
     orc_band_solve(&H->lu, nrhs, u);
   } else if (H->coarse_kind == ORC_COARSE_GMRES) {
+    /* restarted GMRES(k): the first cycle from zero, each further one on the
+     * current residual, its correction added (section 5.3, GMRES-based
+     * coarsest solver) */
 #pragma omp parallel for schedule(dynamic) if (nrhs > 1 && n > 4096)
-    for (int s = 0; s < nrhs; ++s)
-      coarse_gmres(&H->g[l], H->st[l], H->coarse_iters, f + (int64_t)s * n, u + (int64_t)s * n);
+    for (int s = 0; s < nrhs; ++s) {
+      const ozc* fs = f + (int64_t)s * n;
+      ozc* us = u + (int64_t)s * n;
+      coarse_gmres(&H->g[l], H->st[l], H->coarse_iters, fs, us);
+      if (H->coarse_restarts > 1) {
+        ozc* r = (ozc*)malloc(sizeof(ozc) * n);
+        ozc* d = (ozc*)malloc(sizeof(ozc) * n);
+        for (int q = 1; q < H->coarse_restarts; ++q) {
+          orc_apply_stencil(&H->g[l], H->st[l], 1, us, r);
+          for (int64_t t = 0; t < n; ++t) r[t] = fs[t] - r[t];
+          coarse_gmres(&H->g[l], H->st[l], H->coarse_iters, r, d);
+          for (int64_t t = 0; t < n; ++t) us[t] += d[t];
+        }
+        free(r);
+        free(d);
+      }
+    }
   } else {
     /* relaxation only: nu_pre + nu_post damped Jacobi sweeps from zero */
     int sweeps = H->nu_pre[l] + H->nu_post[l];

@@ -100,6 +100,9 @@ void orc_level_stencil(const orc_hier* H, int l, ozc* st);
 void orc_vcycle(const orc_hier* H, int nrhs, const ozc* f, ozc* u);
 /* The coarsest-grid solve as used inside the cycle (M_L^-1 f for LU). */
 void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u);
+/* GMRES coarsest solve as `restarts` cycles of coarse_iters steps (restarted
+ * GMRES; the default is one cycle). */
+void orc_set_coarse_restarts(orc_hier* H, int restarts);
 
 /* Block FGMRES(restart) for H X = Q with X0 = 0 (or X on entry if warm).
  * Right preconditioning by the V-cycle (or identity if H == NULL-prec flag).

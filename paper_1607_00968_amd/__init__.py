@@ -65,7 +65,7 @@ class SetupDesc(C.Structure):
         ("nu_pre", C.c_int32 * MAX_LEVELS), ("nu_post", C.c_int32 * MAX_LEVELS),
         ("jacobi_weight", C.c_double * MAX_LEVELS), ("precision", C.c_int32),
         ("coarse", C.c_int32), ("cycle", C.c_int32), ("coarse_iters", C.c_int32),
-        ("net", C.c_void_p), ("net_bytes", C.c_size_t),
+        ("net", C.c_void_p), ("net_bytes", C.c_size_t), ("coarse_restarts", C.c_int32),
     ]
 
 
@@ -184,7 +184,7 @@ def _per_level(v, levels, typ):
 
 def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_post=2,
                jacobi_weight=0.8, precision="fp64", coarse="lu", cycle="V", coarse_iters=20,
-               net=None, stream=None) -> Handle:
+               net=None, stream=None, coarse_restarts=1) -> Handle:
     """Build the hierarchy. m, gamma: host float64 arrays of N entries."""
     d = SetupDesc()
     lib().helm_setup_desc_default(C.byref(d))
@@ -208,6 +208,7 @@ def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_pos
     d.coarse = COARSE[coarse]
     d.cycle = CYCLE[cycle]
     d.coarse_iters = int(coarse_iters)
+    d.coarse_restarts = int(coarse_restarts)
     blob = None
     if net is not None:
         blob = np.ascontiguousarray(np.frombuffer(net, dtype=np.uint8))

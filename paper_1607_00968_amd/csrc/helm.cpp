@@ -89,6 +89,7 @@ struct helm_ctx {
   int coarse = HELM_COARSE_LU;
   int cycle = HELM_CYCLE_V;
   int coarse_iters = 20;
+  int coarse_restarts = 1;  // GMRES cycles of coarse_iters steps on the coarsest grid
   // coarsest GMRES storage: basis, Hessenberg, coefficients
   void* cg_mem = nullptr;
   int cg_P = 0;
@@ -429,7 +430,15 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
     else
       launch_gemm(P32, c->nc, P, c->nc, c128{1, 0}, c->Minv32, c->nc, f, P, c128{0, 0}, out, P, s);
   } else if (c->coarse == HELM_COARSE_GMRES) {
+    // restarted GMRES(coarse_iters): the first cycle from zero, each further
+    // one on the current residual (Rr of the coarsest level is free)
     coarse_gmres(c, P, f, out, c->coarse_iters, s);
+    for (int q = 1; q < c->coarse_restarts; ++q) {
+      void* r = c->lv[l].Rr;
+      level_op(c, l, 1, P, out, f, r, s);
+      coarse_gmres(c, P, r, r, c->coarse_iters, s);
+      field_axpy(c, l, P, r, out, s);
+    }
   } else if (c->coarse == HELM_COARSE_LEARNED && c->net) {
     bool ok = false;
     if (c->capturing) {
@@ -444,12 +453,15 @@ static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStre
       ++c->fallbacks;
       coarse_gmres(c, P, f, out, coarse_gmres_cap(c), s);
     } else if (c->coarse_iters > 0) {
-      // the network's correction is the initial guess of coarse_iters GMRES
-      // steps on the remaining residual (Rr of the coarsest level is free)
+      // the network's correction is the initial guess of restarted
+      // GMRES(coarse_iters) on the remaining residual (Rr of the coarsest
+      // level is free)
       void* r = c->lv[l].Rr;
-      level_op(c, l, 1, P, out, f, r, s);
-      coarse_gmres(c, P, r, r, c->coarse_iters, s);
-      field_axpy(c, l, P, r, out, s);
+      for (int q = 0; q < c->coarse_restarts; ++q) {
+        level_op(c, l, 1, P, out, f, r, s);
+        coarse_gmres(c, P, r, r, c->coarse_iters, s);
+        field_axpy(c, l, P, r, out, s);
+      }
     }
   } else {
     // relaxation only: nu_pre + nu_post damped Jacobi sweeps from zero
@@ -765,6 +777,7 @@ void helm_setup_desc_default(helm_setup_desc* d) {
   d->coarse = HELM_COARSE_LU;
   d->cycle = HELM_CYCLE_V;
   d->coarse_iters = 20;
+  d->coarse_restarts = 1;
 }
 
 const char* helm_status_string(helm_status s) {
@@ -825,6 +838,8 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 1..48");
   if (d->coarse == HELM_COARSE_LEARNED && (d->coarse_iters < 0 || d->coarse_iters > 48))
     return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 0..48 with the learned coarsest correction");
+  if (d->coarse_restarts < 0 || d->coarse_restarts > 16)
+    return fail(HELM_ERR_INVALID_ARG, "coarse_restarts must be 0..16 (0 and 1: one GMRES cycle)");
   if (d->cycle < HELM_CYCLE_V || d->cycle > HELM_CYCLE_K) return fail(HELM_ERR_INVALID_ARG, "bad cycle kind");
   if (d->cycle == HELM_CYCLE_K) return fail(HELM_ERR_UNSUPPORTED, "the K-cycle is not built in this library version");
   const int f = 1 << (d->levels - 1);
@@ -853,6 +868,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   c->coarse = d->coarse;
   c->cycle = d->cycle;
   c->coarse_iters = d->coarse_iters;
+  c->coarse_restarts = std::max(1, d->coarse_restarts);
   c->omega = d->omega;
   c->shift = d->shift;
   for (int l = 0; l < HELM_MAX_LEVELS; ++l) {

@@ -53,11 +53,13 @@ def small_problem(dim, n, levels, seed=5, nsrc=None):
     return p
 
 
-def setup_both(p, levels, precision="fp64", coarse="lu", coarse_iters=20):
+def setup_both(p, levels, precision="fp64", coarse="lu", coarse_iters=20, coarse_restarts=1):
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=levels,
-                       precision=precision, coarse=coarse, coarse_iters=coarse_iters)
+                       precision=precision, coarse=coarse, coarse_iters=coarse_iters,
+                       coarse_restarts=coarse_restarts)
     ho = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels,
-                          coarse="gmres" if coarse == "gmres" else "lu", coarse_iters=coarse_iters)
+                          coarse="gmres" if coarse == "gmres" else "lu", coarse_iters=coarse_iters,
+                          coarse_restarts=coarse_restarts)
     return hd, ho
 
 
@@ -102,15 +104,24 @@ def test_coarse_lu_solve_matches_oracle(dim, n, levels):
     assert rel(host(E), ho.coarse_solve(F)) <= 1e-10
 
 
-@pytest.mark.parametrize("k", [4, 20])
-def test_coarse_gmres_matches_oracle(k):
+@pytest.mark.parametrize("k,restarts", [(4, 1), (20, 1), (4, 3)])
+def test_coarse_gmres_matches_oracle(k, restarts):
     p = small_problem(3, 32, 3)
-    hd, ho = setup_both(p, 3, coarse="gmres", coarse_iters=k)
+    hd, ho = setup_both(p, 3, coarse="gmres", coarse_iters=k, coarse_restarts=restarts)
     Nc = int(np.prod(pk.helm_level_dims(hd, 2)))
     F = crand(6, Nc)
     E = torch.empty((6, Nc), dtype=torch.complex128, device="cuda")
     pk.helm_coarse_solve(hd, dev(F), E)
     assert rel(host(E), ho.coarse_solve(F)) <= 1e-9
+
+
+def test_vcycle_fp64_restarted_gmres_coarsest_matches_oracle():
+    p = small_problem(3, 32, 3)
+    hd, ho = setup_both(p, 3, coarse="gmres", coarse_iters=6, coarse_restarts=2)
+    F = crand(3, p.N)
+    Z = torch.empty((3, p.N), dtype=torch.complex128, device="cuda")
+    pk.helm_precond(hd, dev(F), Z)
+    assert rel(host(Z), ho.vcycle(F)) <= 1e-9
 
 
 @pytest.mark.parametrize("dim,n,levels,coarse", [(2, 32, 3, "lu"), (3, 16, 3, "lu"), (3, 32, 3, "gmres"),

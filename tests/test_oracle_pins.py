@@ -379,6 +379,43 @@ def test_vcycle_with_gmres_coarsest_equals_dense(k):
         assert np.allclose(out[s], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
 
 
+def test_coarse_gmres_restarts_equal_krylov_minimisers():
+    """Restarted GMRES(k) on the coarsest grid: every restart adds the
+    minimiser of ||r - A d|| over the Krylov space K_k(A, r) of the current
+    residual r. The reference builds the explicit Krylov matrix [r, Ar, ...]
+    and solves that least-squares problem directly (no Arnoldi); the residual
+    never grows from one restart to the next, and one restart is the plain
+    fixed-step solve."""
+    dim, n, levels, k = 2, 16, 2, 3
+    m, gamma = rand_model(dim, n)
+    omega, beta = 12.0, 0.2
+    Ms, Ps = dense_hierarchy(dim, n, m, gamma, omega, beta, levels)
+    A = Ms[-1]
+    g = oracle.grid(dim, (n,) * dim, (1 / n,) * dim)
+    F = crand(2, A.shape[0])
+    res = []
+    for R in (1, 2, 3):
+        H = oracle.Hierarchy(g, m, gamma, omega, beta, levels, coarse="gmres", coarse_iters=k, coarse_restarts=R)
+        out = H.coarse_solve(F)
+        for s in range(2):
+            x = np.zeros(A.shape[0], complex)
+            for _ in range(R):
+                r = F[s] - A @ x
+                K = np.empty((len(r), k), complex)
+                K[:, 0] = r / np.linalg.norm(r)
+                for j in range(1, k):
+                    K[:, j] = A @ K[:, j - 1]
+                    K[:, j] /= np.linalg.norm(K[:, j])
+                y = np.linalg.lstsq(A @ K, r, rcond=None)[0]
+                x = x + K @ y
+            assert np.allclose(out[s], x, rtol=1e-9, atol=1e-9 * np.abs(x).max())
+        res.append(np.linalg.norm(F - out @ A.T, axis=1))
+    assert np.all(res[1] <= res[0] * (1 + 1e-12)) and np.all(res[2] <= res[1] * (1 + 1e-12))
+    H1 = oracle.Hierarchy(g, m, gamma, omega, beta, levels, coarse="gmres", coarse_iters=k)
+    assert np.array_equal(H1.coarse_solve(F), oracle.Hierarchy(g, m, gamma, omega, beta, levels, coarse="gmres",
+                                                               coarse_iters=k, coarse_restarts=1).coarse_solve(F))
+
+
 def test_vcycle_poisson_contraction():
     """omega = 0: V(2,2) with damped Jacobi is a convergent solver for the
     Laplacian; per-cycle error reduction stays well below the 2D smoothing
