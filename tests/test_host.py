@@ -1,0 +1,74 @@
+"""Host-side checks that need no GPU: the ctypes mirrors of the ABI structs
+follow include/helm.h field by field, new options are validated before any
+device call, the network's training models are not the benchmark's model,
+and the bench finds the committed traffic figure of the tile it ran with."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helm.h")
+
+
+def header_struct_fields(name):
+    """Field names, in order, of `typedef struct { ... } name;` in helm.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ident = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[[^\]]*\])?\s*$", decl)
+        fields.append(ident[0])
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("helm_setup_desc", "SetupDesc"), ("helm_solve_opts", "SolveOpts"),
+                                          ("helm_solve_info", "SolveInfo")])
+def test_ctypes_structs_follow_the_header(cname, pyname):
+    import paper_1607_00968_amd as pk
+    py = [f[0] for f in getattr(pk, pyname)._fields_]
+    assert py == header_struct_fields(cname)
+
+
+def test_new_options_are_validated_without_device():
+    import paper_1607_00968_amd as pk
+    m = np.ones(7 * 7)
+    g = np.zeros(7 * 7)
+    for bad in (-1, 17):
+        with pytest.raises(pk.HelmError) as e:
+            pk.helm_setup(2, (8, 8), (1 / 8, 1 / 8), m, g, omega=1.0, levels=2, coarse="gmres", coarse_restarts=bad,
+                          stream=0)
+        assert e.value.status == pk.HELM_ERR_INVALID_ARG
+
+
+def test_training_models_are_not_the_benchmark_model():
+    import synth
+    bench_m = synth.config(3, n=32).m
+    ms = [synth.train_config(j, n=32).m for j in range(4)]
+    for j, mj in enumerate(ms):
+        assert mj.shape == bench_m.shape
+        assert not np.allclose(mj, bench_m), j
+        for k in range(j):
+            assert not np.allclose(mj, ms[k]), (j, k)
+    t = synth.train_config(0, n=32)
+    assert t.levels == 3 and t.Q.shape[0] == 32
+
+
+def test_bench_reads_the_traffic_of_each_committed_tile():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    text = open(os.path.join(ROOT, "profiles", "fine_sweep_mixed_192x64_traffic.md")).read()
+    tiles = re.findall(r"^traffic: .*tile=(\d+)x(\d+)", text, flags=re.M)
+    assert tiles
+    for ry, zc in tiles:
+        v = bench.committed_traffic("mixed", 192, 64, (int(ry), int(zc)))
+        assert v is not None and 10_814_135_792 < v < 2 * 10_814_135_792
+    assert bench.committed_traffic("mixed", 192, 64, (4, 7)) is None
+    assert bench.committed_traffic("fp64", 192, 64, (int(tiles[0][0]), int(tiles[0][1]))) is None
