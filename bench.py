@@ -77,7 +77,7 @@ def train_coarse_net(args, pk, synth, np, torch):
     t0 = time.perf_counter()
     net, D = None, None
     for j in range(args.train_models):
-        pt = synth.train_config(j, n=args.train_n)
+        pt = synth.training_model(j, n=args.train_n)
         teach = pk.helm_setup(pt.dim, pt.n, pt.h, pt.m, pt.gamma, pt.omega, shift=pt.shift, levels=3,
                               precision=args.precision, coarse="lu")
         if net is None:
@@ -274,7 +274,7 @@ def main():
     if args.workload == "batch":
         print(json.dumps(run_batch(args, pk, synth, np, torch)), flush=True)
         return
-    p = synth.config(3, n=args.n)
+    p = synth.layered_3d(n=args.n, seed=3, nsrc=(8, 8))
     net_blob, net_info = None, None
     if args.coarse == "learned" and args.net:
         with open(args.net, "rb") as fh:

@@ -26,8 +26,8 @@ import numpy as np
 
 __all__ = [
     "Problem", "gradient_model_2d", "layered_model", "layer_gamma",
-    "omega_for_ppw", "surface_sources", "random_rhs", "config",
-    "CONFIGS",
+    "omega_for_ppw", "surface_sources", "random_rhs", "gradient_2d", "layered_3d",
+    "training_model", "batch_instances",
 ]
 
 
@@ -191,35 +191,25 @@ def _make(dim, n, v, width, ppw, srcgrid, name, levels, restart, top=False):
                    name=name)
 
 
-def config(k: int, n: int | None = None, nsrc: tuple | None = None,
-           levels: int | None = None) -> Problem:
-    """The benchmark configurations (1-based), optionally resized.
-
-    1: 2D 128^2, linear gradient 1.5->3.0 km/s, 16-cell layer, 10 ppw,
-       4 sources, 3 levels, FGMRES(10).
-    2: 3D 128^3, seeded 8-layer model + 10% smooth perturbation, 12-cell
-       layer, 8 ppw, 32 sources (8x4), 4 levels, FGMRES(5). Seed 2.
-    3: as 2 at 192^3 with 64 sources (8x8). Seed 3.
-    """
-    if k == 1:
-        n = n or 128
-        g = nsrc or (4,)
-        return _make(2, n, gradient_model_2d(n), 16, 10.0, g, "cfg1", levels or 3, 10)
-    if k == 2:
-        n = n or 128
-        g = nsrc or (8, 4)
-        return _make(3, n, layered_model(3, n, 2), 12, 8.0, g, "cfg2", levels or 4, 5)
-    if k == 3:
-        n = n or 192
-        g = nsrc or (8, 8)
-        return _make(3, n, layered_model(3, n, 3), 12, 8.0, g, "cfg3", levels or 4, 5)
-    raise ValueError(k)
+def gradient_2d(n: int = 128, nsrc: tuple = (4,), levels: int = 3) -> Problem:
+    """2D workload: n^2 cells (default 128^2), velocity linear in depth from
+    1.5 to 3.0 km/s, 16-cell absorbing layer, 10 points per wavelength,
+    sources on the first unknown row, FGMRES(10)."""
+    return _make(2, n, gradient_model_2d(n), 16, 10.0, nsrc, f"gradient2d-{n}", levels, 10)
 
 
-def train_config(j: int, n: int = 128, nsrc: tuple = (8, 4)) -> Problem:
-    """Training model j of the learned coarsest correction: the family of
-    configs 2-3 (8 layers + 10% smooth perturbation, 12-cell layer, 8 ppw,
-    3 levels) with seed 5000 + j, so that no training model is a benchmark
+def layered_3d(n: int = 128, seed: int = 2, nsrc: tuple = (8, 4), levels: int = 4) -> Problem:
+    """3D workload: n^3 cells, a seeded 8-layer velocity model (1.5-4.5 km/s)
+    with a 10% smooth perturbation, 12-cell absorbing layer, 8 points per
+    wavelength, an nsrc[0] x nsrc[1] lattice of surface sources, FGMRES(5).
+    The 192^3 benchmark solve is layered_3d(192, seed=3, nsrc=(8, 8))."""
+    return _make(3, n, layered_model(3, n, seed), 12, 8.0, nsrc, f"layered3d-{n}-s{seed}", levels, 5)
+
+
+def training_model(j: int, n: int = 128, nsrc: tuple = (8, 4)) -> Problem:
+    """Training model j of the learned coarsest correction: the layered 3D
+    family (8 layers + 10% smooth perturbation, 12-cell layer, 8 ppw, 3
+    levels) with seed 5000 + j, so that no training model is a benchmark
     model; 32 surface sources (8x4)."""
     return _make(3, n, layered_model(3, n, 5000 + j), 12, 8.0, nsrc, f"train{j}", 3, 5)
 
@@ -252,5 +242,3 @@ def batch_instances(count: int = 48, seed: int = 4000, sizes_2d=None, sizes_3d=N
         out.append(_make(dim, n, v, width, w, grid, f"batch{k}", 3 if w >= 8.0 else 2, 5))
     return out
 
-
-CONFIGS = (1, 2, 3)

@@ -47,7 +47,7 @@ def check_replays(hd, Q, replays=3, **kw):
 
 
 def test_graph_2d_mixed_lu():
-    p = synth.config(1, levels=3)
+    p = synth.gradient_2d(levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="mixed", coarse="lu")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
@@ -55,7 +55,7 @@ def test_graph_2d_mixed_lu():
 
 
 def test_graph_3d_fp64_gmres_coarsest():
-    p = synth.config(2, n=32, nsrc=(2, 2), levels=3)
+    p = synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="fp64", coarse="gmres", coarse_iters=8)
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
@@ -63,7 +63,7 @@ def test_graph_3d_fp64_gmres_coarsest():
 
 
 def test_graph_3d_mixed_w_cycle():
-    p = synth.config(2, n=32, nsrc=(2, 2), levels=3)
+    p = synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="mixed", coarse="lu", cycle="W")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
@@ -83,7 +83,7 @@ def trained_blob(p, D, steps=60):
 
 
 def test_graph_learned_coarsest_and_fallback():
-    p = synth.config(2, n=32, nsrc=(2, 2), levels=3)
+    p = synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2)
     blob = trained_blob(p, 8)
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
     hl = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
@@ -105,7 +105,7 @@ def test_graph_timing_report_small_solve():
     """Not a correctness bound: reports eager vs graph solve time for the 2D
     128^2 workload (every kernel is a few microseconds long)."""
     import time
-    p = synth.config(1, levels=3)
+    p = synth.gradient_2d(levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="mixed", coarse="lu")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()

@@ -150,7 +150,7 @@ def test_loss_grad_matches_oracle(D, B):
 
 
 def coarse_problem(n=32, levels=3, precision="fp64", seed_src=(2, 2)):
-    p = synth.config(2, n=n, nsrc=seed_src, levels=levels)
+    p = synth.layered_3d(n=n, nsrc=seed_src, levels=levels, seed=2)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=levels,
                        precision=precision, coarse="lu")
     return p, hd
@@ -204,7 +204,7 @@ def test_capture_pool_spans_problems():
     without a pool is refused."""
     hs, ps = [], []
     for j in (0, 1):
-        p = synth.train_config(j, n=32, nsrc=(2, 1))
+        p = synth.training_model(j, n=32, nsrc=(2, 1))
         ps.append(p)
         hs.append(pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                                 precision="mixed", coarse="lu"))
@@ -221,7 +221,7 @@ def test_capture_pool_spans_problems():
         counts.append(net.pairs())
         assert info["converged_all"]
     assert 0 < counts[0] < counts[1] <= 4096, counts
-    big = synth.train_config(0, n=64, nsrc=(1, 1))
+    big = synth.training_model(0, n=64, nsrc=(1, 1))
     hb = pk.helm_setup(big.dim, big.n, big.h, big.m, big.gamma, big.omega, shift=big.shift, levels=3,
                        precision="mixed", coarse="lu")
     with pytest.raises(pk.HelmError):
@@ -311,7 +311,7 @@ def test_learned_guess_beats_gmres_from_zero():
     GMRES steps started from the trained network's correction need clearly
     fewer outer cycles than 4 steps from zero and than the untrained network;
     GMRES(20) from zero is reported for reference."""
-    p = synth.config(3, n=64, nsrc=(4, 4), levels=3)
+    p = synth.layered_3d(n=64, nsrc=(4, 4), levels=3, seed=3)
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
     teach = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                           precision="mixed", coarse="lu")
@@ -340,7 +340,7 @@ def test_learned_guess_beats_gmres_from_zero():
 
 
 def test_learned_setup_rejects_bad_blob():
-    p = synth.config(2, n=32, nsrc=(2, 2), levels=3)
+    p = synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2)
     with pytest.raises(pk.HelmError):
         pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, coarse="learned", net=b"HNETxxxx")
     with pytest.raises(pk.HelmError):

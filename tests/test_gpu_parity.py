@@ -47,9 +47,9 @@ def rel(a, b):
 
 def small_problem(dim, n, levels, seed=5, nsrc=None):
     if dim == 2:
-        p = synth.config(1, n=n, nsrc=nsrc or (3,), levels=levels)
+        p = synth.gradient_2d(n=n, nsrc=nsrc or (3,), levels=levels)
     else:
-        p = synth.config(2, n=n, nsrc=nsrc or (2, 2), levels=levels)
+        p = synth.layered_3d(n=n, nsrc=nsrc or (2, 2), levels=levels, seed=2)
     return p
 
 
@@ -161,8 +161,8 @@ def check_solution(p, U, tol_res, Uref=None, err_tol=None):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("block_size", [4, 1])
-def test_solve_config1_2d(precision, block_size):
-    p = synth.config(1)  # 2D 128^2, 4 sources, 3 levels, FGMRES(10)
+def test_solve_2d_128_gradient(precision, block_size):
+    p = synth.gradient_2d()  # 2D 128^2, 4 sources, 3 levels, FGMRES(10)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision)
     Q = dev(p.Q)
     U = torch.zeros_like(Q)
@@ -178,7 +178,7 @@ def test_solve_config1_2d(precision, block_size):
 
 @pytest.mark.parametrize("precision,coarse", [("fp64", "lu"), ("mixed", "gmres")])
 def test_solve_3d_small(precision, coarse):
-    p = synth.config(2, n=32, nsrc=(3, 2), levels=3)  # ragged: 6 sources
+    p = synth.layered_3d(n=32, nsrc=(3, 2), levels=3, seed=2)  # ragged: 6 sources
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse=coarse)
     Q = dev(p.Q)
     U = torch.zeros_like(Q)
@@ -190,7 +190,7 @@ def test_solve_3d_small(precision, coarse):
 
 def test_solve_tracks_oracle_cycle_count_fp64():
     """Same algorithm, same stopping rule: FP64 cycle counts agree closely."""
-    p = synth.config(1, n=64, nsrc=(1,), levels=3)
+    p = synth.gradient_2d(n=64, nsrc=(1,), levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3)
     Q = dev(p.Q)
     U = torch.zeros_like(Q)
@@ -201,7 +201,7 @@ def test_solve_tracks_oracle_cycle_count_fp64():
 
 
 def test_zero_column_converged_at_zero():
-    p = synth.config(1, n=32, nsrc=(3,), levels=3)
+    p = synth.gradient_2d(n=32, nsrc=(3,), levels=3)
     Qn = p.Q.copy()
     Qn[1] = 0
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3)
@@ -214,7 +214,7 @@ def test_zero_column_converged_at_zero():
 
 
 def test_duplicate_columns_block_breakdown_is_reported():
-    p = synth.config(1, n=32, nsrc=(2,), levels=3)
+    p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
     Qd = np.concatenate([p.Q, p.Q[:1]])
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3)
     Q = dev(Qd)
@@ -230,7 +230,7 @@ def test_duplicate_columns_block_breakdown_is_reported():
 
 
 def test_nonfinite_rhs_rejected():
-    p = synth.config(1, n=32, nsrc=(2,), levels=3)
+    p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
     Qn = p.Q.copy()
     Qn[0, 5] = np.nan
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3)
@@ -242,7 +242,7 @@ def test_nonfinite_rhs_rejected():
 
 
 def test_not_converged_reports_last_iterate():
-    p = synth.config(1, n=64, nsrc=(2,), levels=3)
+    p = synth.gradient_2d(n=64, nsrc=(2,), levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3)
     Q = dev(p.Q)
     U = torch.zeros_like(Q)
@@ -266,7 +266,7 @@ def test_fine_tile_choices_are_bitwise_identical(precision, nrhs):
     tile's run); inputs are dense random and sparse point sources (the
     benchmark's right-hand sides). The 47^3 grid leaves ragged x/y tiles,
     coarse tiles and z chunks."""
-    p = synth.config(2, n=48, nsrc=(3, 2), levels=3)
+    p = synth.layered_3d(n=48, nsrc=(3, 2), levels=3, seed=2)
     F = dev(crand(nrhs, p.N))
     S = np.zeros((nrhs, p.N), complex)
     for c in range(nrhs):

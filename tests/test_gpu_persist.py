@@ -29,7 +29,7 @@ def solve(hd, Q, form, **kw):
 
 @pytest.mark.parametrize("precision,levels", [("mixed", 3), ("fp64", 3), ("fp64", 2), ("mixed", 4)])
 def test_persistent_2d_bitwise_equal_to_eager(precision, levels):
-    p = synth.config(1, levels=levels)
+    p = synth.gradient_2d(levels=levels)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=levels,
                        precision=precision, coarse="lu")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
@@ -49,7 +49,7 @@ def test_persistent_2d_bitwise_equal_to_eager(precision, levels):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_persistent_3d_converges_like_eager(precision):
-    p = synth.config(2, n=32, nsrc=(2, 2), levels=3)
+    p = synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision=precision, coarse="lu")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
@@ -64,7 +64,7 @@ def test_persistent_3d_converges_like_eager(precision):
 
 
 def test_persistent_rejects_unsupported_cycles():
-    p = synth.config(1, levels=3)
+    p = synth.gradient_2d(levels=3)
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
     for kw in (dict(coarse="gmres", coarse_iters=8), dict(coarse="lu", cycle="W")):
         hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3, precision="mixed", **kw)
@@ -80,7 +80,7 @@ def test_persistent_timing_report_small_solve():
     """Not a correctness bound: eager, graph and persistent solve times for
     the 2D 128^2 x 4 workload (every kernel is a few microseconds long)."""
     import time
-    p = synth.config(1, levels=3)
+    p = synth.gradient_2d(levels=3)
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="mixed", coarse="lu")
     Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()

@@ -48,14 +48,14 @@ def test_new_options_are_validated_without_device():
 
 def test_training_models_are_not_the_benchmark_model():
     import synth
-    bench_m = synth.config(3, n=32).m
-    ms = [synth.train_config(j, n=32).m for j in range(4)]
+    bench_m = synth.layered_3d(n=32, seed=3, nsrc=(8, 8)).m
+    ms = [synth.training_model(j, n=32).m for j in range(4)]
     for j, mj in enumerate(ms):
         assert mj.shape == bench_m.shape
         assert not np.allclose(mj, bench_m), j
         for k in range(j):
             assert not np.allclose(mj, ms[k]), (j, k)
-    t = synth.train_config(0, n=32)
+    t = synth.training_model(0, n=32)
     assert t.levels == 3 and t.Q.shape[0] == 32
 
 

@@ -480,7 +480,7 @@ def test_fgmres_manufactured_solution(p):
 
 
 def test_fgmres_converged_columns_meet_tolerance_and_dense_solution():
-    p = synth.config(1, n=32, nsrc=(3,), levels=3)
+    p = synth.gradient_2d(n=32, nsrc=(3,), levels=3)
     g = oracle.grid(p.dim, p.n, p.h)
     H = oracle.setup_problem(p)
     X, it, rr, conv = H.fgmres(p.Q, tol=1e-8, restart=10, maxit=500)
@@ -492,7 +492,7 @@ def test_fgmres_converged_columns_meet_tolerance_and_dense_solution():
 
 def test_residual_estimates_track_true_residual():
     """Flexible Arnoldi identity: the LS residual is the true residual."""
-    p = synth.config(1, n=32, nsrc=(2,), levels=3)
+    p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
     H = oracle.setup_problem(p)
     X, it, rr, conv, hist = H.fgmres(p.Q, tol=1e-9, restart=50, maxit=50, hist=True)
     g = oracle.grid(p.dim, p.n, p.h)
