@@ -102,7 +102,7 @@ def train_coarse_net(args, pk, synth, np, torch):
 def train_in_child(args):
     """Run the training in a child process (same interpreter, this script
     with --train-only): all of its device memory (teacher hierarchies, the
-    pair pool, optimiser state) is returned to the driver before the solver
+    pair pool, optimiser state) is released to the device before the solver
     allocates its fields. Returns (blob, info)."""
     import subprocess
     import tempfile
@@ -255,7 +255,7 @@ def main():
         args.train_n = max(32, (2 * args.n // 3) // 4 * 4)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the workload is one GPU's share); "
+        print("bench.py: measures one GPU only (the workload is one GPU's share); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -55,7 +55,7 @@ typedef enum {
   HELM_ERR_NOT_CONVERGED = 4, /* U holds the last iterate, info is filled   */
   HELM_ERR_BREAKDOWN = 5,     /* rank-deficient block that could not be handled */
   HELM_ERR_NONFINITE = 6,     /* NaN/Inf in m, gamma or Q                    */
-  HELM_ERR_UNSUPPORTED = 7    /* valid request this build does not support  */
+  HELM_ERR_UNSUPPORTED = 7    /* valid request the library does not support */
 } helm_status;
 
 enum { HELM_FP64 = 0, HELM_MIXED = 1 };
