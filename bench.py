@@ -122,9 +122,12 @@ def train_in_child(args):
     return blob, info
 
 
-def fp64_compare(args, p, Q, pk, torch):
+def fp64_compare(args, p, Q, pk, torch, Um=None):
     """The plain FP64 GPU solver (GMRES(20) coarsest) on the same block: one
-    untimed warm-up solve, then one timed solve."""
+    untimed warm-up solve, then one timed solve. With Um (the mixed-precision
+    result), the FP64 solve is continued to a 1e-10 relative residual
+    (untimed, warm start) and the per-RHS relative error of Um and of the FP64
+    1e-6 result against that reference is reported."""
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
                        precision="fp64", coarse="gmres", coarse_iters=20)
     pk.helm_fine_tile(hd, p.nrhs)
@@ -139,8 +142,22 @@ def fp64_compare(args, p, Q, pk, torch):
     info = solve()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": round(p.nrhs / dt, 4) if info["converged_all"] else 0.0, "unit": "RHS/s",
-            "cycles": info["cycles"], "max_relres": float(info["relres"].max())}
+    out = {"value": round(p.nrhs / dt, 4) if info["converged_all"] else 0.0, "unit": "RHS/s",
+           "cycles": info["cycles"], "max_relres": float(info["relres"].max())}
+    if Um is not None:
+        Uref = U.clone()
+        ref = pk.helm_solve_block(hd, Q, Uref, tol=1e-10, restart=args.restart, max_cycles=4000,
+                                  block_size=args.block_size, reorth=args.reorth, warm_start=True)
+        nref = torch.linalg.norm(Uref, dim=1)
+        em = (torch.linalg.norm(Um - Uref, dim=1) / nref).cpu().numpy()
+        e64 = (torch.linalg.norm(U - Uref, dim=1) / nref).cpu().numpy()
+        out["reference"] = {"tol": 1e-10, "converged": bool(ref["converged_all"]), "extra_cycles": ref["cycles"],
+                            "max_relres": float(ref["relres"].max())}
+        out["rel_error_vs_reference"] = {
+            "mixed_learned": {"max": float(em.max()), "median": float(sorted(em)[len(em) // 2])},
+            "fp64_at_1e-6": {"max": float(e64.max()), "median": float(sorted(e64)[len(e64) // 2])}}
+        del Uref
+    return out
 
 
 def run_batch(args, pk, synth, np, torch):
@@ -359,7 +376,7 @@ def main():
         out["config"]["coarse_net"] = net_info
     if not args.no_fp64_compare and args.precision == "mixed":
         note(f"{value:.3f} RHS/s; FP64 comparison")
-        out["config"]["fp64_compare"] = fp64_compare(args, p, Q, pk, torch)
+        out["config"]["fp64_compare"] = fp64_compare(args, p, Q, pk, torch, U)
     if not args.no_cpu_baseline:
         note("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, cycles[0], args.cpu_iters)
