@@ -734,7 +734,7 @@ template <int K, class SO, class T> __device__ inline void st_own(SO* p, const c
 constexpr int RT = 8;           // coarse tile edge
 constexpr int RF = 2 * RT + 1;  // fine residual points per axis
 constexpr int RU = RF + 2;      // fine u points per axis (with the ring)
-constexpr int RZC = 8;          // coarse planes per z-chunk
+constexpr int RZC = 32;         // coarse planes per z-chunk
 
 template <class S, class SO, class T>
 __global__ __launch_bounds__(512) void k_resid_restrict(Geo gf, Geo gc, int ncg, int nxb, int nyb, int64_t ntiles,

@@ -290,3 +290,25 @@ def test_fine_tile_choices_are_bitwise_identical(precision, nrhs):
     hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
     ry, zc = pk.helm_fine_tile(hd, nrhs)
     assert ry in (1, 2, 4, 8, 16) and zc >= 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_residual_restriction_across_z_chunks(precision):
+    """The fused residual + restriction marches through chunks of coarse
+    planes; on 80^3 cells the coarse grid has 39 planes, more than one chunk
+    with a ragged last one. The fused tile (16 x 16) and a register-blocked
+    tile (residual, then restriction) must give a bitwise equal cycle."""
+    p = synth.layered_3d(n=80, nsrc=(3, 2), levels=3, seed=2)
+    X = dev(crand(16, p.N))
+    outs = []
+    for ry, zc in [(4, 16), (16, 16), (16, 64)]:
+        hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, coarse="lu")
+        assert pk.helm_level_dims(hd, 1)[2] == 39
+        pk.helm_set_fine_tile(hd, 16, ry, zc)
+        Z = torch.empty_like(X)
+        pk.helm_precond(hd, X, Z)
+        outs.append(host(Z))
+        del hd
+    assert np.isfinite(outs[0]).all()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
