@@ -213,7 +213,11 @@ helm_status helm_coarse_solve(helm_handle h, int32_t nrhs, const void* R, void* 
  * register-blocked kernel; ry = 16 or 8: the LDS-blocked kernel on 16 x 16 or
  * 16 x 8 tiles, used where the block width is a multiple of 128 B of
  * right-hand sides;
- * zc >= 1). Results are bitwise identical for every tile. */
+ * zc >= 1). Results are bitwise identical for every tile. With the
+ * LDS-blocked tiles the finest-level residual runs fused with the
+ * restriction, and the prolongation with the first post-smoothing sweep;
+ * the environment variable HELM_FUSE=0 (read once per process) runs them as
+ * separate kernels instead, again with bitwise identical results. */
 helm_status helm_fine_tile(helm_handle h, int32_t nrhs, int32_t tile[2]);
 helm_status helm_set_fine_tile(helm_handle h, int32_t nrhs, const int32_t tile[2]);
 
