@@ -74,20 +74,31 @@ def test_unet_param_count():
 
 
 def test_unet_gradient_central_differences():
+    """Directional derivatives against central differences. The loss of a
+    ReLU network is differentiable except on the kinks where a pre-activation
+    is zero; a difference quotient whose +-eps step crosses a kink is not the
+    derivative (at eps = 1e-6 that happens in most directions here). So each
+    direction takes the best of eps = 1e-7, 1e-8, 1e-9: a crossing disappears
+    once eps is below the kink's distance, while a wrong gradient (a missing
+    factor, a dropped mask) is off by O(1) at every eps. The gradient is of
+    order 1e3, so rounding stays near 1e-10 relative even at eps = 1e-9."""
+    R = np.random.default_rng(5)
     D, B = 8, 2
     n = oracle.unet_nparams()
-    p = 0.1 * rnd(n)
-    x = rnd(B, D, D, D, 4)
-    t = rnd(B, D, D, D, 2)
-    mask = (RNG.uniform(size=(D, D, D)) > 0.2).astype(float)
+    p = 0.1 * R.standard_normal(n)
+    x = R.standard_normal((B, D, D, D, 4))
+    t = R.standard_normal((B, D, D, D, 2))
+    mask = (R.uniform(size=(D, D, D)) > 0.2).astype(float)
     loss, g = oracle.unet_loss_grad(p, x, t, mask)
     for _ in range(4):
-        d = rnd(n)
-        eps = 1e-6
-        lp, _ = oracle.unet_loss_grad(p + eps * d, x, t, mask)
-        lm, _ = oracle.unet_loss_grad(p - eps * d, x, t, mask)
-        fd = (lp - lm) / (2 * eps)
-        assert abs(fd - g @ d) < 1e-5 * max(abs(fd), 1e-8), (fd, g @ d)
+        d = R.standard_normal(n)
+        errs = []
+        for eps in (1e-7, 1e-8, 1e-9):
+            lp, _ = oracle.unet_loss_grad(p + eps * d, x, t, mask)
+            lm, _ = oracle.unet_loss_grad(p - eps * d, x, t, mask)
+            fd = (lp - lm) / (2 * eps)
+            errs.append(abs(fd - g @ d) / max(abs(fd), 1e-8))
+        assert min(errs) < 1e-5, (errs, g @ d)
 
 
 def test_unet_forward_consistent_with_loss():
@@ -97,3 +108,57 @@ def test_unet_forward_consistent_with_loss():
     out = oracle.unet_forward(p, x)
     loss, _ = oracle.unet_loss_grad(p, x, out)  # target = output -> zero loss
     assert loss < 1e-28
+
+
+def np_conv3(x, W, b):
+    """3x3x3 'same' convolution by its definition, written as 27 shifted
+    slices of a zero-padded volume: out[v] = b + sum_t x[v + off(t)] W[t],
+    off(t) = (t % 3 - 1, t // 3 % 3 - 1, t // 9 - 1) along (x, y, z); arrays
+    are [B][z][y][x][C]. Followed by ReLU (every 3x3x3 layer has one)."""
+    D = x.shape[1]
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1), (0, 0)))
+    y = np.broadcast_to(b, x.shape[:4] + (W.shape[2],)).copy()
+    for t in range(27):
+        dx, dy, dz = t % 3 - 1, (t // 3) % 3 - 1, t // 9 - 1
+        y += xp[:, 1 + dz:1 + dz + D, 1 + dy:1 + dy + D, 1 + dx:1 + dx + D, :] @ W[t]
+    return np.maximum(y, 0.0)
+
+
+def test_unet_forward_equals_composition():
+    """The whole network against its composition from the pinned parts,
+    in numpy: encoder 16/16, pool, 32/32, pool, 64/64; decoder upsample,
+    concatenate [upsampled, skip] (skip in the trailing channels), 32/32,
+    upsample, concatenate, 16/16; linear 1x1x1 head to 2 channels.
+    Parameters unpacked in layer order, W[27][Cin][Cout] then b[Cout], the
+    head W[16][2] then b[2]. A skip in the wrong channels, a swapped layer or
+    a misread packing fails here; none of them would fail the gradient
+    check, which differentiates the oracle's own forward pass."""
+    D, B = 8, 2
+    n = oracle.unet_nparams()
+    p = 0.2 * rnd(n)
+    x = rnd(B, D, D, D, 4)
+    layers, off = [], 0
+    for ci, co in oracle.UNET_LAYERS:
+        W = p[off:off + 27 * ci * co].reshape(27, ci, co)
+        off += 27 * ci * co
+        layers.append((W, p[off:off + co]))
+        off += co
+    Wh, bh = p[off:off + 32].reshape(16, 2), p[off + 32:off + 34]
+    assert off + 34 == n
+
+    def pool(a):
+        b_, d, c = a.shape[0], a.shape[1] // 2, a.shape[4]
+        return a.reshape(b_, d, 2, d, 2, d, 2, c).mean(axis=(2, 4, 6))
+
+    def up(a):
+        return a.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+
+    L = [lambda a, k=k: np_conv3(a, *layers[k]) for k in range(10)]
+    s1 = L[1](L[0](x))
+    s2 = L[3](L[2](pool(s1)))
+    a5 = L[5](L[4](pool(s2)))
+    a7 = L[7](L[6](np.concatenate([up(a5), s2], axis=4)))
+    a9 = L[9](L[8](np.concatenate([up(a7), s1], axis=4)))
+    ref = a9 @ Wh + bh
+    out = oracle.unet_forward(p, x)
+    assert np.allclose(out, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())

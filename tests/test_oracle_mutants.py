@@ -1,0 +1,171 @@
+"""Planted mistakes in the CPU oracle: do the pins catch them?
+
+Each case copies the oracle's C sources to a temporary directory, plants one
+plausible slip in the copy (a sign, a weight, a dropped term or conjugate, a
+transposed operand, a mirrored tap), compiles it to a library of its own,
+points the oracle package at that library and runs the pins named beside the
+mistake: at least one of them must fail. The oracle's own sources and library
+are never changed, and the package is pointed back at them afterwards.
+
+Every planted slip keeps all memory accesses in bounds (offsets stay inside
+the same 3^d neighbourhood, loops keep their ranges), so a mutant can give
+wrong numbers but cannot fault.
+"""
+import contextlib
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_cnn as cnn
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__))
+
+
+def kron(dim, n, beta):
+    return lambda: pins.test_apply_fine_matches_kronecker_assembly(dim, n, beta)
+
+
+# (name, file, text in the oracle, replacement, which occurrence, pins)
+MUTANTS = [
+    # operator (eq:helm, eq:LinearSystem)
+    ("damping sign", "helm_oracle.c", "(1.0 - I * (gam + beta))", "(1.0 + I * (gam + beta))", 0,
+     [kron(3, 6, 0.2)]),
+    ("shift dropped", "helm_oracle.c", "(1.0 - I * (gam + beta))", "(1.0 - I * gam)", 0, [kron(2, 8, 0.2)]),
+    ("off-diagonal sign", "helm_oracle.c", "acc -= w * us[gidx(g, d[0], d[1], d[2])]",
+     "acc += w * us[gidx(g, d[0], d[1], d[2])]", 0, [kron(2, 8, 0.0)]),
+    ("one spacing for every axis", "helm_oracle.c", "lap += 2.0 / (g->h[a] * g->h[a]);",
+     "lap += 2.0 / (g->h[0] * g->h[0]);", 0, [kron(3, 6, 0.0)]),
+    # transfers
+    ("interpolation weight", "helm_oracle.c", "(dx ? 0.5 : 1.0)", "(dx ? 0.25 : 1.0)", 0,
+     [lambda: pins.test_prolong_restrict_match_kron(2, 8)]),
+    ("restriction scale", "helm_oracle.c", "1.0 / (double)(1 << g->dim)", "1.0 / (double)(1 << (g->dim - 1))", 0,
+     [lambda: pins.test_prolong_restrict_match_kron(3, 8)]),
+    ("restriction ignores the z offset", "helm_oracle.c", "int fz = g->dim == 3 ? 2 * Z + 1 + dz : 0;",
+     "int fz = g->dim == 3 ? 2 * Z + 1 : 0;", 1, [lambda: pins.test_prolong_restrict_match_kron(3, 8)]),
+    # Galerkin coarse operators
+    ("coarse stencil mirrored", "helm_oracle.c", "if (col) stc[cj * 27 + sidx(ox, oy, oz)] = y[cj];",
+     "if (col) stc[cj * 27 + sidx(-ox, -oy, -oz)] = y[cj];", 0,
+     [lambda: pins.test_galerkin_matches_triple_product(2, 16)]),
+    # smoothing
+    ("Jacobi without its damping weight", "helm_oracle.c", "u[j] += w * (f[j] - r[j]) / st[i * 27 + sidx(0, 0, 0)];",
+     "u[j] += (f[j] - r[j]) / st[i * 27 + sidx(0, 0, 0)];", 0, [pins.test_jacobi_sine_mode_amplification]),
+    ("cycle smoother residual sign", "helm_oracle.c", "u[j] += H->w[l] * (f[j] - r[j])", "u[j] += H->w[l] * (r[j] - f[j])",
+     0, [lambda: pins.test_vcycle_equals_dense_composition(2, 16, 3)]),
+    ("cycle smooths with the unshifted operator", "helm_oracle.c",
+     "orc_apply_fine(&H->g[0], H->m, H->gamma, H->omega, H->beta, nrhs, u, out);",
+     "orc_apply_fine(&H->g[0], H->m, H->gamma, H->omega, 0.0, nrhs, u, out);", 0,
+     [lambda: pins.test_vcycle_equals_dense_composition(3, 8, 2)]),
+    # the cycle
+    ("cycle residual sign", "helm_oracle.c", "for (int64_t j = 0; j < N * nrhs; ++j) r[j] = f[j] - r[j];",
+     "for (int64_t j = 0; j < N * nrhs; ++j) r[j] = r[j] - f[j];", 0,
+     [lambda: pins.test_vcycle_equals_dense_composition(2, 16, 3)]),
+    ("coarse correction subtracted", "helm_oracle.c", "for (int64_t j = 0; j < N * nrhs; ++j) u[j] += r[j];",
+     "for (int64_t j = 0; j < N * nrhs; ++j) u[j] -= r[j];", 0,
+     [lambda: pins.test_vcycle_equals_dense_composition(2, 16, 3)]),
+    # coarsest solves
+    ("LU back substitution sign", "helm_oracle.c", "for (int64_t j = k + 1; j <= cend; ++j) acc -= BAND(b, k, j) * v[j];",
+     "for (int64_t j = k + 1; j <= cend; ++j) acc += BAND(b, k, j) * v[j];", 0,
+     [lambda: pins.test_coarsest_band_lu_equals_dense_solve(2, 16, 2)]),
+    ("coarse GMRES without the conjugate", "helm_oracle.c", "for (int64_t t = 0; t < n; ++t) d += conj(vi[t]) * w[t];",
+     "for (int64_t t = 0; t < n; ++t) d += vi[t] * w[t];", 0,
+     [lambda: pins.test_vcycle_with_gmres_coarsest_equals_dense(3)]),
+    ("coarse GMRES restart replaces the iterate", "helm_oracle.c", "for (int64_t t = 0; t < n; ++t) us[t] += d[t];",
+     "for (int64_t t = 0; t < n; ++t) us[t] = d[t];", 0, [pins.test_coarse_gmres_restarts_equal_krylov_minimisers]),
+    # dense helpers
+    ("reflector without its factor 2", "helm_oracle.c", "y[i] -= 2.0 * v[i] * d;", "y[i] -= v[i] * d;", 0,
+     [pins.test_householder_qr]),
+    ("back substitution transposed", "helm_oracle.c", "acc -= a[(int64_t)j * mr + i] * Y[(int64_t)c * nc + j];",
+     "acc -= a[(int64_t)i * mr + j] * Y[(int64_t)c * nc + j];", 0, [pins.test_lstsq_matches_numpy]),
+    # block FGMRES
+    ("block Gram without the conjugate", "helm_oracle.c", "acc += conj(va[n]) * wb[n];", "acc += va[n] * wb[n];", 0,
+     [pins.test_fgmres_identity_prec_equals_scipy_gmres]),
+    ("solution updated from V, not Z (not flexible)", "helm_oracle.c", "acc += Z[(int64_t)jj * blk",
+     "acc += V[(int64_t)jj * blk", 0, [pins.test_residual_estimates_track_true_residual]),
+    ("block least-squares right-hand side transposed", "helm_oracle.c", "B[(int64_t)b * r + a] = S[b * p + a];",
+     "B[(int64_t)b * r + a] = S[a * p + b];", 0, [pins.test_block_fgmres_saturates_to_exact_in_one_cycle]),
+    ("restart residual of the shifted operator", "helm_oracle.c",
+     "orc_apply_fine(&Hh->g[0], Hh->m, Hh->gamma, Hh->omega, 0.0, p, X, V);",
+     "orc_apply_fine(&Hh->g[0], Hh->m, Hh->gamma, Hh->omega, Hh->beta, p, X, V);", 0,
+     [lambda: pins.test_fgmres_manufactured_solution(1)]),
+    # the network oracle
+    ("convolution taps mirrored", "conv_oracle.c",
+     "const int xx = X + t % 3 - 1, yy = Y + (t / 3) % 3 - 1, zz = Z + t / 9 - 1;",
+     "const int xx = X - (t % 3 - 1), yy = Y - ((t / 3) % 3 - 1), zz = Z - (t / 9 - 1);", 0,
+     [cnn.test_conv3d_forward_matches_scipy_correlate]),
+    ("backward data taps not mirrored", "conv_oracle.c",
+     "const int xx = X - (t % 3 - 1), yy = Y - ((t / 3) % 3 - 1), zz = Z - (t / 9 - 1);",
+     "const int xx = X + t % 3 - 1, yy = Y + (t / 3) % 3 - 1, zz = Z + t / 9 - 1;", 0,
+     [cnn.test_conv3d_backward_data_is_adjoint]),
+    ("backward weight taps mirrored", "conv_oracle.c",
+     "const int xx = X + t % 3 - 1, yy = Y + (t / 3) % 3 - 1, zz = Z + t / 9 - 1;",
+     "const int xx = X - (t % 3 - 1), yy = Y - ((t / 3) % 3 - 1), zz = Z - (t / 9 - 1);", 1,
+     [cnn.test_conv3d_backward_weight_is_adjoint]),
+    ("pooling weight 1/4 instead of 1/8", "conv_oracle.c", "0.125 * s", "0.25 * s", 0,
+     [cnn.test_pool_upsample_adjoint_pair]),
+    ("skip connection in the wrong channels", "conv_oracle.c", "put_slice(V, 16, s1, 48, 32, A->c1);",
+     "put_slice(V, 16, s1, 48, 16, A->c1);", 0, [cnn.test_unet_forward_equals_composition]),
+    ("ReLU mask of the last layer dropped in the gradient", "conv_oracle.c", "relu_mask(V * 16, A.a9, g9);", ";", 0,
+     [cnn.test_unet_gradient_central_differences]),
+    ("loss gradient without its factor 2", "conv_oracle.c", "g_out[i * 2 + c] = 2.0 * (A.out", "g_out[i * 2 + c] = (A.out",
+     0, [cnn.test_unet_gradient_central_differences]),
+]
+
+
+def plant(text, old, new, occ):
+    at = -1
+    for _ in range(occ + 1):
+        at = text.find(old, at + 1)
+        assert at >= 0, f"the oracle no longer contains {old!r} (occurrence {occ})"
+    return text[:at] + new + text[at + len(old):]
+
+
+@contextlib.contextmanager
+def oracle_library(path):
+    saved = (oracle._LIBPATH, oracle._lib)
+    oracle._LIBPATH, oracle._lib = path, None
+    try:
+        yield
+    finally:
+        oracle._LIBPATH, oracle._lib = saved
+
+
+@pytest.mark.parametrize("name,fname,old,new,occ,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, fname, old, new, occ, checks):
+    for f in ("helm_oracle.c", "helm_oracle.h", "conv_oracle.c"):
+        with open(os.path.join(SRC, f)) as fh:
+            text = fh.read()
+        if f == fname:
+            changed = plant(text, old, new, occ)
+            assert changed != text
+            text = changed
+        (tmp_path / f).write_text(text)
+    lib = str(tmp_path / "libmutant.so")
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-w",
+                           str(tmp_path / "helm_oracle.c"), str(tmp_path / "conv_oracle.c"), "-o", lib, "-lm"])
+    caught = []
+    with oracle_library(lib):
+        for check in checks:
+            try:
+                check()
+            except AssertionError as e:
+                caught.append(str(e)[:80])
+    assert caught, f"no pin caught the planted mistake: {name}"
+
+
+def test_unmutated_copy_passes_the_same_pins(tmp_path):
+    """The harness itself: the copied, recompiled oracle without a planted
+    mistake passes every pin used above (so a caught mutant is caught for
+    its mistake, not for the build)."""
+    for f in ("helm_oracle.c", "helm_oracle.h", "conv_oracle.c"):
+        with open(os.path.join(SRC, f)) as fh:
+            (tmp_path / f).write_text(fh.read())
+    lib = str(tmp_path / "libcopy.so")
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-w",
+                           str(tmp_path / "helm_oracle.c"), str(tmp_path / "conv_oracle.c"), "-o", lib, "-lm"])
+    with oracle_library(lib):
+        for m in MUTANTS:
+            for check in m[5]:
+                check()
