@@ -16,9 +16,9 @@ network on the GPU: exact (LU) coarsest solves of 32-source solves on four
 128^3-cell models of the same family with their own seeds (5000 + j, never
 the benchmark's model) give 8192 (residual, error) pairs, 3000 Adam steps
 fit the network; inside the cycle its correction starts restarted GMRES on
-the coarsest grid (two cycles of 8 steps). The plain FP64 solver (GMRES(20) coarsest) is timed in the
-same run for comparison. --coarse gmres selects GMRES(--coarse-iters) from
-zero instead of the network.
+the coarsest grid (two cycles of 8 steps). The plain FP64 solver (GMRES(20)
+coarsest) is timed in the same run for comparison. --coarse gmres selects
+GMRES(--coarse-iters) from zero instead of the network.
 
 Prints one JSON line.
 """
