@@ -137,7 +137,8 @@ typedef struct {
   int32_t restarts;
   int32_t converged_all;
   int32_t fallback_used;/* coarsest solves where the learned correction was not finite
-                           and coarse_iters GMRES steps replaced it */
+                           or beyond 1e4 in its normalised units, and max(coarse_iters,
+                           20) GMRES steps from zero replaced it */
   double t_solve_ms;    /* device time of the solve (hip events) */
   double* relres;       /* HOST [nrhs] or NULL: final FP64 ||q_s - H u_s|| / ||q_s|| */
   int32_t* converged;   /* HOST [nrhs] or NULL */
