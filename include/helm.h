@@ -305,7 +305,10 @@ int64_t helm_net_pairs(helm_net n);
  * (e / (H^2 rms(r)), 0 outside the grid). Synchronises `stream`. */
 helm_status helm_net_pool_read(helm_net n, int64_t i, float* x, float* target, void* stream);
 /* Adam (beta 0.9, 0.999, eps 1e-8) on minibatches of `batch` pool samples
- * drawn uniformly with `seed`; hist: HOST [steps] loss per step, or NULL. */
+ * drawn uniformly with `seed`; each sample's residual channels and target are
+ * multiplied by one random unit phase (the exact coarsest solve commutes with
+ * it, so the rotated pair is as valid as the stored one). hist: HOST [steps]
+ * loss per step, or NULL. */
 helm_status helm_net_train(helm_net n, int32_t steps, int32_t batch, double lr, uint64_t seed,
                            double* hist, void* stream);
 
