@@ -72,6 +72,7 @@ def lib():
         L.orc_vcycle.argtypes = [P, C.c_int, P, P]
         L.orc_coarse_solve.argtypes = [P, C.c_int, P, P]
         L.orc_set_coarse_restarts.argtypes = [P, C.c_int]
+        L.orc_set_cycle_w.argtypes = [P, C.c_int]
         L.orc_block_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_int), P, P]
         L.orc_householder_qr.argtypes = [C.c_int64, C.c_int, P, P]
@@ -186,7 +187,7 @@ class Hierarchy:
     COARSE = {"lu": 0, "gmres": 1, "none": 2}
 
     def __init__(self, g, m, gamma, omega, beta, levels, nu_pre=None, nu_post=None, wjac=None,
-                 coarse="lu", coarse_iters=20, coarse_restarts=1):
+                 coarse="lu", coarse_iters=20, coarse_restarts=1, cycle="V"):
         self.g = g
         self.levels = levels
         self._m, self._gamma = _d(m), _d(gamma)
@@ -207,6 +208,10 @@ class Hierarchy:
             raise RuntimeError("oracle setup failed")
         if coarse_restarts > 1:
             lib().orc_set_coarse_restarts(self.h, int(coarse_restarts))
+        if cycle not in ("V", "W"):
+            raise ValueError("cycle must be 'V' or 'W'")
+        if cycle == "W":
+            lib().orc_set_cycle_w(self.h, 1)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -345,7 +345,8 @@ void orc_band_free(orc_band* b) {
 }
 
 /* ---------------------------------------------------------------------------
- * Hierarchy and V-cycle (Algorithm "Two-grid cycle", applied recursively).
+ * Hierarchy and V-cycle (Algorithm "Two-grid cycle", applied recursively;
+ * the W-cycle applies it twice to each coarse problem but the coarsest).
  * Level 0 is the shifted fine operator, defined directly from (m, gamma);
  * levels >= 1 are Galerkin stencils; the last level is solved by LU.
  * ------------------------------------------------------------------------- */
@@ -353,6 +354,7 @@ struct orc_hier {
   int levels;
   int coarse_kind, coarse_iters;
   int coarse_restarts; /* GMRES cycles of coarse_iters steps (restarted GMRES); 0 or 1: one */
+  int cycle_w;         /* 1: W-cycle (two coarse cycles where the coarse level is not the coarsest) */
   og_grid g[8];
   ozc* st[8];   /* st[0] = shifted fine operator as a stencil */
   int nu_pre[8], nu_post[8];
@@ -470,6 +472,7 @@ static void coarse_gmres(const og_grid* g, const ozc* st, int k, const ozc* f, o
 }
 
 void orc_set_coarse_restarts(orc_hier* H, int restarts) { H->coarse_restarts = restarts; }
+void orc_set_cycle_w(orc_hier* H, int w) { H->cycle_w = w; }
 
 void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u) {
   const int l = H->levels - 1;
@@ -549,6 +552,20 @@ static void vcycle_rec(const orc_hier* H, int l, int nrhs, const ozc* f, ozc* u)
   ozc* ec = (ozc*)malloc(sizeof(ozc) * Nc * nrhs);
   orc_restrict(&H->g[l], nrhs, r, rc);                     /*    r_c = R r */
   vcycle_rec(H, l + 1, nrhs, rc, ec);                      /* 3. coarse problem */
+  if (H->cycle_w && l + 1 < H->levels - 1) {
+    /* W-cycle: the coarse problem gets a second cycle, on the residual the
+     * first one left: e_c += B_c (r_c - M_c e_c). The coarsest level is
+     * solved once. */
+    const int64_t n2 = Nc * nrhs;
+    ozc* r2 = (ozc*)malloc(sizeof(ozc) * n2);
+    ozc* d2 = (ozc*)malloc(sizeof(ozc) * n2);
+    level_apply(H, l + 1, nrhs, ec, r2);
+    for (int64_t j = 0; j < n2; ++j) r2[j] = rc[j] - r2[j];
+    vcycle_rec(H, l + 1, nrhs, r2, d2);
+    for (int64_t j = 0; j < n2; ++j) ec[j] += d2[j];
+    free(r2);
+    free(d2);
+  }
   orc_prolong(&H->g[l], nrhs, ec, r);                      /* 4. u += P e_c */
   for (int64_t j = 0; j < N * nrhs; ++j) u[j] += r[j];
   level_jacobi(H, l, H->nu_post[l], nrhs, f, u);          /* 5. post-relax */

@@ -103,6 +103,10 @@ void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u);
 /* GMRES coarsest solve as `restarts` cycles of coarse_iters steps (restarted
  * GMRES; the default is one cycle). */
 void orc_set_coarse_restarts(orc_hier* H, int restarts);
+/* 1: W-cycle. The coarse problem of every level whose coarse level is not
+ * the coarsest gets two cycles, the second on the residual of the first
+ * (e_c += B_c(r_c - M_c e_c)); the coarsest level is solved once. 0: V. */
+void orc_set_cycle_w(orc_hier* H, int w);
 
 /* Block FGMRES(restart) for H X = Q with X0 = 0 (or X on entry if warm).
  * Right preconditioning by the V-cycle (or identity if H == NULL-prec flag).

@@ -65,6 +65,9 @@ MUTANTS = [
     ("coarse correction subtracted", "helm_oracle.c", "for (int64_t j = 0; j < N * nrhs; ++j) u[j] += r[j];",
      "for (int64_t j = 0; j < N * nrhs; ++j) u[j] -= r[j];", 0,
      [lambda: pins.test_vcycle_equals_dense_composition(2, 16, 3)]),
+    ("W-cycle second correction subtracted", "helm_oracle.c", "for (int64_t j = 0; j < n2; ++j) ec[j] += d2[j];",
+     "for (int64_t j = 0; j < n2; ++j) ec[j] -= d2[j];", 0,
+     [lambda: pins.test_wcycle_equals_dense_composition(2, 32, 4)]),
     # coarsest solves
     ("LU back substitution sign", "helm_oracle.c", "for (int64_t j = k + 1; j <= cend; ++j) acc -= BAND(b, k, j) * v[j];",
      "for (int64_t j = k + 1; j <= cend; ++j) acc += BAND(b, k, j) * v[j];", 0,

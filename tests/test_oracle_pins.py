@@ -303,7 +303,10 @@ def test_coarsest_band_lu_equals_dense_solve(dim, n, levels):
 # ---------------------------------------------------------------------------
 # V-cycle: the two-grid cycle applied recursively, as a fixed linear map
 # ---------------------------------------------------------------------------
-def dense_vcycle(Ms, Ps, f, l, w, nu, coarse, dim):
+def dense_vcycle(Ms, Ps, f, l, w, nu, coarse, dim, wcycle=False):
+    """The two-grid cycle with dense matrices, recursively. W-cycle: a coarse
+    problem other than the coarsest gets a second cycle on the residual of
+    the first, e += B(r_c - M_c e)."""
     if l == len(Ms) - 1:
         return coarse(Ms[l], f)
     M = Ms[l]
@@ -311,7 +314,10 @@ def dense_vcycle(Ms, Ps, f, l, w, nu, coarse, dim):
     u = np.zeros_like(f)
     for _ in range(nu):
         u = u + w * Dinv * (f - M @ u)
-    e = dense_vcycle(Ms, Ps, Ps[l].T @ (f - M @ u) / 2 ** dim, l + 1, w, nu, coarse, dim)
+    rc = Ps[l].T @ (f - M @ u) / 2 ** dim
+    e = dense_vcycle(Ms, Ps, rc, l + 1, w, nu, coarse, dim, wcycle)
+    if wcycle and l + 1 < len(Ms) - 1:
+        e = e + dense_vcycle(Ms, Ps, rc - Ms[l + 1] @ e, l + 1, w, nu, coarse, dim, wcycle)
     u = u + Ps[l] @ e
     for _ in range(nu):
         u = u + w * Dinv * (f - M @ u)
@@ -362,6 +368,23 @@ def test_vcycle_equals_dense_composition(dim, n, levels):
     for s in range(2):
         ref = dense_vcycle(Ms, Ps, F[s], 0, 0.8, 2, lambda A, b: np.linalg.solve(A, b), dim)
         assert np.allclose(out[s], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 32, 4), (3, 16, 3)])
+def test_wcycle_equals_dense_composition(dim, n, levels):
+    m, gamma = rand_model(dim, n)
+    omega, beta = 10.0, 0.2
+    Ms, Ps = dense_hierarchy(dim, n, m, gamma, omega, beta, levels)
+    g = oracle.grid(dim, (n,) * dim, (1 / n,) * dim)
+    H = oracle.Hierarchy(g, m, gamma, omega, beta, levels, cycle="W")
+    F = crand(2, Ms[0].shape[0])
+    out = H.vcycle(F)
+    solve = lambda A, b: np.linalg.solve(A, b)
+    for s in range(2):
+        ref = dense_vcycle(Ms, Ps, F[s], 0, 0.8, 2, solve, dim, wcycle=True)
+        assert np.allclose(out[s], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+        v = dense_vcycle(Ms, Ps, F[s], 0, 0.8, 2, solve, dim)
+        assert np.linalg.norm(ref - v) > 1e-3 * np.linalg.norm(v)  # the W-cycle is another map
 
 
 @pytest.mark.parametrize("k", [3, 8])
