@@ -135,7 +135,6 @@ void launch_gram(Prec p, int64_t N, int ld, int P, int pb, int k, const PtrList&
   for (int i0 = 0; i0 < k; i0 += kk) {
     const int kc = (k - i0) < kk ? (k - i0) : kk;
     for (int a0 = 0; a0 < pb; a0 += na) {
-      const size_t shm = sizeof(cx<double>) * 256 * kc * na;
       PtrList sub{};
       for (int i = 0; i < kc; ++i) sub.p[i] = X.p[i0 + i];
       if (p == P64)
