@@ -79,7 +79,7 @@ typedef struct {
   const double* gamma;         /* HOST [N] dimensionless attenuation (>= 0) */
   double omega;                /* angular frequency (> 0) */
   double shift;                /* beta >= 0 added to gamma in the preconditioner */
-  int32_t levels;              /* 1..HELM_MAX_LEVELS; coarsest must have >= 1 unknown/axis */
+  int32_t levels;              /* 2..HELM_MAX_LEVELS; coarsest must have >= 1 unknown/axis */
   int32_t nu_pre[HELM_MAX_LEVELS];      /* Jacobi sweeps before the coarse correction */
   int32_t nu_post[HELM_MAX_LEVELS];     /* and after it */
   double jacobi_weight[HELM_MAX_LEVELS];/* damping per level (paper: 0.8) */
