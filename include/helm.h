@@ -104,7 +104,7 @@ typedef struct {
 void helm_setup_desc_default(helm_setup_desc* d);
 
 typedef struct {
-  int32_t restart;     /* m of FGMRES(m) (paper: 5) */
+  int32_t restart;     /* m of FGMRES(m), 1..31 (paper: 5) */
   int32_t max_cycles;  /* cap on preconditioner applications (Arnoldi steps) */
   int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs) */
   int32_t warm_start;  /* 1: U holds an initial guess */

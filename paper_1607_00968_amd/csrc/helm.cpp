@@ -1238,6 +1238,8 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   const int pb = o.block_size <= 0 ? nrhs : o.block_size;
   if (pb < 1 || nrhs % pb != 0 || pb > 32) return fail(HELM_ERR_INVALID_ARG, "block_size must divide nrhs and be <= 32");
   if (o.max_cycles < 1) return fail(HELM_ERR_INVALID_ARG, "max_cycles must be >= 1");
+  if (o.reorth < 0 || o.reorth > 2) return fail(HELM_ERR_INVALID_ARG, "reorth must be 0, 1 or 2");
+  if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");
   hipStream_t s = static_cast<hipStream_t>(stream);
   helm_ctx* c = h;
   const int P = padP(nrhs);
@@ -1250,7 +1252,6 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
   set_fine_tile(c->tile);
   const int64_t fallbacks0 = c->fallbacks;
-  if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");
   // graphs and the persistent kernel need a cycle without host work: no
   // per-kernel timing, no pair capture
   int graph = (c->prof || c->cap) ? 0 : o.graph;
