@@ -1,6 +1,6 @@
 """Host-side checks that need no GPU: the ctypes mirrors of the ABI structs
-follow include/helm.h field by field, new options are validated before any
-device call, the network's training models are not the benchmark's model,
+follow include/helm.h field by field, every documented precondition of
+helm_setup is validated before any device call, the network's training models are not the benchmark's model,
 and the bench finds the committed traffic figure of the tile it ran with."""
 import os
 import re
@@ -72,3 +72,56 @@ def test_bench_reads_the_traffic_of_each_committed_tile():
         assert v is not None and 10_814_135_792 < v < 2 * 10_814_135_792
     assert bench.committed_traffic("mixed", 192, 64, (4, 7)) is None
     assert bench.committed_traffic("fp64", 192, 64, (int(tiles[0][0]), int(tiles[0][1]))) is None
+
+
+def _setup_case(**over):
+    """A valid small 2D set-up (8^2 cells, 2 levels) with `over` applied;
+    m and gamma follow the grid unless given."""
+    kw = dict(dim=2, n=(8, 8), h=(1 / 8, 1 / 8), omega=1.0, levels=2, coarse="lu")
+    kw.update(over)
+    N = int(np.prod([c - 1 for c in kw["n"]]))
+    m = kw.pop("m", np.ones(N))
+    g = kw.pop("gamma", np.zeros(N))
+    dim, n, h, omega = kw.pop("dim"), kw.pop("n"), kw.pop("h"), kw.pop("omega")
+    return dim, n, h, m, g, omega, kw
+
+
+def _bad(x, i, v):
+    x = np.array(x, dtype=float)
+    x[i] = v
+    return x
+
+
+BAD_SETUPS = [
+    ("one level", dict(levels=1), "INVALID_ARG"),
+    ("more levels than the maximum", dict(levels=9, n=(512, 512)), "INVALID_ARG"),
+    ("n not a multiple of 2^(levels-1)", dict(levels=3, n=(10, 8)), "INVALID_ARG"),
+    ("no coarsest unknown", dict(levels=3, n=(4, 4)), "INVALID_ARG"),
+    ("zero spacing", dict(h=(0.0, 1 / 8)), "INVALID_ARG"),
+    ("omega zero", dict(omega=0.0), "INVALID_ARG"),
+    ("omega NaN", dict(omega=float("nan")), "INVALID_ARG"),
+    ("negative shift", dict(shift=-0.1), "INVALID_ARG"),
+    ("m zero", dict(m=_bad(np.ones(49), 5, 0.0)), "INVALID_ARG"),
+    ("m NaN", dict(m=_bad(np.ones(49), 5, np.nan)), "NONFINITE"),
+    ("gamma negative", dict(gamma=_bad(np.zeros(49), 3, -1e-3)), "INVALID_ARG"),
+    ("gamma infinite", dict(gamma=_bad(np.zeros(49), 3, np.inf)), "NONFINITE"),
+    ("negative sweep count", dict(nu_pre=-1), "INVALID_ARG"),
+    ("NaN Jacobi weight", dict(jacobi_weight=float("nan")), "INVALID_ARG"),
+    ("GMRES coarsest with 0 steps", dict(coarse="gmres", coarse_iters=0), "INVALID_ARG"),
+    ("GMRES coarsest with 49 steps", dict(coarse="gmres", coarse_iters=49), "INVALID_ARG"),
+    ("learned coarsest with 49 steps", dict(coarse="learned", coarse_iters=49), "INVALID_ARG"),
+    ("K-cycle", dict(cycle="K"), "UNSUPPORTED"),
+]
+
+
+@pytest.mark.parametrize("name,over,status", BAD_SETUPS, ids=[b[0] for b in BAD_SETUPS])
+def test_setup_rejects_bad_input_before_any_device_call(name, over, status):
+    """Every documented precondition of helm_setup is checked on the host
+    before the first HIP call: here, without a GPU, each bad descriptor gets
+    its own status (a check that came after a device call would report a
+    device error instead)."""
+    import paper_1607_00968_amd as pk
+    dim, n, h, m, g, omega, kw = _setup_case(**over)
+    with pytest.raises(pk.HelmError) as e:
+        pk.helm_setup(dim, n, h, m, g, omega, stream=0, **kw)
+    assert e.value.status == getattr(pk, "HELM_ERR_" + status), str(e.value)
