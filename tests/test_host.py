@@ -125,3 +125,13 @@ def test_setup_rejects_bad_input_before_any_device_call(name, over, status):
     with pytest.raises(pk.HelmError) as e:
         pk.helm_setup(dim, n, h, m, g, omega, stream=0, **kw)
     assert e.value.status == getattr(pk, "HELM_ERR_" + status), str(e.value)
+
+
+@pytest.mark.parametrize("D,max_batch", [(6, 4), (0, 4), (260, 4), (8, 0), (8, 1025)])
+def test_net_create_rejects_bad_shape_before_any_device_call(D, max_batch):
+    """The network's edge must be a multiple of 4 in 4..256 and the batch
+    1..1024; both are checked before the first device allocation."""
+    import paper_1607_00968_amd as pk
+    with pytest.raises(pk.HelmError) as e:
+        pk.helm_net_create(D, max_batch, seed=0, stream=0)
+    assert e.value.status == pk.HELM_ERR_INVALID_ARG, str(e.value)
