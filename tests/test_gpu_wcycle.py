@@ -1,6 +1,8 @@
-"""GPU parity of the W-cycle (the two-grid cycle applied twice to every
-coarse problem but the coarsest) against the oracle's W-cycle, which is
-pinned to a dense-matrix composition on the CPU.
+"""GPU parity of the cycle variants beside the V-cycle with an exact or
+GMRES coarsest solve: the W-cycle (the two-grid cycle applied twice to
+every coarse problem but the coarsest) and the relaxation-only coarsest
+level, each against the oracle's, which is pinned to a dense-matrix
+composition on the CPU.
 
 FP64, with the same 1e-9 bound as the V-cycle parity.
 """
@@ -57,3 +59,15 @@ def test_wcycle_fp64_matches_oracle(dim, n, levels):
     hv = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels)
     assert rel(hv.vcycle(F), ref) > 1e-4
 
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 32, 3), (3, 32, 3)])
+def test_relaxed_coarsest_fp64_matches_oracle(dim, n, levels):
+    """coarse = none: the coarsest level gets nu_pre + nu_post damped Jacobi
+    sweeps from zero instead of a solve."""
+    p = problem(dim, n, levels)
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=levels,
+                       precision="fp64", coarse="none")
+    ho = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels, coarse="none")
+    F = crand(3, p.N)
+    assert rel(precond(hd, F), ho.vcycle(F)) <= 1e-9

@@ -77,6 +77,8 @@ MUTANTS = [
      [lambda: pins.test_vcycle_with_gmres_coarsest_equals_dense(3)]),
     ("coarse GMRES restart replaces the iterate", "helm_oracle.c", "for (int64_t t = 0; t < n; ++t) us[t] += d[t];",
      "for (int64_t t = 0; t < n; ++t) us[t] = d[t];", 0, [pins.test_coarse_gmres_restarts_equal_krylov_minimisers]),
+    ("relaxation-only coarsest with half the sweeps", "helm_oracle.c", "int sweeps = H->nu_pre[l] + H->nu_post[l];",
+     "int sweeps = H->nu_pre[l];", 0, [lambda: pins.test_vcycle_with_relaxed_coarsest_equals_dense(2, 16, 3)]),
     # dense helpers
     ("reflector without its factor 2", "helm_oracle.c", "y[i] -= 2.0 * v[i] * d;", "y[i] -= v[i] * d;", 0,
      [pins.test_householder_qr]),

@@ -387,6 +387,34 @@ def test_wcycle_equals_dense_composition(dim, n, levels):
         assert np.linalg.norm(ref - v) > 1e-3 * np.linalg.norm(v)  # the W-cycle is another map
 
 
+def jacobi_from_zero(A, b, w, sweeps):
+    u = np.zeros_like(b)
+    Dinv = 1.0 / np.diag(A)
+    for _ in range(sweeps):
+        u = u + w * Dinv * (b - A @ u)
+    return u
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 16, 3), (3, 16, 3)])
+def test_vcycle_with_relaxed_coarsest_equals_dense(dim, n, levels):
+    """Relaxation-only coarsest level: nu_pre + nu_post damped Jacobi sweeps
+    from zero with that level's weight (here 2 + 2 at 0.8)."""
+    m, gamma = rand_model(dim, n)
+    omega, beta = 10.0, 0.2
+    Ms, Ps = dense_hierarchy(dim, n, m, gamma, omega, beta, levels)
+    g = oracle.grid(dim, (n,) * dim, (1 / n,) * dim)
+    H = oracle.Hierarchy(g, m, gamma, omega, beta, levels, coarse="none")
+    F = crand(2, Ms[0].shape[0])
+    out = H.vcycle(F)
+    for s in range(2):
+        ref = dense_vcycle(Ms, Ps, F[s], 0, 0.8, 2, lambda A, b: jacobi_from_zero(A, b, 0.8, 4), dim)
+        assert np.allclose(out[s], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    C = Ms[-1]
+    Fc = crand(3, C.shape[0])
+    assert np.allclose(H.coarse_solve(Fc), np.array([jacobi_from_zero(C, f, 0.8, 4) for f in Fc]),
+                       atol=1e-12 * np.abs(Fc).max())
+
+
 @pytest.mark.parametrize("k", [3, 8])
 def test_vcycle_with_gmres_coarsest_equals_dense(k):
     dim, n, levels = 2, 32, 3
