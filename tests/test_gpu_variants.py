@@ -1,10 +1,8 @@
-"""GPU parity of the cycle variants beside the V-cycle with an exact or
-GMRES coarsest solve: the W-cycle (the two-grid cycle applied twice to
-every coarse problem but the coarsest) and the relaxation-only coarsest
-level, each against the oracle's, which is pinned to a dense-matrix
-composition on the CPU.
-
-FP64, with the same 1e-9 bound as the V-cycle parity.
+"""GPU parity of the variants beside the default solve: the W-cycle (the
+two-grid cycle applied twice to every coarse problem but the coarsest) and
+the relaxation-only coarsest level, each against the oracle's, which is
+pinned to a dense-matrix composition on the CPU (FP64, the same 1e-9 bound
+as the V-cycle parity); and a solve warm-started from an initial guess.
 """
 import numpy as np
 import pytest
@@ -71,3 +69,32 @@ def test_relaxed_coarsest_fp64_matches_oracle(dim, n, levels):
     ho = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels, coarse="none")
     F = crand(3, p.N)
     assert rel(precond(hd, F), ho.vcycle(F)) <= 1e-9
+
+
+def test_warm_start_fp64():
+    """A solve started from a partly converged guess (the oracle's solution
+    at 1e-3) reaches the same solution as the oracle's 1e-10 solve within
+    the error bound checked for cold solves (1e-5 at a 1e-8 tolerance), in
+    fewer cycles than from zero; started from a solution that already meets
+    the tolerance it takes no cycle and returns the guess unchanged."""
+    p = synth.gradient_2d()  # 2D 128^2, 4 sources, 3 levels
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision="fp64")
+    ho = oracle.setup_problem(p, levels=3)
+    Xref, _, _, conv = ho.fgmres(p.Q, tol=1e-10, restart=10, maxit=3000)
+    assert conv
+    X0, _, _, _ = ho.fgmres(p.Q, tol=1e-3, restart=10, maxit=3000)
+    Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
+    cold = pk.helm_solve_block(hd, Q, torch.zeros_like(Q), tol=1e-8, restart=10, max_cycles=2000, block_size=1)
+    U = torch.from_numpy(np.ascontiguousarray(X0)).cuda()
+    warm = pk.helm_solve_block(hd, Q, U, tol=1e-8, restart=10, max_cycles=2000, block_size=1, warm_start=True)
+    assert cold["converged_all"] and warm["converged_all"]
+    assert 0 < warm["cycles"] < cold["cycles"]
+    torch.cuda.synchronize()
+    Uh = U.cpu().numpy()
+    err = np.linalg.norm(Uh - Xref, axis=1) / np.linalg.norm(Xref, axis=1)
+    assert err.max() <= 1e-5, err
+    U2 = torch.from_numpy(np.ascontiguousarray(Xref)).cuda()
+    done = pk.helm_solve_block(hd, Q, U2, tol=1e-8, restart=10, block_size=1, warm_start=True)
+    assert done["converged_all"] and done["cycles"] == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(U2.cpu().numpy(), Xref)

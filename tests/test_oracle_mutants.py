@@ -85,6 +85,8 @@ MUTANTS = [
     ("back substitution transposed", "helm_oracle.c", "acc -= a[(int64_t)j * mr + i] * Y[(int64_t)c * nc + j];",
      "acc -= a[(int64_t)i * mr + j] * Y[(int64_t)c * nc + j];", 0, [pins.test_lstsq_matches_numpy]),
     # block FGMRES
+    ("warm start ignored", "helm_oracle.c", "if (!warm) memset(X, 0, sizeof(ozc) * blk);",
+     "memset(X, 0, sizeof(ozc) * blk);", 0, [pins.test_fgmres_warm_start_is_a_shifted_cold_solve]),
     ("block Gram without the conjugate", "helm_oracle.c", "acc += conj(va[n]) * wb[n];", "acc += va[n] * wb[n];", 0,
      [pins.test_fgmres_identity_prec_equals_scipy_gmres]),
     ("solution updated from V, not Z (not flexible)", "helm_oracle.c", "acc += Z[(int64_t)jj * blk",

@@ -541,6 +541,25 @@ def test_fgmres_converged_columns_meet_tolerance_and_dense_solution():
     assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 1e-6
 
 
+def test_fgmres_warm_start_is_a_shifted_cold_solve():
+    """FGMRES sees the initial guess only through its residual: a warm start
+    at X0 gives X0 + (the cold solve of H D = Q - H X0), iterate for
+    iterate; and a warm start at the exact solution takes no cycle."""
+    p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
+    H = oracle.setup_problem(p)
+    g = oracle.grid(p.dim, p.n, p.h)
+    X0 = crand(2, p.N) * 1e-4
+    R0 = p.Q - oracle.apply_fine(g, p.m, p.gamma, p.omega, 0.0, X0)
+    Xw, itw, _, _ = H.fgmres(p.Q, tol=1e-30, restart=5, maxit=12, X0=X0)
+    D, itc, _, _ = H.fgmres(R0, tol=1e-30, restart=5, maxit=12)
+    assert itw == itc == 12
+    assert np.allclose(Xw, X0 + D, rtol=1e-10, atol=1e-10 * np.abs(Xw).max())
+    A = sparse_H(2, p.n, p.h, p.m, p.gamma, p.omega, 0.0)
+    Xs = spl.splu(A.tocsc()).solve(p.Q.T).T
+    X, it, rr, conv = H.fgmres(p.Q, tol=1e-8, restart=5, maxit=50, X0=Xs)
+    assert conv and it == 0 and np.array_equal(X, Xs)
+
+
 def test_residual_estimates_track_true_residual():
     """Flexible Arnoldi identity: the LS residual is the true residual."""
     p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
