@@ -228,19 +228,19 @@ def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:
 def _form(graph) -> int:
     """Execution form of the cycle: False/0 eager, True/1 HIP graph,
     "persistent"/2 the cooperative persistent kernel."""
-    if graph == "persistent":
-        return 2
-    if isinstance(graph, bool):
-        return int(graph)
-    return int(graph)
+    return 2 if graph == "persistent" else int(graph)
 
 
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
                      warm_start=False, reorth=True, workspace=None, stream=None, graph=False,
                      learned_rate=0.0) -> dict:
     """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ...
-    learned_rate: the plain cycle's calibrated per-cycle reduction factor for
-    the learned coarsest correction's rate check (0 = off)."""
+    reorth: 0 one Gram-Schmidt pass, 1 (True, the default here) always two,
+    2 a second pass only where the norm fell below half (the C default when
+    no options are passed). graph: False/0 eager, True/1 HIP graphs,
+    "persistent"/2 the persistent cycle kernel. learned_rate: the plain
+    cycle's calibrated per-cycle reduction factor for the learned coarsest
+    correction's rate check (0 = off)."""
     nrhs = Q.shape[0]
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
