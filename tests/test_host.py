@@ -135,3 +135,27 @@ def test_net_create_rejects_bad_shape_before_any_device_call(D, max_batch):
     with pytest.raises(pk.HelmError) as e:
         pk.helm_net_create(D, max_batch, seed=0, stream=0)
     assert e.value.status == pk.HELM_ERR_INVALID_ARG, str(e.value)
+
+
+def test_bench_algorithmic_bytes_of_the_fine_sweep():
+    """The roofline's numerator: a damped-Jacobi sweep from a nonzero guess
+    reads u and f and writes u (3 x 8 B per point and RHS in mixed, 3 x 16 B
+    in FP64) and reads two coefficients per point (8 B each in mixed, 16 B
+    in FP64): 10.81 GB per launch at 191^3 unknowns x 64 RHS in mixed."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    N = 191 ** 3
+    assert bench.fine_sweep_bytes("mixed", N, 64) == N * (3 * 8 * 64 + 2 * 8) == 10814135792
+    assert bench.fine_sweep_bytes("fp64", N, 64) == N * (3 * 16 * 64 + 2 * 16)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; --gpus N > 1 exits with a message before
+    any device is touched."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
