@@ -87,9 +87,10 @@ typedef struct {
                                   levels >= 2, FP64 outer Krylov) */
   int32_t coarse;              /* HELM_COARSE_* */
   int32_t cycle;               /* HELM_CYCLE_* */
-  int32_t coarse_iters;        /* HELM_COARSE_GMRES: GMRES steps from zero (1..48);
+  int32_t coarse_iters;        /* HELM_COARSE_GMRES: GMRES steps from zero (1..32);
                                   HELM_COARSE_LEARNED: GMRES steps started from the
-                                  network's correction (0..48, 0 = network alone) */
+                                  network's correction (0..32, 0 = network alone);
+                                  larger values return HELM_ERR_INVALID_ARG */
   const void* net;             /* HOST weights blob for HELM_COARSE_LEARNED (or NULL) */
   size_t net_bytes;
   int32_t coarse_restarts;     /* GMRES and learned coarsest solves: restarted GMRES,

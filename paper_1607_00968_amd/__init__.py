@@ -162,11 +162,13 @@ class Handle:
         self.levels = levels
         self.precision = precision
         self.N = int(np.prod([c - 1 for c in self.n]))
+        self.capture_net = None  # the Net whose pool this handle feeds (kept alive while attached)
 
     def close(self):
         if self.ptr:
             lib().helm_destroy(self.ptr)
             self.ptr = None
+        self.capture_net = None
 
     def __del__(self):
         try:
@@ -462,5 +464,11 @@ def helm_net_create(D: int, max_batch: int, seed: int = 0, stream=None) -> Net:
 
 def helm_net_capture(hd: Handle, net: Net, max_pairs: int):
     """Store (input, exact target) pairs of hd's coarsest solves in net's pool
-    (max_pairs == 0 detaches)."""
+    (max_pairs == 0 detaches). While attached, the handle holds a reference
+    to the network, so the pool outlives every solve that writes to it."""
     _check(lib().helm_net_capture(hd.ptr, net.ptr, int(max_pairs)))
+    if int(max_pairs) == 0:
+        if hd.capture_net is net:
+            hd.capture_net = None
+    else:
+        hd.capture_net = net

@@ -82,6 +82,8 @@ struct Level {
 
 using namespace helm;
 
+struct helm_net_s;
+
 struct helm_ctx {
   int dim = 3;
   int L = 0;
@@ -103,6 +105,7 @@ struct helm_ctx {
   learned::Net* net = nullptr;
   int64_t fallbacks = 0;            // learned coarsest solves replaced by GMRES
   learned::Net* cap = nullptr;      // pool receiving coarsest (f, e) pairs
+  helm_net_s* capw = nullptr;       // the network object that owns `cap`
   // cycles captured as HIP graphs, keyed by block width and buffers
   struct CycleGraph {
     int P;
@@ -796,9 +799,12 @@ const char* helm_status_string(helm_status s) {
 
 const char* helm_last_error(void) { return g_err.c_str(); }
 
+static void cap_detach(helm_ctx* h);
+
 static void free_ctx(helm_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  cap_detach(c);
   clear_graphs(c);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->bstream) (void)hipStreamDestroy(c->bstream);
@@ -834,10 +840,11 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     return fail(HELM_ERR_INVALID_ARG, "omega must be > 0 and shift >= 0");
   if (d->precision != HELM_FP64 && d->precision != HELM_MIXED) return fail(HELM_ERR_INVALID_ARG, "bad precision");
   if (d->coarse < HELM_COARSE_LU || d->coarse > HELM_COARSE_GMRES) return fail(HELM_ERR_INVALID_ARG, "bad coarse kind");
-  if (d->coarse == HELM_COARSE_GMRES && (d->coarse_iters < 1 || d->coarse_iters > 48))
-    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 1..48");
-  if (d->coarse == HELM_COARSE_LEARNED && (d->coarse_iters < 0 || d->coarse_iters > 48))
-    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 0..48 with the learned coarsest correction");
+  // the coarsest GMRES keeps its basis vectors in one PtrList (MAXPTR slots)
+  if (d->coarse == HELM_COARSE_GMRES && (d->coarse_iters < 1 || d->coarse_iters > MAXPTR))
+    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 1..%d", MAXPTR);
+  if (d->coarse == HELM_COARSE_LEARNED && (d->coarse_iters < 0 || d->coarse_iters > MAXPTR))
+    return fail(HELM_ERR_INVALID_ARG, "coarse_iters must be 0..%d with the learned coarsest correction", MAXPTR);
   if (d->coarse_restarts < 0 || d->coarse_restarts > 16)
     return fail(HELM_ERR_INVALID_ARG, "coarse_restarts must be 0..16 (0 and 1: one GMRES cycle)");
   if (d->cycle < HELM_CYCLE_V || d->cycle > HELM_CYCLE_K) return fail(HELM_ERR_INVALID_ARG, "bad cycle kind");
@@ -1574,7 +1581,27 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
 struct helm_net_s {
   learned::Net* n = nullptr;
   hipStream_t s = nullptr;
+  // handles whose coarsest solves feed this network's pool: detached when
+  // either side is destroyed, so no handle keeps a pointer to a freed pool
+  std::vector<helm_ctx*> attached;
 };
+
+static void cap_detach(helm_ctx* h) {
+  if (!h || !h->capw) return;
+  auto& a = h->capw->attached;
+  a.erase(std::remove(a.begin(), a.end(), h), a.end());
+  h->cap = nullptr;
+  h->capw = nullptr;
+}
+
+static void cap_attach(helm_ctx* h, helm_net_s* n) {
+  if (h->capw != n) {
+    cap_detach(h);
+    n->attached.push_back(h);
+  }
+  h->cap = n->n;
+  h->capw = n;
+}
 
 int64_t helm_net_nparams(void) { return learned::nparams(); }
 
@@ -1594,6 +1621,7 @@ helm_status helm_net_create(int32_t D, int32_t max_batch, uint64_t seed, void* s
 
 void helm_net_destroy(helm_net n) {
   if (!n) return;
+  while (!n->attached.empty()) cap_detach(n->attached.back());
   learned::destroy(n->n);
   delete n;
 }
@@ -1633,7 +1661,7 @@ helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const floa
 helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs) {
   if (!h || !n) return fail(HELM_ERR_INVALID_ARG, "null argument");
   if (max_pairs == 0) {
-    if (h->cap == n->n) h->cap = nullptr;
+    if (h->capw == n) cap_detach(h);
     return HELM_OK;
   }
   if (h->dim != 3) return fail(HELM_ERR_UNSUPPORTED, "pairs are captured from 3D problems only");
@@ -1643,13 +1671,13 @@ helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs) {
     // keep the pool: pairs of several problems with equal coarsest grids
     helm_status st = learned::capture_continue(n->n, coarse_view(h), n->s);
     if (st != HELM_OK) return st;
-    h->cap = n->n;
+    cap_attach(h, n);
     return HELM_OK;
   }
   helm_status st = learned::bind(n->n, coarse_view(h), n->s);
   if (st != HELM_OK) return st;
   if ((st = learned::capture_begin(n->n, max_pairs)) != HELM_OK) return st;
-  h->cap = n->n;
+  cap_attach(h, n);
   return HELM_OK;
 }
 
