@@ -180,8 +180,13 @@ helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nr
                              helm_solve_info* infos, int32_t* status, int32_t max_threads,
                              void* stream);
 
-/* relres[s] = ||q_s - H u_s|| / ||q_s|| in FP64 (0 for a zero q_s).
- * Q, U: DEVICE complex128 [nrhs][N]; relres: HOST [nrhs]. */
+/* The stopping rule's quantity (section 5.3: a solve ends when the initial
+ * residual is reduced by the tolerance; here per column, from U = 0), in
+ * FP64: relres[s] = ||q_s - H u_s||_2 / ||q_s||_2 with H of eq:helm /
+ * eq:LinearSystem (0 for a zero q_s; NaN where Q or U holds a NaN).
+ * Q, U: DEVICE complex128 [nrhs][N], 1 <= nrhs <= 256, read once in place;
+ * relres: HOST [nrhs]. The handle allocates a partial-sum buffer of about
+ * 1 MB on the first call and keeps it. Synchronises `stream`. */
 helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void* U,
                           double* relres, void* stream);
 

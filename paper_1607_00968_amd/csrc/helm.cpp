@@ -136,6 +136,8 @@ struct helm_ctx {
   // cached per-solve field allocation
   int fieldsP = 0;
   void* fieldmem = nullptr;
+  // partial sums of helm_residual (allocated on its first call)
+  double* resid_buf = nullptr;
   // cached Krylov workspace
   void* ws = nullptr;
   size_t wsbytes = 0;
@@ -823,6 +825,7 @@ static void free_ctx(helm_ctx* c) {
   hipFree(c->fieldmem);
   hipFree(c->cg_mem);
   hipFree(c->ws);
+  hipFree(c->resid_buf);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->net) learned::destroy(c->net);
   for (hipEvent_t e : c->evpool) hipEventDestroy(e);
@@ -1535,41 +1538,17 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
   if (st != HELM_OK) return st;
   if (!relres) return fail(HELM_ERR_INVALID_ARG, "relres is null");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int P = padP(nrhs);
   const Level& L = h->lv[0];
-  const int64_t N = L.npts;
-  c128 *A, *B;
-  if ((st = tmp_blocks(h, P, N, &A, &B)) != HELM_OK) return st;
-  c128* R = nullptr;
-  c128* part = nullptr;
-  double* d = nullptr;
-  hipError_t e = hipMalloc(&R, 16 * N * P);
-  if (e == hipSuccess) e = hipMalloc(&part, 16 * (gram_part_elems(P) + 2 * P));
-  if (e == hipSuccess) e = hipMalloc(&d, 16 * P);
-  if (e != hipSuccess) {
-    hipFree(A);
-    hipFree(B);
-    hipFree(R);
-    hipFree(part);
-    return fail(HELM_ERR_OOM, "helm_residual scratch");
+  // partial sums of the one-pass residual kernel: a buffer of the largest
+  // size (RESID_MAX_COLS columns), allocated on the first call and kept
+  if (!h->resid_buf) {
+    const size_t n = (size_t)RESID_MAX_COLS * (2 * RESID_MAX_CHUNKS + 1);
+    HCHECK(hipMalloc(&h->resid_buf, sizeof(double) * n));
   }
-  launch_to_internal(P64, N, nrhs, P, Q, A, s);
-  launch_to_internal(P64, N, nrhs, P, U, B, s);
-  launch_fine(1, P64, P64, P64, P64, h->dim, L.geo(P), B, A, R, L.dH, nullptr, L.ih, s);
-  c128* G = part + gram_part_elems(P);
-  launch_colnorm2(P64, N, P, nrhs, R, part, G, d, s);
-  launch_colnorm2(P64, N, P, nrhs, A, part, G, d + P, s);
-  std::vector<double> hd(2 * P);
-  e = hipMemcpyAsync(hd.data(), d, 16 * P, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(A);
-  hipFree(B);
-  hipFree(R);
-  hipFree(part);
-  hipFree(d);
-  HCHECK(e);
+  launch_resid_norms(L.geo(1), nrhs, L.ih, L.dH, Q, U, h->resid_buf, s);
   HCHECK(hipGetLastError());
-  for (int c = 0; c < nrhs; ++c) relres[c] = hd[P + c] > 0 ? std::sqrt(hd[c] / hd[P + c]) : 0.0;
+  HCHECK(hipMemcpyAsync(relres, h->resid_buf, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
   return HELM_OK;
 }
 

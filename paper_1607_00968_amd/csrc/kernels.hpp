@@ -51,6 +51,17 @@ void launch_convert(Prec pi, Prec po, int64_t nvals, const void* a, void* b, hip
 void launch_to_internal(Prec po, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
 void launch_to_abi(Prec pi, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
 
+// ---- k_resid.hip ------------------------------------------------------------
+// Final FP64 residual check on the ABI layout: scratch[0..nrhs) receives
+// relres_s = ||q_s - H u_s|| / ||q_s|| (0 for q_s = 0); scratch must hold
+// resid_scratch_doubles(nrhs, N) doubles (the rest holds partial sums).
+constexpr int RESID_MAX_COLS = 256;
+constexpr int RESID_MAX_CHUNKS = 256;
+int resid_chunks(int64_t N);
+size_t resid_scratch_doubles(int nrhs, int64_t N);
+void launch_resid_norms(const Geo& g, int nrhs, const double ih[3], const c128* dH, const void* Q, const void* U,
+                        double* scratch, hipStream_t s);
+
 // ---- k_setup.hip ------------------------------------------------------------
 // Fine-level diagonals from (m, gamma): dH, dM (shifted) and dw = wjac / dM.
 void launch_fine_coef(int dim, int64_t N, const double* m, const double* gamma, double omega, double beta,
