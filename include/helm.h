@@ -190,6 +190,19 @@ helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nr
 helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void* U,
                           double* relres, void* stream);
 
+/* helm_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and bitwise the same relres, but its partial sums live in
+ * a static device array of the library (about 1 MB per device, held until
+ * the process ends) instead of the handle's buffer. It calls no hipMalloc,
+ * hipFree or other allocating routine. nrhs beyond 256 (the array's size)
+ * returns HELM_ERR_INVALID_ARG. Every call on one device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller. Synchronises
+ * `stream`. */
+helm_status helm_residual_noalloc(helm_handle h, int32_t nrhs, const void* Q, const void* U,
+                                  double* relres, void* stream);
+
 /* Y = H X (op 0) or Y = M X (op 1, shifted), in FP64 (eq:LinearSystem).
  * X, Y: DEVICE complex128 [nrhs][N]. */
 helm_status helm_apply(helm_handle h, int32_t op, int32_t nrhs, const void* X, void* Y,

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "HelmError", "lib", "LIBPATH", "Handle", "helm_setup", "helm_solve_block",
     "helm_profile_enable", "helm_profile_read", "KERNEL_CLASSES",
-    "helm_residual", "helm_apply", "helm_precond", "helm_level_stencil",
+    "helm_residual", "helm_residual_noalloc", "helm_apply", "helm_precond", "helm_level_stencil",
     "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "helm_solve_batch", "ABI_SYMBOLS",
     "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture",
 ]
@@ -39,7 +39,7 @@ CYCLE = {"V": 0, "W": 1, "K": 2}
 
 ABI_SYMBOLS = (
     "helm_setup_desc_default", "helm_setup", "helm_destroy", "helm_workspace_size",
-    "helm_solve_block", "helm_solve_batch", "helm_residual", "helm_apply", "helm_precond",
+    "helm_solve_block", "helm_solve_batch", "helm_residual", "helm_residual_noalloc", "helm_apply", "helm_precond",
     "helm_level_dims", "helm_level_stencil", "helm_coarse_solve",
     "helm_profile_enable", "helm_profile_read", "helm_fine_tile", "helm_set_fine_tile",
     "helm_status_string", "helm_last_error",
@@ -100,6 +100,7 @@ def lib():
         L.helm_solve_block.argtypes = [P, I, P, P, D, C.POINTER(SolveOpts), P, C.c_size_t,
                                        C.POINTER(SolveInfo), P]
         L.helm_residual.argtypes = [P, I, P, P, P, P]
+        L.helm_residual_noalloc.argtypes = [P, I, P, P, P, P]
         L.helm_solve_batch.argtypes = [I, P, P, P, P, D, C.POINTER(SolveOpts), P, P, I, P]
         L.helm_apply.argtypes = [P, I, I, P, P, P]
         L.helm_precond.argtypes = [P, I, P, P, P]
@@ -303,6 +304,16 @@ def helm_residual(hd: Handle, Q, U, stream=None) -> np.ndarray:
     rel = np.zeros(nrhs)
     _check(lib().helm_residual(hd.ptr, nrhs, _dev_block(Q, "Q"), _dev_block(U, "U"),
                                rel.ctypes.data, _stream(stream)))
+    return rel
+
+
+def helm_residual_noalloc(hd: Handle, Q, U, stream=None) -> np.ndarray:
+    """helm_residual with its partial sums in the library's static device
+    array (no device allocation; calls on one device must not overlap)."""
+    nrhs = Q.shape[0]
+    rel = np.zeros(nrhs)
+    _check(lib().helm_residual_noalloc(hd.ptr, nrhs, _dev_block(Q, "Q"), _dev_block(U, "U"),
+                                       rel.ctypes.data, _stream(stream)))
     return rel
 
 

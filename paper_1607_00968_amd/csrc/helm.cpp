@@ -1552,6 +1552,26 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
   return HELM_OK;
 }
 
+helm_status helm_residual_noalloc(helm_handle h, int32_t nrhs, const void* Q, const void* U, double* relres,
+                                  void* stream) {
+  if (!h) return fail(HELM_ERR_INVALID_ARG, "null handle");
+  if (nrhs < 1 || nrhs > RESID_MAX_COLS)
+    return fail(HELM_ERR_INVALID_ARG, "nrhs must be 1..%d (the size of the static scratch)", RESID_MAX_COLS);
+  if (!Q || !U) return fail(HELM_ERR_INVALID_ARG, "null device pointer");
+  if (!relres) return fail(HELM_ERR_INVALID_ARG, "relres is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* scr = nullptr;
+  HCHECK(resid_static_scratch(&scr));
+  const Level& L = h->lv[0];
+  // every partial that k_resid_final reads is written by k_resid_part first,
+  // so the array's contents from an earlier call need no clearing
+  launch_resid_norms(L.geo(1), nrhs, L.ih, L.dH, Q, U, scr, s);
+  HCHECK(hipGetLastError());
+  HCHECK(hipMemcpyAsync(relres, scr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -12,9 +12,42 @@
 // does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace helm {
+
+// Partial sums of helm_residual_noalloc, for callers that cannot allocate:
+// the largest block (RESID_MAX_COLS columns x RESID_MAX_CHUNKS chunks x 2
+// doubles, plus one result per column), about 1 MB, held by every device the
+// library runs on until the process ends. Host code never passes this
+// name to a kernel: it is a host-side stand-in, and the device address comes
+// from hipGetSymbolAddress, per device, in resid_static_scratch below.
+constexpr size_t RESID_STATIC_DOUBLES = (size_t)RESID_MAX_COLS * (2 * RESID_MAX_CHUNKS + 1);
+static __device__ __align__(256) double scratch[RESID_STATIC_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t resid_static_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // (H u)_i for column-contiguous u: dH_i u_i - sum_d ih_d (u_{i-e_d} + u_{i+e_d}),
 // zero outside the grid (homogeneous Dirichlet values).

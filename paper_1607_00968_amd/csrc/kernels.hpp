@@ -61,6 +61,10 @@ int resid_chunks(int64_t N);
 size_t resid_scratch_doubles(int nrhs, int64_t N);
 void launch_resid_norms(const Geo& g, int nrhs, const double ih[3], const c128* dH, const void* Q, const void* U,
                         double* scratch, hipStream_t s);
+// Device address, on the current device, of the library's static
+// partial-sum array for launch_resid_norms (sized for RESID_MAX_COLS
+// columns); looked up once per device.
+hipError_t resid_static_scratch(double** out);
 
 // ---- k_setup.hip ------------------------------------------------------------
 // Fine-level diagonals from (m, gamma): dH, dM (shifted) and dw = wjac / dM.
