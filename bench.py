@@ -36,12 +36,16 @@ STORE = {"fp64": 16, "mixed": 8}
 
 
 def fine_sweep_bytes(prec, N, P):
-    """One damped-Jacobi sweep on the finest level from a nonzero guess:
-    reads u and f and writes u (3 fields of P complex values per point) and
-    reads the diagonal and w/D once per point."""
+    """Algorithmic bytes of one damped-Jacobi sweep on the finest level from
+    a nonzero guess: it must read u and f and write u (3 fields of P complex
+    values per point) and read one complex coefficient per point (w/D; the
+    off-diagonal couplings are constants). The kernel also reads the
+    diagonal, which a sweep written as (1 - w) u + (w/D)(f - off-diagonal
+    part of M u) would not need; those 8 (16) bytes per point are not
+    counted."""
     s = STORE[prec]
     coef = 16 if prec == "fp64" else 8
-    return N * (3 * s * P + 2 * coef)
+    return N * (3 * s * P + coef)
 
 
 def note(msg):
@@ -160,6 +164,30 @@ def fp64_compare(args, p, Q, pk, torch, Um=None):
     return out
 
 
+def mixed_gmres_compare(args, p, Q, pk, torch):
+    """The mixed-precision solver with the GMRES(20) coarsest solve from zero
+    (no network) and the same kernels, block size and orthogonalisation: one
+    untimed warm-up solve, then one timed solve. The learned coarsest
+    correction's gain is the ratio of the two RHS/s figures."""
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                       precision="mixed", coarse="gmres", coarse_iters=20)
+    tile = pk.helm_fine_tile(hd, p.nrhs)
+    U = torch.zeros_like(Q)
+
+    def solve():
+        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
+                                   block_size=args.block_size, reorth=args.reorth)
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(p.nrhs / dt, 4) if info["converged_all"] else 0.0, "unit": "RHS/s",
+            "cycles": info["cycles"], "max_relres": float(info["relres"].max()),
+            "coarsest": "GMRES(20) from zero", "fine_tile_rows_planes": list(tile)}
+
+
 def run_batch(args, pk, synth, np, torch):
     """The batched workload: 48 independent uneven instances (2D 64^2-512^2,
     3D 64^3-160^3, 1-32 sources each), mixed precision, solved concurrently by
@@ -214,21 +242,63 @@ def run_batch(args, pk, synth, np, torch):
     }
 
 
-def cpu_baseline(p, gpu_cycles, iters):
-    """The oracle (plain FP64 C, OpenMP on this host's cores) on a bounded
-    sample: `iters` preconditioned FGMRES iterations for one right-hand side
-    of the same 192^3 workload; RHS/s = 1 / (time per iteration * cycles the
-    GPU solve needed)."""
+def cpu_model():
+    """The host CPU's model name (lscpu), or the platform string."""
+    import platform
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_sample(n, iters):
+    """Runs in a child process without a GPU: the oracle (plain FP64 C,
+    OpenMP) sets up the 3-level hierarchy with the GMRES(20) coarsest solve
+    of the FP64 comparison solver and runs `iters` preconditioned FGMRES(5)
+    iterations for one right-hand side of the same workload. Prints JSON."""
     import oracle
+    import synth
+    p = synth.layered_3d(n=n, seed=3, nsrc=(8, 8))
     g = oracle.grid(p.dim, p.n, p.h)
+    t0 = time.perf_counter()
     H = oracle.Hierarchy(g, p.m, p.gamma, p.omega, p.shift, 3, coarse="gmres", coarse_iters=20)
+    t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     H.fgmres(p.Q[:1], tol=1e-30, restart=5, maxit=iters)
     dt = (time.perf_counter() - t0) / iters
-    return {"value": 1.0 / (dt * gpu_cycles), "unit": "RHS/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{iters} FGMRES(5) iterations (V-cycle + outer step) for 1 RHS of the same 192^3 workload, "
-                      f"{dt:.2f} s/iteration, scaled by the {gpu_cycles} cycles of the GPU block solve"}
+    print(json.dumps({"s_per_iter": dt, "threads": oracle.num_threads(), "setup_s": t_setup}), flush=True)
+
+
+def cpu_baseline(n, cycles, iters):
+    """The oracle on this host's cores on a bounded sample (cpu_sample, in a
+    child process with OMP_PROC_BIND=close on every core), scaled to RHS/s
+    with `cycles`: the cycle count of the FP64 GPU solve of the same
+    configuration (3 levels, GMRES(20) coarsest, FGMRES(5), block size 1),
+    i.e. of the algorithm the oracle runs."""
+    import subprocess
+    env = dict(os.environ)
+    ncores = os.cpu_count() or 1
+    env.setdefault("OMP_NUM_THREADS", str(ncores))
+    env["OMP_PROC_BIND"] = "close"
+    env["OMP_PLACES"] = "cores"
+    r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--cpu-sample", "--n", str(n),
+                        "--cpu-iters", str(iters)], capture_output=True, text=True, env=env)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU sample failed with status {r.returncode}: {r.stderr[-2000:]}")
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    dt = res["s_per_iter"]
+    return {"value": 1.0 / (dt * cycles), "unit": "RHS/s", "cores": res["threads"], "kind": "oracle",
+            "cpu": cpu_model(), "omp": f"OMP_NUM_THREADS={env['OMP_NUM_THREADS']} OMP_PROC_BIND=close "
+                                      f"OMP_PLACES=cores",
+            "sample": f"{iters} FGMRES(5) iterations (V-cycle with the GMRES(20) coarsest solve + outer step) "
+                      f"for 1 RHS of the same {n}^3 workload, {dt:.3f} s/iteration, scaled by the {cycles} cycles "
+                      f"the FP64 GPU solver of the same configuration needs; oracle setup {res['setup_s']:.1f} s "
+                      f"excluded"}
 
 
 def main():
@@ -255,7 +325,11 @@ def main():
                     help="single: the 192^3 x 64 headline; batch: 48 uneven instances solved concurrently")
     ap.add_argument("--threads", type=int, default=16, help="host threads of the batch workload")
     ap.add_argument("--reorth", type=int, default=0)
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-sample", action="store_true",
+                    help="(internal) time the oracle's sample on the CPU and print JSON; no GPU")
+    ap.add_argument("--no-mixed-compare", action="store_true",
+                    help="skip the mixed-precision solve without the network")
     ap.add_argument("--max-cycles", type=int, default=2000,
                     help="cap on cycles per solve (profiling runs; a capped solve reports value 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,6 +344,9 @@ def main():
         args.coarse_restarts = 2 if args.coarse == "learned" else 1
     if args.train_n is None:
         args.train_n = max(32, (2 * args.n // 3) // 4 * 4)
+    if args.cpu_sample:
+        cpu_sample(args.n, args.cpu_iters)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: measures one GPU only (the workload is one GPU's share); "
@@ -323,20 +400,28 @@ def main():
         step()
     note("timed steps")
     torch.cuda.synchronize()
-    pk.helm_profile_enable(hd, True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stats = pk.helm_profile_read(hd)
-    pk.helm_profile_enable(hd, False)
-
     dt = t1 - t0
     cycles = [i["cycles"] for i in infos]
     ok = all(i["converged_all"] for i in infos)
     relres = max(float(i["relres"].max()) for i in infos)
     value = p.nrhs * args.steps / dt if ok else 0.0
+
+    # one more step with per-kernel HIP events (recorded on the solve's
+    # stream around every launch) for the roofline and the time per class;
+    # kept out of the timed steps above
+    note("profiled step")
+    pk.helm_profile_enable(hd, True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    pinfo = step()
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    stats = pk.helm_profile_read(hd)
+    pk.helm_profile_enable(hd, False)
 
     # roofline of the dominant stencil kernel: the finest-level Jacobi sweep
     N = p.N
@@ -348,9 +433,13 @@ def main():
     traffic = committed_traffic(args.precision, args.n, p.nrhs, tile)
     roof = {"kernel": "finest-level damped-Jacobi sweep", "bound": "hbm", "achieved": round(achieved, 1),
             "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-            "bytes_per_launch": int(byts), "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches}
-    per_step = {k: round(v[1] / args.steps, 2) for k, v in stats.items()}
+            "bytes_per_launch": int(byts), "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
+            "measured_in": "one extra solve with per-kernel HIP events on the solve's stream",
+            "profiled_step_ms": round((tp1 - tp0) * 1e3, 1), "profiled_step_cycles": pinfo["cycles"]}
+    per_step = {k: round(v[1], 2) for k, v in stats.items()}
 
+    blk = ("64 single-column FGMRES({r}) solves sharing every launch (block size 1)" if args.block_size == 1
+           else f"block FGMRES({{r}}), blocks of {args.block_size}").format(r=args.restart)
     out = {
         "metric": "RHS solved/sec to 1e-6 rel. residual, 3D 192\u00b3 x 64 src; mixed+learned vs FP64",
         "value": round(value, 4), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
@@ -360,7 +449,7 @@ def main():
                   if args.precision == "mixed" else "f64"),
         "data": "synthetic",
         "config": {"workload": f"3D Helmholtz {args.n}^3 cells x {p.nrhs} point sources, 8 ppw, "
-                               f"block FGMRES({args.restart}) + 3-level shifted-Laplacian V(2,2), "
+                               f"{blk}, 3-level shifted-Laplacian V(2,2), "
                                + (f"GMRES({args.coarse_iters}) x {args.coarse_restarts} coarsest"
                                   if args.coarse == "gmres" else
                                   f"learned coarsest correction + GMRES({args.coarse_iters}) x "
@@ -368,18 +457,33 @@ def main():
                    "precision": args.precision, "block_size": args.block_size, "reorth": args.reorth,
                    "cycles_per_step": cycles, "max_relres": relres, "converged": ok,
                    "setup_s": round(t_setup, 2), "fine_tile_rows_planes": list(tile),
-                   "kernel_ms_per_step": per_step,
+                   "kernel_ms_profiled_step": per_step,
                    "fallbacks": sum(i["fallback_used"] for i in infos)},
         "roofline": roof,
     }
     if net_info is not None:
         out["config"]["coarse_net"] = net_info
+    if args.coarse == "learned" and args.precision == "mixed" and not args.no_mixed_compare:
+        note(f"{value:.3f} RHS/s; mixed precision without the network (GMRES(20) coarsest)")
+        mc = mixed_gmres_compare(args, p, Q, pk, torch)
+        mc["learned_gain"] = round(value / mc["value"], 4) if mc["value"] > 0 else None
+        out["config"]["mixed_gmres_compare"] = mc
+    fp64_cycles = None
     if not args.no_fp64_compare and args.precision == "mixed":
-        note(f"{value:.3f} RHS/s; FP64 comparison")
+        note("FP64 comparison")
         out["config"]["fp64_compare"] = fp64_compare(args, p, Q, pk, torch, U)
+        fp64_cycles = out["config"]["fp64_compare"]["cycles"]
     if not args.no_cpu_baseline:
-        note("CPU baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(p, cycles[0], args.cpu_iters)
+        note("CPU baseline (oracle, child process)")
+        if fp64_cycles is None:
+            # the oracle's configuration (FP64, GMRES(20) coarsest) on the GPU, untimed
+            hf = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                               precision="fp64", coarse="gmres", coarse_iters=20)
+            fi = pk.helm_solve_block(hf, Q, torch.zeros_like(Q), tol=1e-6, restart=args.restart,
+                                     max_cycles=args.max_cycles, block_size=args.block_size, reorth=args.reorth)
+            fp64_cycles = fi["cycles"]
+            del hf
+        out["cpu_baseline"] = cpu_baseline(args.n, fp64_cycles, args.cpu_iters)
     print(json.dumps(out), flush=True)
 
 
