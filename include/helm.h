@@ -310,6 +310,14 @@ helm_status helm_net_forward(helm_net n, int32_t B, const float* x, float* out, 
  * loss: HOST. Synchronises `stream`. */
 helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const float* target,
                                const uint8_t* mask, float* grad, double* loss, void* stream);
+/* One training step on a caller-supplied minibatch (buffers as for
+ * helm_net_loss_grad; no sampling and no phase rotation): the loss and its
+ * gradient, then one Adam update (Kingma & Ba: beta 0.9, 0.999, eps 1e-8,
+ * bias-corrected moments; step t counts every update since the parameters
+ * were last set) of the FP32 master weights and their BF16 working copies.
+ * loss: HOST, may be NULL. Synchronises `stream`. */
+helm_status helm_net_train_step(helm_net n, int32_t B, const float* x, const float* target, const uint8_t* mask,
+                               double lr, double* loss, void* stream);
 /* Training pairs from a solver: until the next call, every coarsest solve of
  * `h` (3D; coarse must be LU or GMRES; its coarsest grid must fit D) stores
  * (input volume, exact-solve target) of each nonzero column into a pool of

@@ -190,6 +190,7 @@ class Hierarchy:
                  coarse="lu", coarse_iters=20, coarse_restarts=1, cycle="V"):
         self.g = g
         self.levels = levels
+        self.omega, self.beta = float(omega), float(beta)
         self._m, self._gamma = _d(m), _d(gamma)
         nu1 = np.ascontiguousarray(nu_pre if nu_pre is not None else [2] * levels, dtype=np.int32)
         nu2 = np.ascontiguousarray(nu_post if nu_post is not None else [2] * levels, dtype=np.int32)

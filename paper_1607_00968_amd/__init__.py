@@ -45,7 +45,7 @@ ABI_SYMBOLS = (
     "helm_status_string", "helm_last_error",
     "helm_net_nparams", "helm_net_create", "helm_net_destroy", "helm_net_set_params",
     "helm_net_get_params", "helm_net_save", "helm_net_forward", "helm_net_loss_grad",
-    "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train",
+    "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train", "helm_net_train_step",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
                   "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep")
@@ -128,6 +128,7 @@ def lib():
         L.helm_net_pairs.argtypes = [P]
         L.helm_net_pool_read.argtypes = [P, C.c_int64, P, P, P]
         L.helm_net_train.argtypes = [P, I, I, D, C.c_uint64, P, P]
+        L.helm_net_train_step.argtypes = [P, I, P, P, P, D, C.POINTER(D), P]
         _lib = L
     return _lib
 
@@ -459,6 +460,20 @@ class Net:
         V = self.D ** 3
         _check(lib().helm_net_pool_read(self.ptr, int(i), _dev_f32(x, "x", (V, 4)),
                                         _dev_f32(target, "target", (V, 2)), _stream(stream)))
+
+    def train_step(self, x, target, mask, lr=1e-3, stream=None) -> float:
+        """One Adam step on the given minibatch (x [B, D^3, 4], target
+        [B, D^3, 2] float32 CUDA, mask uint8 CUDA [D^3]); returns the loss."""
+        import torch
+        B = x.shape[0]
+        V = self.D ** 3
+        if not (mask.is_cuda and mask.dtype == torch.uint8 and mask.numel() == V and mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 CUDA tensor of D^3 entries")
+        loss = C.c_double(0.0)
+        _check(lib().helm_net_train_step(self.ptr, B, _dev_f32(x, "x", (B, V, 4)),
+                                         _dev_f32(target, "target", (B, V, 2)), C.c_void_p(mask.data_ptr()),
+                                         float(lr), C.byref(loss), _stream(stream)))
+        return loss.value
 
     def train(self, steps, batch, lr=1e-3, seed=0, stream=None) -> np.ndarray:
         hist = np.zeros(steps, dtype=np.float64)

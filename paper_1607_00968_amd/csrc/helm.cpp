@@ -1657,6 +1657,12 @@ helm_status helm_net_loss_grad(helm_net n, int32_t B, const float* x, const floa
   return learned::loss_grad(n->n, B, x, target, mask, grad, loss, static_cast<hipStream_t>(stream));
 }
 
+helm_status helm_net_train_step(helm_net n, int32_t B, const float* x, const float* target, const uint8_t* mask,
+                               double lr, double* loss, void* stream) {
+  if (!n) return fail(HELM_ERR_INVALID_ARG, "null network");
+  return learned::train_step(n->n, B, x, target, mask, lr, loss, static_cast<hipStream_t>(stream));
+}
+
 helm_status helm_net_capture(helm_handle h, helm_net n, int32_t max_pairs) {
   if (!h || !n) return fail(HELM_ERR_INVALID_ARG, "null argument");
   if (max_pairs == 0) {

@@ -1499,6 +1499,39 @@ helm_status pool_read(Net* n, int64_t i, float* x, float* t, hipStream_t s) {
   return HELM_OK;
 }
 
+// One Adam step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+// moments) on the FP32 master weights from the gradient in n->g, then the
+// BF16 working copies.
+static void adam_update(Net* n, double lr, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  ++n->adam_t;
+  const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+  hipLaunchKernelGGL(k_adam, g1(n->np), dim3(256), 0, s, n->np, n->p, (const float*)n->g, n->am, n->av, (float)lr, b1,
+                     b2, eps, c1, c2);
+  pack_weights(n, s);
+}
+
+helm_status train_step(Net* n, int B, const float* x, const float* target, const uint8_t* mask, double lr,
+                       double* loss, hipStream_t s) {
+  if (B < 1 || B > n->Bmax) return fail(HELM_ERR_INVALID_ARG, "batch %d outside 1..%d", B, n->Bmax);
+  if (!x || !target || !mask) return fail(HELM_ERR_INVALID_ARG, "null buffer");
+  if (!(lr > 0.0)) return fail(HELM_ERR_INVALID_ARG, "lr must be > 0");
+  helm_status st = ensure_backward(n);
+  if (st != HELM_OK) return st;
+  const int64_t BV = (int64_t)B * n->V;
+  hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
+  LCHECK(hipMemcpyAsync(n->tgt, target, 8 * BV, hipMemcpyDeviceToDevice, s));
+  run_forward(n, B, s);
+  run_loss_backward(n, B, mask, n->lossd, s);
+  adam_update(n, lr, s);
+  float lf = 0.f;
+  LCHECK(hipMemcpyAsync(&lf, n->lossd, 4, hipMemcpyDeviceToHost, s));
+  LCHECK(hipStreamSynchronize(s));
+  LCHECK(hipGetLastError());
+  if (loss) *loss = lf;
+  return HELM_OK;
+}
+
 helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double* hist, hipStream_t s) {
   if (steps < 1 || batch < 1 || batch > n->Bmax || !(lr > 0.0))
     return fail(HELM_ERR_INVALID_ARG, "steps >= 1, batch 1..%d and lr > 0 are required", n->Bmax);
@@ -1527,7 +1560,6 @@ helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double
   }
   LCHECK(hipMemcpyAsync(n->idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, s));
   LCHECK(hipMemcpyAsync(n->rot, rot.data(), 4 * rot.size(), hipMemcpyHostToDevice, s));
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const int64_t BV = (int64_t)batch * n->V;
   for (int k = 0; k < steps; ++k) {
     hipLaunchKernelGGL(k_gather_samples, g1(BV), dim3(256), 0, s, batch, (const int*)(n->idx + (size_t)k * batch),
@@ -1535,11 +1567,7 @@ helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double
                        n->x0, n->tgt);
     run_forward(n, batch, s);
     run_loss_backward(n, batch, n->mask, n->hist + k, s);
-    ++n->adam_t;
-    const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
-    hipLaunchKernelGGL(k_adam, g1(n->np), dim3(256), 0, s, n->np, n->p, (const float*)n->g, n->am, n->av, (float)lr,
-                       b1, b2, eps, c1, c2);
-    pack_weights(n, s);
+    adam_update(n, lr, s);
   }
   std::vector<float> h(steps);
   LCHECK(hipMemcpyAsync(h.data(), n->hist, 4 * (size_t)steps, hipMemcpyDeviceToHost, s));

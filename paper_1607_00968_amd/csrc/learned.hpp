@@ -75,6 +75,9 @@ int64_t pairs(const Net* n);
 helm_status pool_read(Net* n, int64_t i, float* x, float* t, hipStream_t s);
 // Adam on random minibatches of the pool; hist[steps] gets the loss per step.
 helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double* hist, hipStream_t s);
+// One Adam step on a caller-supplied minibatch (no sampling, no phase turn).
+helm_status train_step(Net* n, int B, const float* x, const float* target, const uint8_t* mask, double lr,
+                       double* loss, hipStream_t s);
 
 }  // namespace learned
 }  // namespace helm

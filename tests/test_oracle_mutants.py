@@ -176,3 +176,91 @@ def test_unmutated_copy_passes_the_same_pins(tmp_path):
         for m in MUTANTS:
             for check in m[5]:
                 check()
+
+
+# Planted mistakes in the oracle's learned coarsest solve and Adam update
+# (oracle/learned.py, numpy): each mutant is the module's source with one
+# slip, loaded as a module of its own and run through the pins named beside it.
+import importlib.util  # noqa: E402
+import sys  # noqa: E402
+
+import test_oracle_learned as lpins  # noqa: E402
+
+_P32 = []
+
+
+def _p32():
+    """The pins' 32^3 layered problem (built once)."""
+    if not _P32:
+        _P32.append(lpins.synth.layered_3d(n=32, nsrc=(2, 2), levels=3, seed=2))
+    return _P32[0]
+
+
+LEARNED_MUTANTS = [
+    ("rms over the whole volume", "axis=1) / Nc)", "axis=1) / D ** 3)",
+     [lambda: lpins.test_constant_network_closed_form(_p32())]),
+    ("output scaled by H instead of H^2", "E[b] = (H2 * rms[b])", "E[b] = (np.sqrt(H2) * rms[b])",
+     [lambda: lpins.test_probe_networks_see_the_stated_channels(_p32())]),
+    ("diagonal channels without H^2", "centre = (H2 * st[:, 13])", "centre = (st[:, 13])",
+     [lambda: lpins.test_probe_networks_see_the_stated_channels(_p32())]),
+    ("GMRES restarts ignore the network's guess", "E = E + hier_gmres.coarse_solve(R)",
+     "E = hier_gmres.coarse_solve(R)", [lambda: lpins.test_perfect_network_gives_the_exact_solve(_p32(), 8, 2)]),
+    ("fallback only on non-finite output", "np.abs(out).max(initial=0.0) <= 1e4", "True",
+     [lambda: lpins.test_fallback_on_nonfinite_or_huge_output(_p32())]),
+    ("Adam without bias correction", "mhat = m / (1.0 - b1 ** t)", "mhat = m",
+     [lpins.test_adam_two_steps_worked_by_hand]),
+    ("Adam second moment of |g|", "v = b2 * v + (1.0 - b2) * g * g", "v = b2 * v + (1.0 - b2) * np.abs(g)",
+     [lpins.test_adam_two_steps_worked_by_hand]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", LEARNED_MUTANTS, ids=[m[0] for m in LEARNED_MUTANTS])
+def test_learned_pins_catch_planted_mistake(tmp_path, name, old, new, checks):
+    """Also run unmutated by test_learned_unmutated_copy_passes below."""
+    with open(os.path.join(SRC, "learned.py")) as fh:
+        text = fh.read()
+    changed = plant(text, old, new, 0)
+    assert changed != text
+    path = tmp_path / "learned_mutant.py"
+    path.write_text(changed)
+    spec = importlib.util.spec_from_file_location("oracle.learned_mutant", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    mod.__package__ = "oracle"
+    sys.modules["oracle.learned_mutant"] = mod
+    spec.loader.exec_module(mod)
+    saved = lpins.ol
+    lpins.ol = mod
+    caught = []
+    try:
+        for check in checks:
+            try:
+                check()
+            except AssertionError as e:
+                caught.append(str(e)[:80])
+    finally:
+        lpins.ol = saved
+        sys.modules.pop("oracle.learned_mutant", None)
+    assert caught, f"no pin caught the planted mistake: {name}"
+
+
+def test_learned_unmutated_copy_passes(tmp_path):
+    """The harness for the learned oracle: a copy of the module loaded the
+    same way, without a planted mistake, passes every pin used above."""
+    with open(os.path.join(SRC, "learned.py")) as fh:
+        text = fh.read()
+    path = tmp_path / "learned_copy.py"
+    path.write_text(text)
+    spec = importlib.util.spec_from_file_location("oracle.learned_copy", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    mod.__package__ = "oracle"
+    sys.modules["oracle.learned_copy"] = mod
+    spec.loader.exec_module(mod)
+    saved = lpins.ol
+    lpins.ol = mod
+    try:
+        for m in LEARNED_MUTANTS:
+            for check in m[3]:
+                check()
+    finally:
+        lpins.ol = saved
+        sys.modules.pop("oracle.learned_copy", None)
