@@ -53,24 +53,43 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def committed_traffic(precision, n, nrhs, tile):
-    """HBM bytes per launch of the finest-level sweep from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel
-    calibration recorded there), or None when that summary was taken for
-    another configuration or tile."""
-    path = os.path.join(ROOT, "profiles", "fine_sweep_mixed_192x64_traffic.md")
-    try:
-        lines = open(path).read().splitlines()
-    except OSError:
-        return None
-    for ln in lines:
-        if not ln.startswith("traffic:"):
+def fine_kernel_bytes(prec, N, Nc, P):
+    """Algorithmic bytes per launch of each finest-level kernel class (HBM
+    bound): the fields a launch must read and write once (u, f, out: P
+    complex values per point in the field precision; the level-2 coarse
+    field, BF16 in mixed precision, for the transfers) and one coefficient
+    per point. N: finest unknowns, Nc: level-2 unknowns, P: columns."""
+    s = STORE[prec]
+    coef = 16 if prec == "fp64" else 8
+    sc = 16 if prec == "fp64" else 4
+    return {
+        "fine_sweep": fine_sweep_bytes(prec, N, P),             # u, f -> u
+        "fine_sweep01": N * (2 * s * P + coef),                 # f -> u (two sweeps from zero)
+        "fine_sweep0": N * (2 * s * P + coef),                  # f -> u
+        "fine_prosweep": fine_sweep_bytes(prec, N, P) + Nc * sc * P,  # u, f, e_c -> u
+        "fine_resid": N * (2 * s * P + coef) + Nc * sc * P,     # u, f -> r_c (restricted)
+    }
+
+
+def committed_traffic(precision, n, nrhs, tile, kernel="fine_sweep"):
+    """HBM bytes per launch of a finest-level kernel class from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summaries (scaled by the copy-kernel
+    calibration recorded there), or None when no summary was taken for this
+    kernel, configuration and tile."""
+    found = None
+    pdir = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not fn.endswith("_traffic.md"):
             continue
-        kv = dict(t.split("=", 1) for t in ln[len("traffic:"):].split())
-        if (kv.get("precision") == precision and int(kv.get("n", 0)) == n and int(kv.get("nrhs", 0)) == nrhs
-                and kv.get("tile") == f"{tile[0]}x{tile[1]}"):
-            return int(float(kv["bytes_per_launch"]))
-    return None
+        for ln in open(os.path.join(pdir, fn)).read().splitlines():
+            if not ln.startswith("traffic:"):
+                continue
+            kv = dict(t.split("=", 1) for t in ln[len("traffic:"):].split())
+            if (kv.get("kernel", "fine_sweep") == kernel and kv.get("precision") == precision
+                    and int(kv.get("n", 0)) == n and int(kv.get("nrhs", 0)) == nrhs
+                    and kv.get("tile") == f"{tile[0]}x{tile[1]}"):
+                found = int(float(kv["bytes_per_launch"]))
+    return found
 
 
 def train_coarse_net(args, pk, synth, np, torch):
@@ -423,19 +442,29 @@ def main():
     stats = pk.helm_profile_read(hd)
     pk.helm_profile_enable(hd, False)
 
-    # roofline of the dominant stencil kernel: the finest-level Jacobi sweep
+    # roofline of the dominant finest-level kernel (the HBM-bound class with
+    # the most time in the profiled step), and the fraction of every class
     N = p.N
     P = (p.nrhs + 3) // 4 * 4
-    launches, ms = stats["fine_sweep"]
-    byts = fine_sweep_bytes(args.precision, N, P)
-    avg_s = ms / 1e3 / max(launches, 1)
-    achieved = byts / avg_s / 1e9
-    traffic = committed_traffic(args.precision, args.n, p.nrhs, tile)
-    roof = {"kernel": "finest-level damped-Jacobi sweep", "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-            "bytes_per_launch": int(byts), "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
+    Nc = (args.n // 2 - 1) ** 3
+    kb = fine_kernel_bytes(args.precision, N, Nc, P)
+    fine = {}
+    for k, byts in kb.items():
+        launches, ms = stats[k]
+        if launches:
+            avg_s = ms / 1e3 / launches
+            fine[k] = {"launches": launches, "avg_launch_ms": round(avg_s * 1e3, 4), "bytes_per_launch": int(byts),
+                       "achieved": round(byts / avg_s / 1e9, 1), "frac": round(byts / avg_s / 1e9 / 8000.0, 4),
+                       "total_ms": round(ms, 1)}
+    dom = max(fine, key=lambda k: fine[k]["total_ms"])
+    d = fine[dom]
+    roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved"], "peak": 8000.0, "unit": "GB/s",
+            "frac": d["frac"], "traffic": committed_traffic(args.precision, args.n, p.nrhs, tile, dom),
+            "bytes_per_launch": d["bytes_per_launch"], "avg_launch_ms": d["avg_launch_ms"],
+            "launches": d["launches"],
             "measured_in": "one extra solve with per-kernel HIP events on the solve's stream",
-            "profiled_step_ms": round((tp1 - tp0) * 1e3, 1), "profiled_step_cycles": pinfo["cycles"]}
+            "profiled_step_ms": round((tp1 - tp0) * 1e3, 1), "profiled_step_cycles": pinfo["cycles"],
+            "fine_kernels": fine}
     per_step = {k: round(v[1], 2) for k, v in stats.items()}
 
     blk = ("64 single-column FGMRES({r}) solves sharing every launch (block size 1)" if args.block_size == 1

@@ -254,6 +254,8 @@ enum {
   HELM_K_UPDATE,         /* block updates W -= V H, V = W R^-1, X += Z Y */
   HELM_K_FINE_SWEEP0,    /* the first (zero initial guess) sweep on the finest level */
   HELM_K_FINE_PROSWEEP,  /* the first post-smoothing sweep with the prolongation fused in */
+  HELM_K_FINE_SWEEP01,   /* the zero-guess sweep and the next sweep fused in one pass (3D,
+                            LDS-blocked tiles) */
   HELM_K_NCLASS
 };
 typedef struct {

@@ -48,7 +48,7 @@ ABI_SYMBOLS = (
     "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train", "helm_net_train_step",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
-                  "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep")
+                  "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep", "fine_sweep01")
 
 
 class HelmError(RuntimeError):

@@ -283,19 +283,30 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   const int alternations = (npre >= 1 ? npre - 1 : 0) + npost;
   void* a = (alternations % 2 == 0) ? out : tmp;
   void* b = (a == out) ? tmp : out;
+  Level& C = c->lv[l + 1];
+  const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
   if (npre >= 1) {
-    level_op(c, l, 3, P, nullptr, f, a, s);
-    for (int k = 1; k < npre; ++k) {
+    int k1 = 1;
+    if (l == 0 && c->dim == 3 && npre >= 2 && !c->plan && can_sweep01(pf, pt, L.geo(P))) {
+      // the zero-guess sweep and the next one in one pass: b = JAC(w D^-1 f),
+      // where the second sweep would have written
+      Prof pr(c, HELM_K_FINE_SWEEP01, s);
+      const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+      launch_sweep01(pf, pt, L.geo(P), f, b, diag, level_dw(c, 0), L.ih, s);
+      std::swap(a, b);
+      k1 = 2;
+    } else {
+      level_op(c, l, 3, P, nullptr, f, a, s);
+    }
+    for (int k = k1; k < npre; ++k) {
       level_op(c, l, 2, P, a, f, b, s);
       std::swap(a, b);
     }
   } else {
     zero_field(c, l, P, a, s);
   }
-  Level& C = c->lv[l + 1];
-  const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
   bool fused = false;
-  if (l == 0 && c->dim == 3 && !c->plan) {
+  if (l == 0 && c->dim == 3 && !c->plan && can_resid_restrict(pf, pc, pt, L.geo(P))) {
     // residual and restriction in one pass (counted as the fine residual)
     Prof pr(c, HELM_K_FINE_RESID, s);
     const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
@@ -328,7 +339,7 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
     field_axpy(c, l + 1, P, C.U1, C.U0, s);
   }
   int k0 = 0;
-  if (l == 0 && c->dim == 3 && npost >= 1 && !c->plan) {
+  if (l == 0 && c->dim == 3 && npost >= 1 && !c->plan && can_prolong_sweep(pc, pf, pt, L.geo(P))) {
     // prolongation and correction fused into the first post-smoothing sweep:
     // b = JAC(a + P e); a itself is not updated (the next sweep overwrites it)
     Prof pr(c, HELM_K_FINE_PROSWEEP, s);
@@ -691,9 +702,12 @@ static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
     c->tile = t;
     return HELM_OK;
   }
+  // Each candidate is timed on a whole cycle (the fused finest-level kernels
+  // exist for some tiles only, and the LDS tiles also select the LDS form of
+  // the Galerkin sweeps), from a zero right-hand side in the level-0 buffers,
+  // with kernel timing and pair capture off.
   Level& L = c->lv[0];
   const size_t bytes = psize(field_prec(c, 0)) * L.npts * P;
-  HCHECK(hipMemsetAsync(L.U0, 0, bytes, s));
   HCHECK(hipMemsetAsync(L.F, 0, bytes, s));
   hipEvent_t a, b;
   HCHECK(hipEventCreate(&a));
@@ -701,19 +715,22 @@ static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
   // rows per lane of the register-blocked kernel, or 8 / 16: the LDS-blocked
   // kernel on 16 x 8 / 16 x 16 tiles (k_fine_t16)
   const int rys[5] = {1, 2, 4, 8, 16};
-  const int zcs[3] = {16, 32, 64};
+  const int zcs[4] = {16, 24, 32, 64};
   double best = 1e30;
   FineTile bt = c->tile;
   const bool was = c->prof;
+  learned::Net* cap = c->cap;
+  const int64_t fb0 = c->fallbacks;
   c->prof = false;
+  c->cap = nullptr;
   for (int ri = 0; ri < 5; ++ri)
-    for (int zi = 0; zi < 3; ++zi) {
+    for (int zi = 0; zi < 4; ++zi) {
       set_fine_tile(FineTile{rys[ri], zcs[zi]});
-      level_op(c, 0, 2, P, L.U0, L.F, L.U1, s);  // warm-up
+      cycle_rec(c, 0, P, L.F, L.U0, L.U1, s);  // warm-up
       std::vector<float> ts;
       for (int r = 0; r < 3; ++r) {
         hipEventRecord(a, s);
-        level_op(c, 0, 2, P, L.U0, L.F, L.U1, s);
+        cycle_rec(c, 0, P, L.F, L.U0, L.U1, s);
         hipEventRecord(b, s);
         hipEventSynchronize(b);
         float ms = 0.f;
@@ -727,6 +744,8 @@ static helm_status autotune_fine(helm_ctx* c, int P, hipStream_t s) {
       }
     }
   c->prof = was;
+  c->cap = cap;
+  c->fallbacks = fb0;
   hipEventDestroy(a);
   hipEventDestroy(b);
   HCHECK(hipGetLastError());

@@ -524,12 +524,42 @@ __device__ inline Par par_of(int i, int nc) {
   return r;
 }
 
-// u with the coarse-grid correction added on the fly (PRO): value of u + P e
-// at fine point (x, y, z), the terms in the order of k_prolong_add.
-template <int K, class S, class SC, class T, int PRO>
-__device__ inline void ld_u(const S* p, bool ok, int x, int y, int z, const SC* ec, const Geo& gc, int c, cx<T>* o) {
+// The sweep's input u at fine point (x, y, z), K columns from p:
+//  PRO = 0: u as stored;
+//  PRO = 1: u with the coarse-grid correction added on the fly, u + P e, the
+//           terms in the order of k_prolong_add;
+//  PRO = 2: p points at f and u is the zero-guess sweep's result w D^-1 f,
+//           formed as that sweep forms it (so the fused pair of sweeps is
+//           bitwise the two separate ones).
+// Coarse correction staged in LDS for the prolongation-fused sweep: a window
+// of LCZ coarse planes (slot = plane % LCZ) of the LCX x LCY coarse points
+// the 16 x TY fine tile and its ring interpolate from, CG columns each.
+struct LCoarse {
+  const unsigned char* base;  // LDS, this lane's K columns of point 0 of slot 0
+  int cx0, cy0;               // coarse (x, y) of the window's first point
+  int stride_pt, stride_slot; // bytes between points / between plane slots
+};
+constexpr int LCZ = 3;
+
+template <int K, class S, class SC, class T, int PRO, bool LDSC = false>
+__device__ inline void ld_u(const S* p, bool ok, int x, int y, int z, const SC* ec, const Geo& gc,
+                            const cx<T>* dwp, int64_t pt, int c, cx<T>* o, const LCoarse& lc = LCoarse{}) {
   ldKz<K, S, T>(p, ok, o);
+  if (PRO == 2) {
+    if (ok) {
+      const cx<T> w = dwp[pt];  // pt: the point's index (z, y, x)
+#pragma unroll
+      for (int k = 0; k < K; ++k) o[k] = w * o[k];
+    }
+    return;
+  }
   if (!PRO || !ok) return;
+  if (LDSC) {
+    // recompute the (loop-invariant) parents of x and y at every use: a few
+    // integer operations, where keeping them for the own point and the ring
+    // point would hold about 20 registers through the whole z march
+    asm volatile("" : "+v"(x), "+v"(y));
+  }
   const Par ax = par_of(x, gc.nx), ay = par_of(y, gc.ny), az = par_of(z, gc.nz);
   cx<T> v[K];
 #pragma unroll
@@ -544,17 +574,33 @@ __device__ inline void ld_u(const S* p, bool ok, int x, int y, int z, const SC* 
         const float wx = e ? ax.w1 : ax.w0, wy = b ? ay.w1 : ay.w0, wz = a ? az.w1 : az.w0;
         const T w = (T)(wx * wy * wz);
         const int cx_ = e ? ax.p1 : ax.p0, cy_ = b ? ay.p1 : ay.p0, cz_ = a ? az.p1 : az.p0;
-        const int64_t ci = ((int64_t)cz_ * gc.ny + cy_) * gc.nx + cx_;
-        ldK<K, SC, T>(ec + ci * gc.P + c, v);
+        if (LDSC) {
+          const unsigned char* q = lc.base + (cz_ % LCZ) * lc.stride_slot +
+                                   ((cy_ - lc.cy0) * (TB / 2 + 2) + (cx_ - lc.cx0)) * lc.stride_pt;
+          ldK<K, SC, T>(reinterpret_cast<const SC*>(q), v);
+        } else {
+          const int64_t ci = ((int64_t)cz_ * gc.ny + cy_) * gc.nx + cx_;
+          ldK<K, SC, T>(ec + ci * gc.P + c, v);
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) o[k] = o[k] + w * v[k];
+        // LDS parents one at a time: the scheduler would otherwise hoist all
+        // eight reads (8 x 2K registers) ahead of their sums
+        if (LDSC) __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
 }
 
+// Waves per SIMD the 16-row tile asks the compiler for: 8 (at most 64 VGPRs,
+// two 1024-lane workgroups per CU) for the FP32 sweeps, which fit without
+// spilling (the compiler's resource remarks are checked for scratch).
+template <class S, class T, int TY, int PRO> constexpr int t16_waves() {
+  return TY == 16 && PRO != 1 && sizeof(S) == 8 && sizeof(T) == 4 ? 8 : 1;
+}
+
 template <class S, class T, int MODE, int TY, class SC = S, int PRO = 0>
-__global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
+__global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
                                                       const S* __restrict__ f, S* __restrict__ out,
                                                       const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw,
                                                       T ihx, T ihy, T ihz, const SC* __restrict__ ec, Geo gc) {
@@ -569,6 +615,15 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   constexpr int NPT = HX * HY;
   constexpr int PSR = (NPT * 32 + 255) / 256 * 256;
   __shared__ __attribute__((aligned(256))) unsigned char smraw[4 * PSR + 256];
+  // PRO = 1 with BF16 coarse fields on 16-row tiles: the coarse correction
+  // the tile interpolates from is staged in LDS one coarse plane at a time
+  // (16 B = K columns per chunk), instead of every fine value gathering its
+  // up to 8 parents from global memory
+  constexpr bool LDSC = PRO == 1 && TY == 16 && sizeof(SC) * K == 16;
+  constexpr int LCX = TB / 2 + 2, LCY = TY / 2 + 2;
+  constexpr int LPT = CG * (int)sizeof(SC);  // bytes per coarse point
+  constexpr int LSLOT = LCX * LCY * LPT;
+  __shared__ __attribute__((aligned(16))) unsigned char lcraw[LDSC ? LCZ * LSLOT : 16];
   const int64_t t0 = (int64_t)(blockIdx.x % 8) * zt.per + blockIdx.x / 8;
   if (t0 >= zt.ntiles) return;  // whole workgroup leaves together
   int64_t t = t0;
@@ -607,18 +662,60 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   const bool rin = ring && rx >= 0 && rx < g.nx && ry >= 0 && ry < g.ny;
   const int64_t icol = (int64_t)y * g.nx + x;    // own (x, y) column index
   const int64_t rcol = (int64_t)ry * g.nx + rx;  // ring (x, y) column index
+  LCoarse lc;
+  lc.base = lcraw + sl * 16;
+  lc.cx0 = xb * (TB / 2) - 1;
+  lc.cy0 = yb * (TY / 2) - 1;
+  lc.stride_pt = LPT;
+  lc.stride_slot = LSLOT;
+  // coarse plane pz (all window points, zero outside the coarse grid) into
+  // slot pz % LCZ: the global load now, the LDS store by put_stage later
+  uint4 stv = {0u, 0u, 0u, 0u};
+  int stpz = -1;
+  const int ste = threadIdx.x;  // chunk of this lane (LCX * LCY * 4 chunks)
+  auto load_stage = [&](int pz) {
+    stpz = -1;
+    if (!LDSC || pz < 0 || pz >= gc.nz || ste >= LCX * LCY * 4) return;
+    stpz = pz;
+    const int pi = ste >> 2, q = ste & 3;
+    const int ccx = lc.cx0 + pi % LCX, ccy = lc.cy0 + pi / LCX;
+    stv = uint4{0u, 0u, 0u, 0u};
+    if (ccx >= 0 && ccx < gc.nx && ccy >= 0 && ccy < gc.ny)
+      stv = *reinterpret_cast<const uint4*>(ec + (((int64_t)pz * gc.ny + ccy) * gc.nx + ccx) * gc.P + cgi * CG + q * K);
+  };
+  auto put_stage = [&]() {
+    if (!LDSC || stpz < 0) return;
+    *reinterpret_cast<uint4*>(lcraw + (stpz % LCZ) * LSLOT + (ste >> 2) * LPT + (ste & 3) * 16) = stv;
+  };
+  if (LDSC) {
+    // the window the prologue and the first step read: the parents of
+    // planes z0 - 1 (if it exists) to z0 + 1
+    const int zl = z0 > 0 ? z0 - 1 : z0;
+    const int plo = ((zl & 1) ? zl / 2 : zl / 2 - 1) < 0 ? 0 : ((zl & 1) ? zl / 2 : zl / 2 - 1);
+    const int phi = (z0 + 1) / 2 < gc.nz - 1 ? (z0 + 1) / 2 : gc.nz - 1;
+    for (int pz = plo; pz <= phi; ++pz) {
+      load_stage(pz);
+      put_stage();
+    }
+    __syncthreads();
+  }
   // TY = 8 prefetches one plane ahead (u(z+2), the ring of z+1, f(z+1) are
   // in flight while plane z is computed); TY = 16 keeps the registers low
   constexpr bool PF = TY == 8;
   cx<T> um[K], uc[K], un[K], unn[K], rc[K], rn[K], fc[K], fn[K];
-  const S* up = u + ((int64_t)z0 * plane + icol) * g.P + c;
-  const S* rpp = u + ((int64_t)z0 * plane + rcol) * g.P + c;
+  // PRO = 2 reads u from f (the zero-guess sweep is formed on the fly):
+  // the same pointers, so that the compiler keeps one copy of them
+  const S* ub = PRO == 2 ? f : u;
+  const S* up = ub + ((int64_t)z0 * plane + icol) * g.P + c;
+  const S* rpp = ub + ((int64_t)z0 * plane + rcol) * g.P + c;
   const S* fp = f + ((int64_t)z0 * plane + icol) * g.P + c;
-  ld_u<K, S, SC, T, PRO>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, c, um);
-  ld_u<K, S, SC, T, PRO>(up, inb, x, y, z0, ec, gc, c, uc);
+  ld_u<K, S, SC, T, PRO, LDSC>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, dw, (int64_t)(z0 - 1) * plane + icol,
+                               c, um, lc);
+  ld_u<K, S, SC, T, PRO, LDSC>(up, inb, x, y, z0, ec, gc, dw, (int64_t)z0 * plane + icol, c, uc, lc);
   if (PF) {
-    ld_u<K, S, SC, T, PRO>(up + sz, inb && z0 + 1 < g.nz, x, y, z0 + 1, ec, gc, c, un);
-    ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z0, ec, gc, c, rc);
+    ld_u<K, S, SC, T, PRO>(up + sz, inb && z0 + 1 < g.nz, x, y, z0 + 1, ec, gc, dw, (int64_t)(z0 + 1) * plane + icol,
+                           c, un);
+    ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z0, ec, gc, dw, (int64_t)z0 * plane + rcol, c, rc);
     if (MODE != 0) ldKz<K, S, T>(fp, inb, fc);
   }
   // the tile holds values in storage precision (32 B per lane and point);
@@ -628,22 +725,37 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   const int me = ((py + 1) * HX + px + 1) * K;  // own point, in units of cx<LE>
   const int ro = (hy * HX + hx) * K;
   constexpr int RX = K, RYS = HX * K;           // x and y neighbour strides
+  // One base address for the own point and its four in-plane neighbours:
+  // the lowest of them (y - 1), so that every access is the base plus a
+  // constant non-negative offset (LDS offsets cannot be negative). The empty
+  // asm keeps the compiler from folding the base back into `me` and holding
+  // separate address registers for the neighbours below it.
+  int lo = me - RYS;
+  asm volatile("" : "+v"(lo));
+  cx<LE>* const nb = sm + lo;
   for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
     if (PF) {
       const bool more = z + 1 < z1;
-      ld_u<K, S, SC, T, PRO>(up + 2 * sz, inb && z + 2 < g.nz, x, y, z + 2, ec, gc, c, unn);
-      ld_u<K, S, SC, T, PRO>(rpp + sz, rin && more, rx, ry, z + 1, ec, gc, c, rn);
+      ld_u<K, S, SC, T, PRO>(up + 2 * sz, inb && z + 2 < g.nz, x, y, z + 2, ec, gc, dw,
+                             (int64_t)(z + 2) * plane + icol, c, unn);
+      ld_u<K, S, SC, T, PRO>(rpp + sz, rin && more, rx, ry, z + 1, ec, gc, dw, (int64_t)(z + 1) * plane + rcol, c,
+                             rn);
       if (MODE != 0) ldKz<K, S, T>(fp + sz, inb && more, fn);
     } else {
-      ld_u<K, S, SC, T, PRO>(up + sz, inb && z + 1 < g.nz, x, y, z + 1, ec, gc, c, un);
-      ld_u<K, S, SC, T, PRO>(rpp, rin, rx, ry, z, ec, gc, c, rc);
+      ld_u<K, S, SC, T, PRO, LDSC>(up + sz, inb && z + 1 < g.nz, x, y, z + 1, ec, gc, dw,
+                                   (int64_t)(z + 1) * plane + icol, c, un, lc);
+      ld_u<K, S, SC, T, PRO, LDSC>(rpp, rin, rx, ry, z, ec, gc, dw, (int64_t)z * plane + rcol, c, rc, lc);
+      // the coarse plane the next step adds (the upper parent of z + 2) goes
+      // to the slot no plane of this step uses; the barrier below orders it
+      if (LDSC && (z & 1) == 0) load_stage((z + 2) / 2);
     }
+    if (LDSC && (z & 1) == 0) put_stage();
     if (ring) {
 #pragma unroll
       for (int k = 0; k < K; ++k) sm[ro + k] = cx<LE>{(LE)rc[k].re, (LE)rc[k].im};
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) sm[me + k] = cx<LE>{(LE)uc[k].re, (LE)uc[k].im};
+    for (int k = 0; k < K; ++k) nb[RYS + k] = cx<LE>{(LE)uc[k].re, (LE)uc[k].im};
     __syncthreads();
     if (inb) {
       const int64_t ir = (int64_t)z * plane + icol;
@@ -652,15 +764,17 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         acc[k] = d * uc[k];
-        sum[k] = ihz * (um[k] + un[k]) + ihy * (wid<T>(sm[me - RYS + k]) + wid<T>(sm[me + RYS + k]));
-        sum[k] = sum[k] + ihx * wid<T>(sm[me - RX + k]);
-        sum[k] = sum[k] + ihx * wid<T>(sm[me + RX + k]);
+        sum[k] = ihz * (um[k] + un[k]) + ihy * (wid<T>(nb[k]) + wid<T>(nb[2 * RYS + k]));
+        sum[k] = sum[k] + ihx * wid<T>(nb[RYS - RX + k]);
+        sum[k] = sum[k] + ihx * wid<T>(nb[RYS + RX + k]);
         acc[k] = acc[k] - sum[k];
       }
       const int64_t o = ir * g.P + c;
       if (MODE == 0) {
         stK<K, S, T>(out + o, acc);
       } else {
+        // f after the barrier (issuing it with the u loads was measured
+        // slower: it lengthens the wait before the LDS stores)
         if (!PF) ldK<K, S, T>(f + o, fc);
         cx<T> res[K];
         if (MODE == 1) {
@@ -1038,17 +1152,32 @@ static thread_local FineTile g_tile = {4, 32};
 void set_fine_tile(FineTile t) { g_tile = t; }
 FineTile get_fine_tile() { return g_tile; }
 
-bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& gc, const void* ec, const void* u,
-                          const void* f, void* out, const void* dg, const void* dw, const double ih[3],
-                          hipStream_t s) {
-  // with the LDS-blocked tiles only (the register-blocked family keeps the
-  // separate prolongation, and the tile-identity test compares the two)
+// The fused finest-level kernels run with the LDS-blocked tiles only (the
+// register-blocked family keeps the separate kernels, and the tile-identity
+// test compares the two), unless HELM_FUSE=0.
+static bool fused_tiles() {
   if (g_tile.ry != 8 && g_tile.ry != 16) return false;
   static const bool off = [] {
     const char* e = std::getenv("HELM_FUSE");
     return e && std::strcmp(e, "0") == 0;
   }();
-  if (off) return false;
+  return !off;
+}
+
+bool can_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf) {
+  return fused_tiles() && ((pf == P32 && pc == PBF && pt == P32 && gf.P % 16 == 0) ||
+                           (pf == P64 && pc == P64 && pt == P64 && gf.P % 8 == 0));
+}
+
+bool can_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf) {
+  return fused_tiles() && ((pf == P32 && (pc == PBF || pc == P32) && pt == P32 && gf.P % 8 == 0) ||
+                           (pf == P64 && pc == P64 && pt == P64 && gf.P % 4 == 0));
+}
+
+bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& gc, const void* ec, const void* u,
+                          const void* f, void* out, const void* dg, const void* dw, const double ih[3],
+                          hipStream_t s) {
+  if (!can_prolong_sweep(pc, pf, pt, gf)) return false;
   const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
   if (pf == P32 && pc == PBF && pt == P32 && gf.P % 16 == 0) {
     if (g_tile.ry == 16)
@@ -1067,16 +1196,31 @@ bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& g
   return false;
 }
 
+bool can_sweep01(Prec pf, Prec pt, const Geo& g) {
+  return fused_tiles() && ((pf == P32 && pt == P32 && g.P % 16 == 0) || (pf == P64 && pt == P64 && g.P % 8 == 0));
+}
+
+void launch_sweep01(Prec pf, Prec pt, const Geo& g, const void* f, void* out, const void* dg, const void* dw,
+                    const double ih[3], hipStream_t s) {
+  if (!can_sweep01(pf, pt, g)) fatal_combo("launch_sweep01");
+  const int zc = g_tile.zc > 0 ? g_tile.zc : 32;
+  // the zero-guess sweep's output is formed on the fly from f (PRO = 2)
+  if (pf == P32) {
+    if (g_tile.ry == 16)
+      fine_t16_launch<c64, float, 2, 16, c64, 2>(g, f, f, out, dg, dw, ih, zc, s);
+    else
+      fine_t16_launch<c64, float, 2, 8, c64, 2>(g, f, f, out, dg, dw, ih, zc, s);
+  } else {
+    if (g_tile.ry == 16)
+      fine_t16_launch<c128, double, 2, 16, c128, 2>(g, f, f, out, dg, dw, ih, zc, s);
+    else
+      fine_t16_launch<c128, double, 2, 8, c128, 2>(g, f, f, out, dg, dw, ih, zc, s);
+  }
+}
+
 bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* u, const void* f,
                            void* rc, const void* dg, const double ih[3], hipStream_t s) {
-  // with the LDS-blocked tiles only, so that the register-blocked tiles keep
-  // the two-kernel path and the tile-identity test compares the two
-  if (g_tile.ry != 8 && g_tile.ry != 16) return false;
-  static const bool off = [] {
-    const char* e = std::getenv("HELM_FUSE");
-    return e && std::strcmp(e, "0") == 0;
-  }();
-  if (off) return false;
+  if (!can_resid_restrict(pf, pc, pt, gf)) return false;
   if (pf == P32 && pc == PBF && pt == P32 && gf.P % 8 == 0) {
     resid_restrict_launch<c64, cbf, float>(gf, gc, u, f, rc, dg, ih, s);
     return true;

@@ -28,14 +28,22 @@ void set_fine_tile(FineTile t);
 // Fused 3D finest-level residual f - M u and full-weighting restriction into
 // the coarse field rc (bitwise equal to the two separate kernels). Runs and
 // returns true only for the LDS-blocked tiles and supported precisions.
+bool can_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf);
 bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* u, const void* f,
                            void* rc, const void* dg, const double ih[3], hipStream_t s);
 // First post-smoothing sweep of the 3D finest level with the coarse-grid
 // correction fused in: out = JAC(u + P ec) (bitwise the prolongation followed
 // by the sweep). Runs and returns true only for the LDS-blocked tiles.
+bool can_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf);
 bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& gc, const void* ec, const void* u,
                           const void* f, void* out, const void* dg, const void* dw, const double ih[3],
                           hipStream_t s);
+// The first two damped-Jacobi sweeps of the 3D finest level in one pass:
+// out = JAC(w D^-1 f), bitwise the zero-guess sweep followed by a sweep.
+// Available (can_sweep01) for the LDS-blocked tiles and FP32 / FP64 fields.
+bool can_sweep01(Prec pf, Prec pt, const Geo& g);
+void launch_sweep01(Prec pf, Prec pt, const Geo& g, const void* f, void* out, const void* dg, const void* dw,
+                    const double ih[3], hipStream_t s);
 FineTile get_fine_tile();
 // mode: 0 apply (out = A u), 1 residual (out = f - A u),
 //       2 Jacobi (out = u + dw (f - A u)), 3 zero-guess Jacobi (out = dw f).

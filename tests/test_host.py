@@ -159,3 +159,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_classes_follow_the_header():
+    """The binding's kernel-class names cover the header's HELM_K_* enum, in order."""
+    import paper_1607_00968_amd as pk
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"enum\s*\{\s*(HELM_K_FINE_SWEEP\s*=\s*0[^}]*)\}", text)
+    assert m
+    names = [t.strip().split("=")[0].strip() for t in m.group(1).split(",") if t.strip()]
+    assert names[-1] == "HELM_K_NCLASS"
+    assert [n[len("HELM_K_"):].lower() for n in names[:-1]] == list(pk.KERNEL_CLASSES)
