@@ -264,3 +264,65 @@ def test_learned_unmutated_copy_passes(tmp_path):
     finally:
         lpins.ol = saved
         sys.modules.pop("oracle.learned_copy", None)
+
+
+# Planted mistakes in the oracle's block BiCGSTAB (oracle/bicgstab.py).
+import test_oracle_bicgstab as bpins  # noqa: E402
+
+BICG_MUTANTS = [
+    ("beta with the wrong sign", "beta = -np.linalg.solve(A, Rt.conj() @ T.T)", "beta = np.linalg.solve(A, Rt.conj() @ T.T)",
+     [lambda: bpins.test_single_rhs_unpreconditioned_matches_scipy(0.1, (4, 8, 12), 1e-10)]),
+    ("update without omega", "X = X + alpha.T @ Phat + omega * Shat", "X = X + alpha.T @ Phat + Shat",
+     [lambda: bpins.test_single_rhs_unpreconditioned_matches_scipy(0.1, (4, 8, 12), 1e-10)]),
+    ("shadow inner product without conjugate", "A = Rt.conj() @ V.T", "A = Rt @ V.T",
+     [lambda: bpins.test_single_rhs_unpreconditioned_matches_scipy(0.1, (4, 8, 12), 1e-10)]),
+    ("direction update keeps V", "P = R + beta.T @ (P - omega * V)", "P = R + beta.T @ P",
+     [lambda: bpins.test_single_rhs_unpreconditioned_matches_scipy(0.1, (4, 8, 12), 1e-10)]),
+]
+
+
+def _load_module_copy(tmp_path, fname, text, modname):
+    path = tmp_path / (modname + ".py")
+    path.write_text(text)
+    spec = importlib.util.spec_from_file_location("oracle." + modname, str(path))
+    mod = importlib.util.module_from_spec(spec)
+    mod.__package__ = "oracle"
+    sys.modules["oracle." + modname] = mod
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name,old,new,checks", BICG_MUTANTS, ids=[m[0] for m in BICG_MUTANTS])
+def test_bicgstab_pins_catch_planted_mistake(tmp_path, name, old, new, checks):
+    with open(os.path.join(SRC, "bicgstab.py")) as fh:
+        text = fh.read()
+    changed = plant(text, old, new, 0)
+    assert changed != text
+    mod = _load_module_copy(tmp_path, "bicgstab.py", changed, "bicgstab_mutant")
+    saved = bpins.ob
+    bpins.ob = mod
+    caught = []
+    try:
+        for check in checks:
+            try:
+                check()
+            except AssertionError as e:
+                caught.append(str(e)[:80])
+    finally:
+        bpins.ob = saved
+        sys.modules.pop("oracle.bicgstab_mutant", None)
+    assert caught, f"no pin caught the planted mistake: {name}"
+
+
+def test_bicgstab_unmutated_copy_passes(tmp_path):
+    with open(os.path.join(SRC, "bicgstab.py")) as fh:
+        mod = _load_module_copy(tmp_path, "bicgstab.py", fh.read(), "bicgstab_copy")
+    saved = bpins.ob
+    bpins.ob = mod
+    try:
+        for m in BICG_MUTANTS:
+            for check in m[3]:
+                check()
+    finally:
+        bpins.ob = saved
+        sys.modules.pop("oracle.bicgstab_copy", None)
