@@ -53,7 +53,8 @@ typedef enum {
   HELM_ERR_OOM = 2,           /* device allocation failed                   */
   HELM_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed */
   HELM_ERR_NOT_CONVERGED = 4, /* U holds the last iterate, info is filled   */
-  HELM_ERR_BREAKDOWN = 5,     /* rank-deficient block that could not be handled */
+  HELM_ERR_BREAKDOWN = 5,     /* rank-deficient block, or a Krylov breakdown or divergence
+                                 that could not be handled (U holds the last good iterate) */
   HELM_ERR_NONFINITE = 6,     /* NaN/Inf in m, gamma or Q                    */
   HELM_ERR_UNSUPPORTED = 7    /* valid request the library does not support */
 } helm_status;
@@ -131,10 +132,23 @@ typedef struct {
                           i.e. the solve would need more than twice the calibrated
                           cycles, the coarsest solves switch to the GMRES fallback for
                           the rest of the solve (info.rate_switch). */
+  int32_t method;      /* HELM_METHOD_FGMRES (0): block FGMRES(restart). HELM_METHOD_BICGSTAB (1):
+                          block BiCGSTAB (the paper's W-BiCG with cycle = HELM_CYCLE_W; El
+                          Guennouni, Jbilou and Sadok's block version), two cycles per
+                          iteration, groups of block_size columns; restart and reorth are
+                          ignored. BiCGSTAB is not flexible: its theory needs a linear cycle
+                          (LU or relaxation-only coarsest solve); with the GMRES or learned
+                          coarsest solve it runs with a fixed but nonlinear cycle, and the
+                          FP64 true residual, checked whenever the recursive one meets tol
+                          (then restarting from the current iterate if needed), keeps the
+                          result honest either way. */
 } helm_solve_opts;
 
+enum { HELM_METHOD_FGMRES = 0, HELM_METHOD_BICGSTAB = 1 };
+
 typedef struct {
-  int32_t cycles;       /* Arnoldi steps = preconditioner applications (the paper's #Cyc) */
+  int32_t cycles;       /* preconditioner applications (the paper's #Cyc): Arnoldi steps of
+                           FGMRES, two per BiCGSTAB iteration */
   int32_t restarts;
   int32_t converged_all;
   int32_t fallback_used;/* coarsest solves where the learned correction was not finite

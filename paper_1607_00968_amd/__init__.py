@@ -72,7 +72,7 @@ class SetupDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_cycles", C.c_int32), ("block_size", C.c_int32),
                 ("warm_start", C.c_int32), ("reorth", C.c_int32), ("graph", C.c_int32),
-                ("learned_rate", C.c_double)]
+                ("learned_rate", C.c_double), ("method", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -235,22 +235,26 @@ def _form(graph) -> int:
     return 2 if graph == "persistent" else int(graph)
 
 
+METHOD = {"fgmres": 0, "bicgstab": 1}
+
+
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
                      warm_start=False, reorth=True, workspace=None, stream=None, graph=False,
-                     learned_rate=0.0) -> dict:
+                     learned_rate=0.0, method="fgmres") -> dict:
     """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ...
     reorth: 0 one Gram-Schmidt pass, 1 (True, the default here) always two,
     2 a second pass only where the norm fell below half (the C default when
     no options are passed). graph: False/0 eager, True/1 HIP graphs,
     "persistent"/2 the persistent cycle kernel. learned_rate: the plain
     cycle's calibrated per-cycle reduction factor for the learned coarsest
-    correction's rate check (0 = off)."""
+    correction's rate check (0 = off). method: "fgmres" (block FGMRES(restart))
+    or "bicgstab" (block BiCGSTAB, two cycles per iteration)."""
     nrhs = Q.shape[0]
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
         raise ValueError("Q and U must both be [nrhs, N]")
     o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), _form(graph),
-                  float(learned_rate))
+                  float(learned_rate), METHOD[method])
     rel = np.zeros(nrhs)
     conv = np.zeros(nrhs, np.int32)
     info = SolveInfo()
@@ -267,7 +271,7 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
 
 
 def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, block_size=1, reorth=0,
-                     graph=False, max_threads=16, stream=None, learned_rate=0.0) -> list:
+                     graph=False, max_threads=16, stream=None, learned_rate=0.0, method="fgmres") -> list:
     """Solve independent instances concurrently (one stream and one host
     thread of a pool per instance). Returns one dict per instance, as
     helm_solve_block does, plus "status"."""
@@ -283,7 +287,7 @@ def helm_solve_batch(handles, Qs, Us, tol=1e-6, restart=5, max_cycles=1000, bloc
             raise ValueError("Q and U must both be [nrhs, N] of their instance")
     qp = (C.c_void_p * k)(*[q.data_ptr() for q in Qs])
     up = (C.c_void_p * k)(*[u.data_ptr() for u in Us])
-    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), _form(graph), float(learned_rate))
+    o = SolveOpts(restart, max_cycles, block_size, 0, int(reorth), _form(graph), float(learned_rate), METHOD[method])
     infos = (SolveInfo * k)()
     rel = [np.zeros(int(q.shape[0])) for q in Qs]
     conv = [np.zeros(int(q.shape[0]), np.int32) for q in Qs]

@@ -1205,11 +1205,55 @@ static WsLayout ws_layout(const helm_ctx* c, int P, int m, int pb) {
   return w;
 }
 
+// Block BiCGSTAB workspace: the FP64 blocks Q, X (and its copy at the last
+// restart), R, the shadow Rt, the
+// directions P (and its successor), V = H M P, S, T = H M S; the cycle
+// outputs M P and M S in the cycle's precision; Gram and coefficient blocks.
+struct BiWs {
+  size_t Qi, X, Xr, R, Rt, Pp, Pn, V, S, T, Ph, Sh, part, G1, G2, G3, Al, Be, Cl, q2, r2, tn2, om, flag, act, end;
+};
+
+static BiWs bicg_layout(const helm_ctx* c, int P, int pb) {
+  const int64_t N = c->lv[0].npts;
+  const size_t blk = 16 * (size_t)N * P;
+  const size_t zblk = (c->precision == HELM_FP64 ? 16 : 8) * (size_t)N * P;
+  const int ng = (P + pb - 1) / pb;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  BiWs w{};
+  size_t o = 0;
+  size_t* big[10] = {&w.Qi, &w.X, &w.Xr, &w.R, &w.Rt, &w.Pp, &w.Pn, &w.V, &w.S, &w.T};
+  for (size_t* f : big) {
+    *f = o;
+    o += al(blk);
+  }
+  w.Ph = o; o += al(zblk);
+  w.Sh = o; o += al(zblk);
+  w.part = o; o += al(16 * gram_part_elems(P));
+  const size_t gm = al(16 * (size_t)P * pb);
+  w.G1 = o; o += gm;
+  w.G2 = o; o += gm;
+  w.G3 = o; o += gm;
+  w.Al = o; o += gm;
+  w.Be = o; o += gm;
+  w.Cl = o; o += 3 * gm;
+  w.q2 = o; o += al(8 * (size_t)P);
+  w.r2 = o; o += al(8 * (size_t)P);
+  w.tn2 = o; o += al(8 * (size_t)P);
+  w.om = o; o += al(16 * (size_t)ng);
+  w.flag = o; o += al(4 * (size_t)ng);
+  w.act = o; o += al(4 * (size_t)ng);
+  w.end = o;
+  return w;
+}
+
 helm_status helm_workspace_size(helm_handle h, int32_t nrhs, int32_t restart, size_t* bytes) {
   if (!h || !bytes || nrhs < 1 || nrhs > 256 || restart < 1 || restart >= MAXPTR)
     return fail(HELM_ERR_INVALID_ARG, "bad workspace query");
   const int P = padP(nrhs);
-  *bytes = ws_layout(h, P, restart, 1).end + ws_layout(h, P, restart, P).end;
+  // enough for either method at any block size
+  const size_t fg = std::max(ws_layout(h, P, restart, 1).end, ws_layout(h, P, restart, P).end);
+  const size_t bi = std::max(bicg_layout(h, P, 1).end, bicg_layout(h, P, std::min(P, 32)).end);
+  *bytes = std::max(fg, bi);
   return HELM_OK;
 }
 
@@ -1252,6 +1296,296 @@ __global__ void k_zero_inactive(int ng, int pb, int P, int k, const int* __restr
   if (!act[c / pb]) C[t] = c128{0.0, 0.0};
 }
 
+// ---------------------------------------------------------------------------
+// Block BiCGSTAB (El Guennouni, Jbilou and Sadok; the paper's W-BiCG of
+// section 5.3) right-preconditioned by the multigrid cycle, per group of pb
+// columns, all outer quantities in FP64:
+//   R = Q - H X, Rt = R, P = R; per iteration
+//   V = H M P, alpha = (Rt^H V)^-1 Rt^H R, S = R - V alpha,
+//   T = H M S, omega = tr(T^H S) / tr(T^H T),
+//   X += M P alpha + omega M S, R = S - omega T,
+//   beta = -(Rt^H V)^-1 Rt^H T, P = R + (P - omega V) beta.
+// When every active column's recursive residual meets tol (or a group's
+// Rt^H V is singular), the FP64 true residual decides: stop, or restart from
+// the current X. Converged groups get alpha = beta = omega = 0 and keep
+// their columns. One host synchronisation per iteration.
+// ---------------------------------------------------------------------------
+static helm_status bicgstab_solve(helm_ctx* c, int nrhs, const void* Q, void* U, double tol, const helm_solve_opts& o,
+                                  int pb, void* workspace, size_t ws_bytes, helm_solve_info* info, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int P = padP(nrhs);
+  const int Pa = nrhs;
+  const int ng = Pa / pb;
+  const int64_t N = c->lv[0].npts;
+  const Level& L0 = c->lv[0];
+  const Prec pz = c->precision == HELM_FP64 ? P64 : P32;
+  helm_status st;
+  if ((st = ensure_fields(c, P)) != HELM_OK) return st;
+  if ((st = autotune_fine(c, P, s)) != HELM_OK) return st;
+  set_fine_tile(c->tile);
+  const int64_t fallbacks0 = c->fallbacks;
+  const int graph = (c->prof || c->cap) ? 0 : o.graph;
+  const BiWs w = bicg_layout(c, P, pb);
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    if (c->wsbytes < w.end) {
+      clear_graphs(c);
+      hipFree(c->ws);
+      c->ws = nullptr;
+      c->wsbytes = 0;
+      HCHECK(hipMalloc(&c->ws, w.end));
+      c->wsbytes = w.end;
+    }
+    base = static_cast<char*>(c->ws);
+  } else if (ws_bytes < w.end) {
+    return fail(HELM_ERR_INVALID_ARG, "workspace too small (%zu < %zu)", ws_bytes, w.end);
+  }
+  if (c->hbufn < (size_t)4 * P) {
+    if (c->hbuf) hipHostFree(c->hbuf);
+    HCHECK(hipHostMalloc(&c->hbuf, sizeof(double) * 4 * P));
+    c->hbufn = 4 * P;
+  }
+  double* hq = c->hbuf;
+  double* hr = c->hbuf + P;
+  int* hflag = reinterpret_cast<int*>(c->hbuf + 2 * P);
+  c128* Qi = (c128*)(base + w.Qi);
+  c128* X = (c128*)(base + w.X);
+  c128* Xr = (c128*)(base + w.Xr);
+  c128* R = (c128*)(base + w.R);
+  c128* Rt = (c128*)(base + w.Rt);
+  c128* Pd = (c128*)(base + w.Pp);
+  c128* Pn = (c128*)(base + w.Pn);
+  c128* V = (c128*)(base + w.V);
+  c128* S = (c128*)(base + w.S);
+  c128* T = (c128*)(base + w.T);
+  void* Ph = base + w.Ph;
+  void* Sh = base + w.Sh;
+  c128* part = (c128*)(base + w.part);
+  c128* G1 = (c128*)(base + w.G1);
+  c128* G2 = (c128*)(base + w.G2);
+  c128* G3 = (c128*)(base + w.G3);
+  c128* Al = (c128*)(base + w.Al);
+  c128* Be = (c128*)(base + w.Be);
+  c128* Cl = (c128*)(base + w.Cl);
+  double* dq = (double*)(base + w.q2);
+  double* dr = (double*)(base + w.r2);
+  double* dtn = (double*)(base + w.tn2);
+  c128* dom = (c128*)(base + w.om);
+  int* dflag = (int*)(base + w.flag);
+  int* dact = (int*)(base + w.act);
+  const size_t blk = 16 * (size_t)N * P;
+  const Geo g0 = L0.geo(P);
+  const double tol2 = tol * tol;
+  const Level& Lz = c->lv[0];
+
+  hipEvent_t e0, e1;
+  HCHECK(hipEventCreate(&e0));
+  HCHECK(hipEventCreate(&e1));
+  auto cleanup = [&]() {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  };
+  HCHECK(hipEventRecord(e0, s));
+  launch_to_internal(P64, N, nrhs, P, Q, Qi, s);
+  if (o.warm_start)
+    launch_to_internal(P64, N, nrhs, P, U, X, s);
+  else
+    HCHECK(hipMemsetAsync(X, 0, blk, s));
+  { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, Qi, part, G1, dq, s); }
+  HCHECK(hipMemcpyAsync(hq, dq, 8 * Pa, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  for (int cidx = 0; cidx < Pa; ++cidx)
+    if (!std::isfinite(hq[cidx])) {
+      cleanup();
+      return fail(HELM_ERR_NONFINITE, "non-finite right-hand side column %d", cidx);
+    }
+  // the cycle M applied to a c128 block: FP64 directly, mixed through the
+  // FP32 input field of the finest level
+  auto precond = [&](const c128* in, void* out) -> helm_status {
+    if (pz == P64) return run_cycle(c, P, in, out, Lz.U1, graph, s);
+    launch_convert(P64, P32, N * P, in, Lz.F, s);
+    return run_cycle(c, P, Lz.F, out, Lz.U1, graph, s);
+  };
+  auto apply_H = [&](const void* in, c128* out) {
+    Prof pr(c, HELM_K_OUTER_APPLY, s);
+    launch_fine(0, pz, P64, P64, P64, c->dim, g0, in, nullptr, out, L0.dH, nullptr, L0.ih, s);
+  };
+  int cycles = 0, restarts = 0;
+  bool converged = false;
+  std::vector<double> relres(Pa, 0.0);
+  for (;;) {
+    // true FP64 residual R = Q - H X and the stopping test
+    launch_fine(1, P64, P64, P64, P64, c->dim, g0, X, Qi, R, L0.dH, nullptr, L0.ih, s);
+    { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, R, part, G1, dr, s); }
+    HCHECK(hipMemcpyAsync(hr, dr, 8 * Pa, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    HCHECK(hipGetLastError());
+    bool all = true;
+    for (int cidx = 0; cidx < Pa; ++cidx) {
+      relres[cidx] = hq[cidx] > 0 ? std::sqrt(hr[cidx] / hq[cidx]) : 0.0;
+      if (!std::isfinite(relres[cidx])) {
+        cleanup();
+        return fail(HELM_ERR_NONFINITE, "non-finite residual in column %d", cidx);
+      }
+      if (relres[cidx] > tol) all = false;
+    }
+    if (all) {
+      converged = true;
+      break;
+    }
+    if (cycles >= o.max_cycles) break;
+    restarts += cycles > 0;
+    hipLaunchKernelGGL(k_set_active, dim3((ng + 255) / 256), dim3(256), 0, s, ng, pb, tol2, dr, dq, dact);
+    HCHECK(hipMemcpyAsync(Rt, R, blk, hipMemcpyDeviceToDevice, s));
+    HCHECK(hipMemcpyAsync(Pd, R, blk, hipMemcpyDeviceToDevice, s));
+    HCHECK(hipMemcpyAsync(Xr, X, blk, hipMemcpyDeviceToDevice, s));
+    std::vector<double> r2start(hr, hr + Pa);
+    bool diverged = false;
+    PtrList rt{};
+    rt.p[0] = Rt;
+    bool stalled = true;  // no iteration completed since this restart
+    while (cycles < o.max_cycles) {
+      // V = H M P, alpha = (Rt^H V)^-1 Rt^H R
+      if ((st = precond(Pd, Ph)) != HELM_OK) {
+        cleanup();
+        return st;
+      }
+      ++cycles;
+      apply_H(Ph, V);
+      {
+        Prof pr_(c, HELM_K_GRAM, s);
+        launch_gram(P64, N, P, Pa, pb, 1, rt, V, part, G1, s);
+        launch_gram(P64, N, P, Pa, pb, 1, rt, R, part, G2, s);
+      }
+      launch_bicg_solve(ng, pb, 1.0, G1, G2, Al, dact, dflag, s);
+      // S = R - V alpha
+      launch_bicg_coefs(0, Pa, pb, Al, dom, Cl, s);
+      {
+        Prof pr_(c, HELM_K_UPDATE, s);
+        PtrList vr{};
+        vr.p[0] = V;
+        vr.p[1] = R;
+        launch_block_update(1, P64, P64, N, P, Pa, pb, 2, vr, Cl, S, s);
+      }
+      // T = H M S, omega = tr(T^H S) / tr(T^H T)
+      if ((st = precond(S, Sh)) != HELM_OK) {
+        cleanup();
+        return st;
+      }
+      ++cycles;
+      apply_H(Sh, T);
+      {
+        Prof pr_(c, HELM_K_GRAM, s);
+        PtrList tl{};
+        tl.p[0] = T;
+        launch_gram(P64, N, P, Pa, pb, 1, tl, S, part, G3, s);
+        launch_colnorm2(P64, N, P, Pa, T, part, G2, dtn, s);
+      }
+      launch_bicg_omega(ng, pb, G3, dtn, dact, dom, s);
+      {
+        Prof pr_(c, HELM_K_UPDATE, s);
+        // X += M P alpha + omega M S
+        launch_bicg_coefs(1, Pa, pb, Al, dom, Cl, s);
+        PtrList ps{};
+        ps.p[0] = Ph;
+        ps.p[1] = Sh;
+        launch_block_update(2, pz, P64, N, P, Pa, pb, 2, ps, Cl, X, s);
+        // R = S - omega T
+        launch_bicg_coefs(2, Pa, pb, nullptr, dom, Cl, s);
+        PtrList st2{};
+        st2.p[0] = S;
+        st2.p[1] = T;
+        launch_block_update(1, P64, P64, N, P, Pa, pb, 2, st2, Cl, R, s);
+      }
+      { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, R, part, G2, dr, s); }
+      HCHECK(hipMemcpyAsync(hr, dr, 8 * Pa, hipMemcpyDeviceToHost, s));
+      HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      HCHECK(hipGetLastError());
+      bool brk = false;
+      for (int gg = 0; gg < ng; ++gg) brk = brk || hflag[gg];
+      if (brk) break;  // singular Rt^H V: this step did nothing for that group; restart
+      // divergence (a non-finite or exploding recursive residual, e.g. with
+      // a cycle that is not linear enough): back to the restart's iterate
+      for (int cidx = 0; cidx < Pa; ++cidx)
+        if (!std::isfinite(hr[cidx]) || hr[cidx] > 1e16 * std::max(r2start[cidx], 1e-300)) diverged = true;
+      if (diverged) break;
+      stalled = false;
+      bool conv = true;
+      for (int cidx = 0; cidx < Pa; ++cidx)
+        if (hq[cidx] > 0 && hr[cidx] > tol2 * hq[cidx]) conv = false;
+      if (conv) break;
+      // beta = -(Rt^H V)^-1 Rt^H T, P = R + (P - omega V) beta
+      { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, rt, T, part, G2, s); }
+      launch_bicg_solve(ng, pb, -1.0, G1, G2, Be, dact, dflag, s);
+      launch_bicg_coefs(3, Pa, pb, Be, dom, Cl, s);
+      {
+        Prof pr_(c, HELM_K_UPDATE, s);
+        PtrList rpv{};
+        rpv.p[0] = R;
+        rpv.p[1] = Pd;
+        rpv.p[2] = V;
+        launch_block_update(1, P64, P64, N, P, Pa, pb, 3, rpv, Cl, Pn, s);
+      }
+      std::swap(Pd, Pn);
+    }
+    if (diverged) {
+      HCHECK(hipMemcpyAsync(X, Xr, blk, hipMemcpyDeviceToDevice, s));
+      launch_to_abi(P64, N, nrhs, P, X, U, s);
+      HCHECK(hipStreamSynchronize(s));
+      cleanup();
+      if (info) {
+        info->cycles = cycles;
+        info->restarts = restarts;
+        info->converged_all = 0;
+        info->fallback_used = (int32_t)(c->fallbacks - fallbacks0);
+        info->t_solve_ms = 0.0;
+        info->rate_switch = -1;
+        for (int cidx = 0; cidx < nrhs; ++cidx) {
+          if (info->relres) info->relres[cidx] = relres[cidx];
+          if (info->converged) info->converged[cidx] = relres[cidx] <= tol;
+        }
+      }
+      return fail(HELM_ERR_BREAKDOWN,
+                  "block BiCGSTAB diverged after %d cycles (U holds the iterate of the last restart); BiCGSTAB "
+                  "needs a linear cycle: use FP64 or FGMRES", cycles);
+    }
+    if (stalled) {
+      // a breakdown in the first step after a (re)start cannot be cured by
+      // restarting again (the flags were read with that step's residuals)
+      bool any = false;
+      for (int gg = 0; gg < ng; ++gg) any = any || hflag[gg];
+      if (any) {
+        cleanup();
+        return fail(HELM_ERR_BREAKDOWN,
+                    "block BiCGSTAB breakdown (singular shadow product) in a fresh start; dependent right-hand "
+                    "sides in a group? use block_size 1");
+      }
+    }
+  }
+  launch_to_abi(P64, N, nrhs, P, X, U, s);
+  HCHECK(hipEventRecord(e1, s));
+  HCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  cleanup();
+  HCHECK(hipGetLastError());
+  if (info) {
+    info->cycles = cycles;
+    info->restarts = restarts;
+    info->converged_all = converged ? 1 : 0;
+    info->fallback_used = (int32_t)(c->fallbacks - fallbacks0);
+    info->t_solve_ms = ms;
+    info->rate_switch = -1;
+    for (int cidx = 0; cidx < nrhs; ++cidx) {
+      if (info->relres) info->relres[cidx] = relres[cidx];
+      if (info->converged) info->converged[cidx] = relres[cidx] <= tol;
+    }
+  }
+  if (!converged) return fail(HELM_ERR_NOT_CONVERGED, "not converged after %d cycles", cycles);
+  return HELM_OK;
+}
+
 helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U, double tol,
                              const helm_solve_opts* opts, void* workspace, size_t ws_bytes, helm_solve_info* info,
                              void* stream) {
@@ -1269,6 +1603,9 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if (o.max_cycles < 1) return fail(HELM_ERR_INVALID_ARG, "max_cycles must be >= 1");
   if (o.reorth < 0 || o.reorth > 2) return fail(HELM_ERR_INVALID_ARG, "reorth must be 0, 1 or 2");
   if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");
+  if (o.method != HELM_METHOD_FGMRES && o.method != HELM_METHOD_BICGSTAB)
+    return fail(HELM_ERR_INVALID_ARG, "method must be HELM_METHOD_FGMRES or HELM_METHOD_BICGSTAB");
+  if (o.method == HELM_METHOD_BICGSTAB) return bicgstab_solve(h, nrhs, Q, U, tol, o, pb, workspace, ws_bytes, info, stream);
   hipStream_t s = static_cast<hipStream_t>(stream);
   helm_ctx* c = h;
   const int P = padP(nrhs);

@@ -148,6 +148,16 @@ void launch_lazy_next(int P, int j, const double* n2, const double* ref2, double
                       int64_t hstride, int* flag, hipStream_t s);
 void launch_lazy_start(int P, const double* r2, double* nu, c128* S, int* flag, hipStream_t s);
 void launch_lazy_y(int P, int k, const double* nu, c128* Y, hipStream_t s);
+// ---- k_bicg.hip -------------------------------------------------------------
+// Block BiCGSTAB per group of pb columns (matrices in the Gram layout):
+// X_g = sgn A_g^-1 B_g (zero for an inactive group or, flag[g] = 1, a
+// singular A_g); omega_g = trace(T^H S) / trace(T^H T); coefficient lists
+// (kind 0..3, see k_bicg.hip) for launch_block_update.
+void launch_bicg_solve(int ng, int pb, double sgn, const c128* A, const c128* B, c128* X, const int* act, int* flag,
+                       hipStream_t s);
+void launch_bicg_omega(int ng, int pb, const c128* Gts, const double* tn2, const int* act, c128* om, hipStream_t s);
+void launch_bicg_coefs(int kind, int P, int pb, const c128* M, const c128* om, c128* C, hipStream_t s);
+
 // Fixed-step per-column GMRES helpers for the coarsest grid.
 void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s);
 void launch_inv_sqrt(int P, const double* b2, double* sc, hipStream_t s);

@@ -135,3 +135,21 @@ def test_headline_fp64_comparison_solver_matches_oracle(oracle_solution):
                        precision="fp64", coarse="gmres", coarse_iters=20)
     U, info = solve(hd, 1e-8, TILE_LDS)
     check(U, info, 1e-8, oracle_solution)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_wbicg_3d_matches_oracle(oracle_solution, precision):
+    """The paper's W-BiCG solver (block BiCGSTAB, W-cycle with the exact
+    coarsest solve, a linear map) on the same 64^3 problem, block size 1:
+    residuals by the oracle's operator, sampled errors <= 1e-5 at 1e-8."""
+    hd = pk.helm_setup(PROB.dim, PROB.n, PROB.h, PROB.m, PROB.gamma, PROB.omega, shift=PROB.shift, levels=3,
+                       precision=precision, coarse="lu", cycle="W")
+    Q = torch.from_numpy(np.ascontiguousarray(PROB.Q)).cuda()
+    U = torch.zeros_like(Q)
+    pk.helm_set_fine_tile(hd, PROB.nrhs, *TILE_LDS)
+    info = pk.helm_solve_block(hd, Q, U, tol=1e-8, max_cycles=3000, block_size=1, method="bicgstab")
+    assert info["converged_all"], info
+    torch.cuda.synchronize()
+    print(precision, "W-BiCG cycles", info["cycles"], "restarts", info["restarts"])
+    check(U, info, 1e-8, oracle_solution)
