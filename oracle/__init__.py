@@ -73,6 +73,7 @@ def lib():
         L.orc_coarse_solve.argtypes = [P, C.c_int, P, P]
         L.orc_set_coarse_restarts.argtypes = [P, C.c_int]
         L.orc_set_cycle_w.argtypes = [P, C.c_int]
+        L.orc_set_cycle_k.argtypes = [P, C.c_int]
         L.orc_block_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_int), P, P]
         L.orc_householder_qr.argtypes = [C.c_int64, C.c_int, P, P]
@@ -209,10 +210,12 @@ class Hierarchy:
             raise RuntimeError("oracle setup failed")
         if coarse_restarts > 1:
             lib().orc_set_coarse_restarts(self.h, int(coarse_restarts))
-        if cycle not in ("V", "W"):
-            raise ValueError("cycle must be 'V' or 'W'")
+        if cycle not in ("V", "W", "K"):
+            raise ValueError("cycle must be 'V', 'W' or 'K'")
         if cycle == "W":
             lib().orc_set_cycle_w(self.h, 1)
+        if cycle == "K":
+            lib().orc_set_cycle_k(self.h, 1)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -355,6 +355,7 @@ struct orc_hier {
   int coarse_kind, coarse_iters;
   int coarse_restarts; /* GMRES cycles of coarse_iters steps (restarted GMRES); 0 or 1: one */
   int cycle_w;         /* 1: W-cycle (two coarse cycles where the coarse level is not the coarsest) */
+  int cycle_k;         /* 1: K-cycle (two flexible GMRES steps on such a coarse level) */
   og_grid g[8];
   ozc* st[8];   /* st[0] = shifted fine operator as a stencil */
   int nu_pre[8], nu_post[8];
@@ -473,6 +474,7 @@ static void coarse_gmres(const og_grid* g, const ozc* st, int k, const ozc* f, o
 
 void orc_set_coarse_restarts(orc_hier* H, int restarts) { H->coarse_restarts = restarts; }
 void orc_set_cycle_w(orc_hier* H, int w) { H->cycle_w = w; }
+void orc_set_cycle_k(orc_hier* H, int k) { H->cycle_k = k; }
 
 void orc_coarse_solve(const orc_hier* H, int nrhs, const ozc* f, ozc* u) {
   const int l = H->levels - 1;
@@ -536,6 +538,64 @@ static void level_jacobi(const orc_hier* H, int l, int nsweep, int nrhs, const o
   free(r);
 }
 
+static void vcycle_rec(const orc_hier* H, int l, int nrhs, const ozc* f, ozc* u);
+
+/* K-cycle coarse correction (Notay and Vassilevski's recursive Krylov
+ * cycle; the paper's K-FGMRES, section 5.3): the coarse problem M_l e = f is
+ * solved by two iterations of flexible GMRES from e = 0, each step
+ * preconditioned by the cycle of level l, one column at a time:
+ *   v1 = f / ||f||, z1 = B v1, w = M z1, h11 = v1^H w, w -= h11 v1,
+ *   h21 = ||w||, v2 = w / h21, z2 = B v2, w = M z2, h12 = v1^H w,
+ *   w -= h12 v1, h22 = v2^H w, w -= h22 v2, h32 = ||w||,
+ *   y = argmin || ||f|| e1 - H y ||, e = z1 y1 + z2 y2
+ * (a vanishing h21 ends after one step). */
+static void kcycle_coarse(const orc_hier* H, int l, int nrhs, const ozc* f, ozc* e) {
+  const int64_t n = og_npts(&H->g[l]);
+  ozc* v = (ozc*)malloc(sizeof(ozc) * n * 2);
+  ozc* z = (ozc*)malloc(sizeof(ozc) * n * 2);
+  ozc* w = (ozc*)malloc(sizeof(ozc) * n);
+  for (int s = 0; s < nrhs; ++s) {
+    const ozc* fs = f + (int64_t)s * n;
+    ozc* es = e + (int64_t)s * n;
+    memset(es, 0, sizeof(ozc) * n);
+    const double beta = vnorm(n, fs);
+    if (beta == 0.0) continue;
+    ozc Hm[6] = {0, 0, 0, 0, 0, 0}; /* column-major 3 x 2 */
+    for (int64_t i = 0; i < n; ++i) v[i] = fs[i] / beta;
+    int steps = 2;
+    for (int j = 0; j < 2; ++j) {
+      vcycle_rec(H, l, 1, v + (int64_t)j * n, z + (int64_t)j * n);
+      orc_apply_stencil(&H->g[l], H->st[l], 1, z + (int64_t)j * n, w);
+      for (int i = 0; i <= j; ++i) {
+        const ozc* vi = v + (int64_t)i * n;
+        ozc d = 0;
+        for (int64_t t = 0; t < n; ++t) d += conj(vi[t]) * w[t];
+        Hm[j * 3 + i] = d;
+        for (int64_t t = 0; t < n; ++t) w[t] -= d * vi[t];
+      }
+      const double hn = vnorm(n, w);
+      Hm[j * 3 + j + 1] = hn;
+      if (j == 0) {
+        if (hn == 0.0) {
+          steps = 1;
+          break;
+        }
+        for (int64_t t = 0; t < n; ++t) v[n + t] = w[t] / hn;
+      }
+    }
+    ozc A[6], B[3] = {beta, 0, 0}, y[2];
+    double res;
+    for (int c = 0; c < steps; ++c)
+      for (int r = 0; r <= steps; ++r) A[c * (steps + 1) + r] = Hm[c * 3 + r];
+    orc_lstsq(steps + 1, steps, 1, A, B, y, &res);
+    for (int c = 0; c < steps; ++c)
+      for (int64_t t = 0; t < n; ++t) es[t] += z[(int64_t)c * n + t] * y[c];
+  }
+  free(v);
+  free(z);
+  free(w);
+}
+
 static void vcycle_rec(const orc_hier* H, int l, int nrhs, const ozc* f, ozc* u) {
   const int64_t N = og_npts(&H->g[l]);
   if (l == H->levels - 1) {
@@ -551,7 +611,10 @@ static void vcycle_rec(const orc_hier* H, int l, int nrhs, const ozc* f, ozc* u)
   ozc* rc = (ozc*)malloc(sizeof(ozc) * Nc * nrhs);
   ozc* ec = (ozc*)malloc(sizeof(ozc) * Nc * nrhs);
   orc_restrict(&H->g[l], nrhs, r, rc);                     /*    r_c = R r */
-  vcycle_rec(H, l + 1, nrhs, rc, ec);                      /* 3. coarse problem */
+  if (H->cycle_k && l + 1 < H->levels - 1)
+    kcycle_coarse(H, l + 1, nrhs, rc, ec);                 /* 3. coarse problem: K-cycle */
+  else
+    vcycle_rec(H, l + 1, nrhs, rc, ec);                    /* 3. coarse problem */
   if (H->cycle_w && l + 1 < H->levels - 1) {
     /* W-cycle: the coarse problem gets a second cycle, on the residual the
      * first one left: e_c += B_c (r_c - M_c e_c). The coarsest level is

@@ -107,6 +107,10 @@ void orc_set_coarse_restarts(orc_hier* H, int restarts);
  * the coarsest gets two cycles, the second on the residual of the first
  * (e_c += B_c(r_c - M_c e_c)); the coarsest level is solved once. 0: V. */
 void orc_set_cycle_w(orc_hier* H, int w);
+/* 1: K-cycle (the paper's K-FGMRES): every coarse level but the coarsest is
+ * solved by two flexible GMRES steps from zero, each preconditioned by that
+ * level's cycle. 0: V. */
+void orc_set_cycle_k(orc_hier* H, int k);
 
 /* Block FGMRES(restart) for H X = Q with X0 = 0 (or X on entry if warm).
  * Right preconditioning by the V-cycle (or identity if H == NULL-prec flag).

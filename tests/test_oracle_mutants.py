@@ -118,6 +118,15 @@ MUTANTS = [
      [cnn.test_unet_gradient_central_differences]),
     ("loss gradient without its factor 2", "conv_oracle.c", "g_out[i * 2 + c] = 2.0 * (A.out", "g_out[i * 2 + c] = (A.out",
      0, [cnn.test_unet_gradient_central_differences]),
+    # K-cycle coarse correction
+    ("K-cycle combines the basis instead of the preconditioned vectors", "helm_oracle.c",
+     "for (int64_t t = 0; t < n; ++t) es[t] += z[(int64_t)c * n + t] * y[c];",
+     "for (int64_t t = 0; t < n; ++t) es[t] += v[(int64_t)c * n + t] * y[c];", 0,
+     [lambda: pins.test_kcycle_equals_dense_minimal_residual(2, 32, 3)]),
+    ("K-cycle second direction not normalised", "helm_oracle.c",
+     "for (int64_t t = 0; t < n; ++t) v[n + t] = w[t] / hn;",
+     "for (int64_t t = 0; t < n; ++t) v[n + t] = w[t];", 0,
+     [lambda: pins.test_kcycle_equals_dense_minimal_residual(2, 32, 3)]),
 ]
 
 

@@ -387,6 +387,59 @@ def test_wcycle_equals_dense_composition(dim, n, levels):
         assert np.linalg.norm(ref - v) > 1e-3 * np.linalg.norm(v)  # the W-cycle is another map
 
 
+def dense_kcycle(Ms, Ps, f, l, w, nu, coarse, dim):
+    """The cycle with the K-cycle coarse correction, densely: a coarse level
+    other than the coarsest is solved by the minimal residual over the
+    flexible Krylov space of two steps, span{z1, z2} with z1 = B v1,
+    v1 = r / ||r||, z2 = B v2 and v2 the part of M z1 orthogonal to v1
+    (normalised), B the level's own K-cycle: e = Z argmin ||r - M Z y||."""
+    if l == len(Ms) - 1:
+        return coarse(Ms[l], f)
+    M = Ms[l]
+    Dinv = 1.0 / np.diag(M)
+    u = np.zeros_like(f)
+    for _ in range(nu):
+        u = u + w * Dinv * (f - M @ u)
+    rc = Ps[l].T @ (f - M @ u) / 2 ** dim
+    if l + 1 < len(Ms) - 1:
+        Mc = Ms[l + 1]
+        B = lambda v: dense_kcycle(Ms, Ps, v, l + 1, w, nu, coarse, dim)
+        v1 = rc / np.linalg.norm(rc)
+        z1 = B(v1)
+        t = Mc @ z1
+        t = t - np.vdot(v1, t) * v1
+        z2 = B(t / np.linalg.norm(t))
+        Z = np.stack([z1, z2], axis=1)
+        y = np.linalg.lstsq(Mc @ Z, rc, rcond=None)[0]
+        e = Z @ y
+    else:
+        e = dense_kcycle(Ms, Ps, rc, l + 1, w, nu, coarse, dim)
+    u = u + Ps[l] @ e
+    for _ in range(nu):
+        u = u + w * Dinv * (f - M @ u)
+    return u
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 32, 3), (2, 32, 4), (3, 16, 3)])
+def test_kcycle_equals_dense_minimal_residual(dim, n, levels):
+    """The K-cycle (two flexible GMRES steps on every coarse level but the
+    coarsest) equals its definition as a minimal residual over the flexible
+    Krylov space, and differs from the V-cycle."""
+    m, gamma = rand_model(dim, n)
+    omega, beta = 10.0, 0.2
+    Ms, Ps = dense_hierarchy(dim, n, m, gamma, omega, beta, levels)
+    g = oracle.grid(dim, (n,) * dim, (1 / n,) * dim)
+    H = oracle.Hierarchy(g, m, gamma, omega, beta, levels, cycle="K")
+    F = crand(2, Ms[0].shape[0])
+    out = H.vcycle(F)
+    solve = lambda A, b: np.linalg.solve(A, b)
+    for s in range(2):
+        ref = dense_kcycle(Ms, Ps, F[s], 0, 0.8, 2, solve, dim)
+        assert np.allclose(out[s], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+        v = dense_vcycle(Ms, Ps, F[s], 0, 0.8, 2, solve, dim)
+        assert np.linalg.norm(ref - v) > 1e-3 * np.linalg.norm(v)
+
+
 def jacobi_from_zero(A, b, w, sweeps):
     u = np.zeros_like(b)
     Dinv = 1.0 / np.diag(A)
