@@ -67,8 +67,11 @@ enum { HELM_FP64 = 0, HELM_MIXED = 1 };
  * coarsest solve, which the paper discusses in section 5.3 for coarse grids
  * too large to factor). */
 enum { HELM_COARSE_LU = 0, HELM_COARSE_LEARNED = 1, HELM_COARSE_NONE = 2, HELM_COARSE_GMRES = 3 };
-/* Cycle shape below the finest level: V (one recursive call) or W (two;
- * the two-grid cycle text). K is reserved and rejected as unsupported. */
+/* Cycle shape below the finest level: V (one recursive call), W (two; the
+ * two-grid cycle text), or K (the paper's K-FGMRES of section 5.3: every
+ * coarse level but the coarsest is solved by two flexible GMRES steps from
+ * zero per column, each preconditioned by that level's cycle; a nonlinear
+ * preconditioner, for FGMRES). */
 enum { HELM_CYCLE_V = 0, HELM_CYCLE_W = 1, HELM_CYCLE_K = 2 };
 
 typedef struct {

@@ -141,8 +141,13 @@ struct helm_ctx {
   // cached Krylov workspace
   void* ws = nullptr;
   size_t wsbytes = 0;
-  // K-cycle inner workspace (allocated with the fields)
+  // per-level field-sized scratch (allocated with the fields): the second
+  // coarse cycle's right-hand side of the W-cycle, z2 of the K-cycle
   std::vector<void*> kbuf;
+  // K-cycle: per coarse level, three vectors (v1, v2, w) in the cycle's
+  // arithmetic precision and the per-column Hessenberg / least-squares data
+  void* kmem = nullptr;
+  std::vector<char*> klev;
   double* hbuf = nullptr;  // pinned host scratch
   size_t hbufn = 0;
   // tuned tile of the finest-level marching kernel, per block width P
@@ -265,6 +270,81 @@ static void zero_field(helm_ctx* c, int l, int P, void* u, hipStream_t s) {
 static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s);
 void field_axpy(helm_ctx* c, int l, int P, const void* x, void* y, hipStream_t s);
 
+static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void* tmp, hipStream_t s);
+
+// K-cycle storage of coarse level l: v1, v2, w in the cycle's arithmetic
+// precision, then per column the 3 x 2 Hessenberg matrix, the Gram
+// coefficients, the least-squares solution and the norms.
+static size_t kcycle_bytes(const helm_ctx* c, int l, int P) {
+  const size_t vb = (psize(comp_prec(c)) * c->lv[l].npts * P + 255) / 256 * 256;
+  return 3 * vb + 16 * (6 * (size_t)P + 6 * (size_t)P + 3 * (size_t)P + gram_part_elems(P) + 2 * (size_t)P) +
+         8 * 3 * (size_t)P + 256;
+}
+
+// K-cycle coarse correction of level l (not the coarsest; the paper's
+// K-FGMRES, section 5.3): the coarse problem M_l e = f (f in lv[l].F) is
+// solved by two flexible GMRES steps from zero per column, each step
+// preconditioned by the cycle of level l; e goes to lv[l].U0. The Krylov
+// vectors are kept in the cycle's arithmetic precision (FP32 in mixed
+// precision, where the level's fields are BF16); the preconditioned vectors
+// z1, z2 are the cycle's outputs in the level's storage (U0 and kbuf).
+static void kcycle_coarse(helm_ctx* c, int l, int P, hipStream_t s) {
+  Level& L = c->lv[l];
+  const int64_t N = L.npts;
+  const Prec fp = field_prec(c, l), kp = comp_prec(c);
+  char* m = c->klev[l];
+  const size_t vb = (psize(kp) * N * P + 255) / 256 * 256;
+  void* v1 = m;
+  void* v2 = m + vb;
+  void* w = m + 2 * vb;
+  c128* Hm = reinterpret_cast<c128*>(m + 3 * vb);
+  c128* Gc = Hm + 6 * (size_t)P;  // 2 (k+1) P entries, k = 2
+  c128* Yc = Gc + 6 * (size_t)P;  // (k+1) P
+  c128* part = Yc + 3 * (size_t)P;
+  c128* Gs = part + gram_part_elems(P);
+  double* b2 = reinterpret_cast<double*>(Gs + 2 * (size_t)P);
+  double* hn2 = b2 + P;
+  double* sc = hn2 + P;
+  void* z[2] = {L.U0, c->kbuf[l]};
+  // v1 = f / ||f|| (a zero column stays zero)
+  const void* fin = L.F;
+  if (fp != kp) {
+    launch_convert(fp, kp, N * P, L.F, v1, s);
+    fin = v1;
+  }
+  launch_colnorm2(kp, N, P, P, fin, part, Gs, b2, s);
+  launch_inv_sqrt(P, b2, sc, s);
+  launch_scale_cols(kp, N, P, P, sc, fin, v1, s);
+  PtrList vl{};
+  vl.p[0] = v1;
+  vl.p[1] = v2;
+  for (int j = 0; j < 2; ++j) {
+    const void* vj = vl.p[j];
+    // z_j = B v_j; the cycle reads its input in the level's storage (F is
+    // free once v1 is formed)
+    const void* cin = vj;
+    if (fp != kp) {
+      launch_convert(kp, fp, N * P, vj, L.F, s);
+      cin = L.F;
+    }
+    cycle_rec(c, l, P, cin, z[j], L.U1, s);
+    // w = M z_j, then one classical Gram-Schmidt pass against v_1..v_j
+    if (fp != kp) {
+      level_op(c, l, 0, P, z[j], nullptr, L.Rr, s);
+      launch_convert(fp, kp, N * P, L.Rr, w, s);
+    } else {
+      level_op(c, l, 0, P, z[j], nullptr, w, s);
+    }
+    launch_gram(kp, N, P, P, 1, j + 1, vl, w, part, Gc, s);
+    launch_update_norm(kp, N, P, P, j + 1, vl, Gc, w, part, Gs, hn2, s);
+    launch_cg_hcol(P, j, 2, Gc, hn2, Hm, sc, s);
+    if (j == 0) launch_scale_cols(kp, N, P, P, sc, w, v2, s);
+  }
+  // y = argmin || ||f|| e1 - H y || per column, e = z1 y1 + z2 y2 (into z1 = U0)
+  launch_cg_ls(P, 2, Hm, b2, Gc, Yc, s);
+  launch_kc_combine(fp, N, P, Yc, z[0], z[1], s);
+}
+
 // Multigrid cycle at level l for right-hand side f (level storage), result in
 // `out`; `tmp` is a second buffer of the same size (ping-pong for Jacobi).
 static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void* tmp, hipStream_t s) {
@@ -329,7 +409,12 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
       launch_restrict(pf, pc, pt, c->dim, L.geo(P), C.geo(P), L.Rr, C.F, s);
     }
   }
-  cycle_rec(c, l + 1, P, C.F, C.U0, C.U1, s);
+  if (c->cycle == HELM_CYCLE_K && l + 1 < c->L - 1) {
+    if (c->plan) c->plan_bad = true;  // the persistent cycle has no K-cycle
+    kcycle_coarse(c, l + 1, P, s);
+  } else {
+    cycle_rec(c, l + 1, P, C.F, C.U0, C.U1, s);
+  }
   if (c->cycle == HELM_CYCLE_W && l + 1 < c->L - 1) {
     if (c->plan) c->plan_bad = true;
     // W-cycle: a second coarse cycle on the residual of the first result,
@@ -642,6 +727,19 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
     c->cg_mem = nullptr;
     HCHECK(hipMalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
   }
+  hipFree(c->kmem);
+  c->kmem = nullptr;
+  c->klev.assign(c->L, nullptr);
+  if (c->cycle == HELM_CYCLE_K && c->L > 2) {
+    size_t kt = 0;
+    for (int l = 1; l < c->L - 1; ++l) kt += kcycle_bytes(c, l, P);
+    HCHECK(hipMalloc(&c->kmem, kt));
+    char* q = static_cast<char*>(c->kmem);
+    for (int l = 1; l < c->L - 1; ++l) {
+      c->klev[l] = q;
+      q += kcycle_bytes(c, l, P);
+    }
+  }
   c->fieldsP = P;
   return HELM_OK;
 }
@@ -842,6 +940,7 @@ static void free_ctx(helm_ctx* c) {
   hipFree(c->Minv64);
   hipFree(c->Minv32);
   hipFree(c->fieldmem);
+  hipFree(c->kmem);
   hipFree(c->cg_mem);
   hipFree(c->ws);
   hipFree(c->resid_buf);
@@ -870,7 +969,6 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   if (d->coarse_restarts < 0 || d->coarse_restarts > 16)
     return fail(HELM_ERR_INVALID_ARG, "coarse_restarts must be 0..16 (0 and 1: one GMRES cycle)");
   if (d->cycle < HELM_CYCLE_V || d->cycle > HELM_CYCLE_K) return fail(HELM_ERR_INVALID_ARG, "bad cycle kind");
-  if (d->cycle == HELM_CYCLE_K) return fail(HELM_ERR_UNSUPPORTED, "the K-cycle is not built in this library version");
   const int f = 1 << (d->levels - 1);
   int64_t N = 1;
   for (int a = 0; a < d->dim; ++a) {

@@ -1425,6 +1425,31 @@ void launch_convert(Prec pi, Prec po, int64_t nvals, const void* a, void* b, hip
   fatal_combo("launch_convert");
 }
 
+// z1 <- y1 z1 + y2 z2 per column c (y_j of column c at Y[j * P + c]), the
+// K-cycle's combination of its two preconditioned vectors; FP64 arithmetic,
+// rounded once to the field's storage.
+template <class S>
+__global__ void k_kc_combine(int64_t n, int P, const c128* __restrict__ Y, S* __restrict__ z1,
+                             const S* __restrict__ z2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % P);
+  const c128 a = get1(z1 + i), b = get1(z2 + i);
+  const c128 y1 = Y[c], y2 = Y[(int64_t)P + c];
+  put1(z1 + i, c128{y1.re * a.re - y1.im * a.im + (y2.re * b.re - y2.im * b.im),
+                    y1.re * a.im + y1.im * a.re + (y2.re * b.im + y2.im * b.re)});
+}
+
+void launch_kc_combine(Prec pf, int64_t N, int P, const c128* Y, void* z1, const void* z2, hipStream_t s) {
+  const int64_t n = N * P;
+  if (pf == P64)
+    hipLaunchKernelGGL((k_kc_combine<c128>), grid1(n), dim3(256), 0, s, n, P, Y, (c128*)z1, (const c128*)z2);
+  else if (pf == P32)
+    hipLaunchKernelGGL((k_kc_combine<c64>), grid1(n), dim3(256), 0, s, n, P, Y, (c64*)z1, (const c64*)z2);
+  else
+    hipLaunchKernelGGL((k_kc_combine<cbf>), grid1(n), dim3(256), 0, s, n, P, Y, (cbf*)z1, (const cbf*)z2);
+}
+
 void launch_to_internal(Prec po, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s) {
   dim3 gr((unsigned)((N + 31) / 32), (unsigned)((P + 31) / 32));
   if (po == P64) { hipLaunchKernelGGL((k_to_internal<c128>), gr, dim3(256), 0, s, N, nrhs, P, (const c128*)src, (c128*)dst); return; }

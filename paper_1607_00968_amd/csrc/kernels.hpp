@@ -56,6 +56,8 @@ void launch_restrict(Prec pi, Prec po, Prec pt, int dim, const Geo& gf, const Ge
 void launch_prolong_add(Prec pc, Prec pf, Prec pt, int dim, const Geo& gf, const Geo& gc, const void* ec, void* uf,
                         hipStream_t s);
 void launch_convert(Prec pi, Prec po, int64_t nvals, const void* a, void* b, hipStream_t s);
+// K-cycle: z1 <- y1 z1 + y2 z2 per column (Y: [2][P] complex), fields of N x P.
+void launch_kc_combine(Prec pf, int64_t N, int P, const c128* Y, void* z1, const void* z2, hipStream_t s);
 void launch_to_internal(Prec po, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
 void launch_to_abi(Prec pi, int64_t N, int nrhs, int P, const void* src, void* dst, hipStream_t s);
 

@@ -153,3 +153,14 @@ def test_wbicg_3d_matches_oracle(oracle_solution, precision):
     torch.cuda.synchronize()
     print(precision, "W-BiCG cycles", info["cycles"], "restarts", info["restarts"])
     check(U, info, 1e-8, oracle_solution)
+
+
+@pytest.mark.timeout(900)
+def test_kfgmres_3d_mixed_matches_oracle(oracle_solution):
+    """The paper's K-FGMRES (FGMRES(5) with the K-cycle, exact coarsest solve)
+    in mixed precision on the same 64^3 problem, block size 1."""
+    hd = pk.helm_setup(PROB.dim, PROB.n, PROB.h, PROB.m, PROB.gamma, PROB.omega, shift=PROB.shift, levels=3,
+                       precision="mixed", coarse="lu", cycle="K")
+    U, info = solve(hd, 1e-8, TILE_LDS)
+    print("K-FGMRES mixed cycles", info["cycles"])
+    check(U, info, 1e-8, oracle_solution)

@@ -122,3 +122,53 @@ def test_selective_reorthogonalisation_fp64():
         assert err.max() <= 1e-5, (r, err)
         out[r] = info["cycles"]
     assert abs(out[2] - out[1]) <= max(3, 0.1 * out[1]), out
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 32, 3), (2, 48, 4), (3, 16, 3), (3, 32, 3)])
+def test_kcycle_fp64_matches_oracle(dim, n, levels):
+    """The K-cycle (two flexible GMRES steps on every coarse level but the
+    coarsest) against the oracle's, which is pinned to its dense
+    minimal-residual definition: a nonlinear but deterministic map, equal
+    to rounding in FP64 (1e-9); a zero column stays zero."""
+    p = problem(dim, n, levels)
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=levels, coarse="lu",
+                       cycle="K")
+    ho = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels, cycle="K")
+    F = crand(5, p.N)
+    F[2] = 0.0
+    ref = ho.vcycle(F)
+    got = precond(hd, F)
+    assert rel(got, ref) <= 1e-9, rel(got, ref)
+    assert np.all(got[2] == 0)
+    hv = oracle.Hierarchy(oracle.grid(p.dim, p.n, p.h), p.m, p.gamma, p.omega, p.shift, levels)
+    assert rel(hv.vcycle(F), ref) > 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kfgmres_solve_2d_matches_oracle(precision):
+    """K-FGMRES (block FGMRES(5) with the K-cycle) on 2D 128^2 to 1e-8:
+    residuals by the oracle's operator, error against the oracle's 1e-10
+    solution <= 1e-5; FP64 cycle counts within 2% (or 2) of the oracle's
+    K-FGMRES."""
+    p = synth.gradient_2d()
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision, cycle="K")
+    Q = torch.from_numpy(np.ascontiguousarray(p.Q)).cuda()
+    U = torch.zeros_like(Q)
+    info = pk.helm_solve_block(hd, Q, U, tol=1e-8, restart=5, max_cycles=2000, block_size=1, reorth=1)
+    assert info["converged_all"], info
+    ho = oracle.setup_problem(p, levels=3, cycle="K")
+    Xo, it, rr, conv = ho.fgmres(p.Q, tol=1e-10, restart=5, maxit=3000)
+    assert conv
+    Uh = U.cpu().numpy()
+    g = oracle.grid(p.dim, p.n, p.h)
+    res = np.linalg.norm(p.Q - oracle.apply_fine(g, p.m, p.gamma, p.omega, 0.0, Uh), axis=1) / np.linalg.norm(
+        p.Q, axis=1)
+    assert res.max() <= 1e-8 * (1 + 1e-6), res
+    err = np.linalg.norm(Uh - Xo, axis=1) / np.linalg.norm(Xo, axis=1)
+    assert err.max() <= 1e-5, err
+    if precision == "fp64":
+        # block size 1: every column is its own FGMRES; the solve takes as
+        # many cycles as its slowest column
+        itk = max(ho.fgmres(p.Q[s:s + 1], tol=1e-8, restart=5, maxit=2000)[1] for s in range(p.nrhs))
+        print("K-FGMRES cycles GPU", info["cycles"], "oracle", itk)
+        assert abs(info["cycles"] - itk) <= max(2, 0.02 * itk), (info["cycles"], itk)

@@ -110,7 +110,6 @@ BAD_SETUPS = [
     ("GMRES coarsest with 0 steps", dict(coarse="gmres", coarse_iters=0), "INVALID_ARG"),
     ("GMRES coarsest with 33 steps (beyond the basis list)", dict(coarse="gmres", coarse_iters=33), "INVALID_ARG"),
     ("learned coarsest with 33 steps", dict(coarse="learned", coarse_iters=33), "INVALID_ARG"),
-    ("K-cycle", dict(cycle="K"), "UNSUPPORTED"),
 ]
 
 
