@@ -145,9 +145,17 @@ typedef struct {
                           FP64 true residual, checked whenever the recursive one meets tol
                           (then restarting from the current iterate if needed), keeps the
                           result honest either way. */
+  int32_t op;          /* the system solved: HELM_OP_H (0) H U = Q; HELM_OP_HT (1) the
+                          transposed system H^T U = Q, the same system because H is complex
+                          symmetric (a symmetric stencil plus a diagonal) and so is every
+                          Galerkin level (R = 2^-d P^T), so the hierarchy serves both, as the
+                          paper notes for the transposed solves of its sensitivities;
+                          HELM_OP_HH (2) the adjoint H^H U = Q, solved as H conj(U) = conj(Q)
+                          (the reported relres is that of the adjoint system) */
 } helm_solve_opts;
 
 enum { HELM_METHOD_FGMRES = 0, HELM_METHOD_BICGSTAB = 1 };
+enum { HELM_OP_H = 0, HELM_OP_HT = 1, HELM_OP_HH = 2 };
 
 typedef struct {
   int32_t cycles;       /* preconditioner applications (the paper's #Cyc): Arnoldi steps of
@@ -219,6 +227,41 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
  * `stream`. */
 helm_status helm_residual_noalloc(helm_handle h, int32_t nrhs, const void* Q, const void* U,
                                   double* relres, void* stream);
+
+/* ---- Sensitivities of full waveform inversion (eq:fwisens) -----------------
+ * With H u = q and dH/dm = -omega^2 diag(1 - i gamma) (m the squared
+ * slowness, real), the Jacobian of the field in the model is
+ *     J dm  = omega^2 H^-1 ((1 - i gamma) u . dm)        (one solve per source)
+ *     J^H w = omega^2 conj((1 - i gamma) u) . H^-H w     (one adjoint solve each)
+ * Fields u_s are given either in complex128 (U) or in the paper's 16-bit
+ * storage (U16 + scales, see helm_fields_pack16); exactly one of U and U16
+ * is non-NULL. The solves use helm_solve_block with the given tol and opts
+ * (opts.op is set by the call); info as there. */
+
+/* 16-bit storage of fields (the paper stores fields in a 16-bit floating
+ * point format, 32 bits per complex unknown and source): per source,
+ * scales[s] = the largest |re| or |im| of u_s (1 for a zero source), and
+ * U16[s][i] = (half(re / scales[s]), half(im / scales[s])), each value
+ * formed in FP64, rounded to FP32 and then to IEEE half (nearest even).
+ * U: DEVICE complex128 [nrhs][N]; U16: DEVICE 2 x FP16 [nrhs][N] (4 bytes per
+ * entry, re first); scales: DEVICE double [nrhs]. */
+helm_status helm_fields_pack16(helm_handle h, int32_t nrhs, const void* U, void* U16, double* scales,
+                               void* stream);
+/* U[s][i] = scales[s] * (re + i im) of U16[s][i], in FP64. */
+helm_status helm_fields_unpack16(helm_handle h, int32_t nrhs, const void* U16, const double* scales, void* U,
+                                 void* stream);
+/* JV[s] = J_s dm for every source: dm DEVICE double [N] (a real model
+ * perturbation of m), JV DEVICE complex128 [nrhs][N] (also the solve's
+ * right-hand side buffer). */
+helm_status helm_jvp(helm_handle h, int32_t nrhs, const void* U, const void* U16, const double* scales,
+                     const double* dm, void* JV, double tol, const helm_solve_opts* opts, helm_solve_info* info,
+                     void* stream);
+/* g = Re sum_s J_s^H w_s (the gradient of a real misfit with residuals w_s):
+ * W DEVICE complex128 [nrhs][N], g DEVICE double [N]. The adjoint solutions
+ * live in a buffer the handle allocates on first use and keeps. */
+helm_status helm_jtvp(helm_handle h, int32_t nrhs, const void* U, const void* U16, const double* scales,
+                      const void* W, double* g, double tol, const helm_solve_opts* opts, helm_solve_info* info,
+                      void* stream);
 
 /* Y = H X (op 0) or Y = M X (op 1, shifted), in FP64 (eq:LinearSystem).
  * X, Y: DEVICE complex128 [nrhs][N]. */

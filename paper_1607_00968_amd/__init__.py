@@ -23,6 +23,7 @@ __all__ = [
     "HelmError", "lib", "LIBPATH", "Handle", "helm_setup", "helm_solve_block",
     "helm_profile_enable", "helm_profile_read", "KERNEL_CLASSES",
     "helm_residual", "helm_residual_noalloc", "helm_apply", "helm_precond", "helm_level_stencil",
+    "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp",
     "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "helm_solve_batch", "ABI_SYMBOLS",
     "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture",
 ]
@@ -46,6 +47,7 @@ ABI_SYMBOLS = (
     "helm_net_nparams", "helm_net_create", "helm_net_destroy", "helm_net_set_params",
     "helm_net_get_params", "helm_net_save", "helm_net_forward", "helm_net_loss_grad",
     "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train", "helm_net_train_step",
+    "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
                   "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep", "fine_sweep01")
@@ -72,7 +74,7 @@ class SetupDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_cycles", C.c_int32), ("block_size", C.c_int32),
                 ("warm_start", C.c_int32), ("reorth", C.c_int32), ("graph", C.c_int32),
-                ("learned_rate", C.c_double), ("method", C.c_int32)]
+                ("learned_rate", C.c_double), ("method", C.c_int32), ("op", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -101,6 +103,10 @@ def lib():
                                        C.POINTER(SolveInfo), P]
         L.helm_residual.argtypes = [P, I, P, P, P, P]
         L.helm_residual_noalloc.argtypes = [P, I, P, P, P, P]
+        L.helm_fields_pack16.argtypes = [P, I, P, P, P, P]
+        L.helm_fields_unpack16.argtypes = [P, I, P, P, P, P]
+        L.helm_jvp.argtypes = [P, I, P, P, P, P, P, D, P, P, P]
+        L.helm_jtvp.argtypes = [P, I, P, P, P, P, P, D, P, P, P]
         L.helm_solve_batch.argtypes = [I, P, P, P, P, D, C.POINTER(SolveOpts), P, P, I, P]
         L.helm_apply.argtypes = [P, I, I, P, P, P]
         L.helm_precond.argtypes = [P, I, P, P, P]
@@ -236,11 +242,12 @@ def _form(graph) -> int:
 
 
 METHOD = {"fgmres": 0, "bicgstab": 1}
+OP = {"H": 0, "HT": 1, "HH": 2}
 
 
 def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, block_size=0,
                      warm_start=False, reorth=True, workspace=None, stream=None, graph=False,
-                     learned_rate=0.0, method="fgmres") -> dict:
+                     learned_rate=0.0, method="fgmres", op="H") -> dict:
     """Solve H U = Q (U overwritten). Returns a dict with cycles, relres, ...
     reorth: 0 one Gram-Schmidt pass, 1 (True, the default here) always two,
     2 a second pass only where the norm fell below half (the C default when
@@ -248,13 +255,14 @@ def helm_solve_block(hd: Handle, Q, U, tol=1e-6, restart=5, max_cycles=1000, blo
     "persistent"/2 the persistent cycle kernel. learned_rate: the plain
     cycle's calibrated per-cycle reduction factor for the learned coarsest
     correction's rate check (0 = off). method: "fgmres" (block FGMRES(restart))
-    or "bicgstab" (block BiCGSTAB, two cycles per iteration)."""
+    or "bicgstab" (block BiCGSTAB, two cycles per iteration). op: "H" (H U = Q),
+    "HT" (the transposed system, the same one) or "HH" (the adjoint)."""
     nrhs = Q.shape[0]
     qp, up = _dev_block(Q, "Q"), _dev_block(U, "U")
     if U.shape != Q.shape or Q.shape[1] != hd.N:
         raise ValueError("Q and U must both be [nrhs, N]")
     o = SolveOpts(restart, max_cycles, block_size, int(bool(warm_start)), int(reorth), _form(graph),
-                  float(learned_rate), METHOD[method])
+                  float(learned_rate), METHOD[method], OP[op])
     rel = np.zeros(nrhs)
     conv = np.zeros(nrhs, np.int32)
     info = SolveInfo()
@@ -320,6 +328,84 @@ def helm_residual_noalloc(hd: Handle, Q, U, stream=None) -> np.ndarray:
     _check(lib().helm_residual_noalloc(hd.ptr, nrhs, _dev_block(Q, "Q"), _dev_block(U, "U"),
                                        rel.ctypes.data, _stream(stream)))
     return rel
+
+
+def _dev_any(t, name, dtype, shape):
+    import torch
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def helm_fields_pack16(hd: Handle, U, stream=None):
+    """16-bit storage of fields: returns (U16 int16-viewed half pairs [nrhs, N, 2]
+    as torch.float16, scales float64 [nrhs]) on the device."""
+    import torch
+    nrhs = U.shape[0]
+    U16 = torch.empty((nrhs, hd.N, 2), dtype=torch.float16, device=U.device)
+    sc = torch.empty(nrhs, dtype=torch.float64, device=U.device)
+    _check(lib().helm_fields_pack16(hd.ptr, nrhs, _dev_block(U, "U"), C.c_void_p(U16.data_ptr()),
+                                    C.c_void_p(sc.data_ptr()), _stream(stream)))
+    return U16, sc
+
+
+def helm_fields_unpack16(hd: Handle, U16, scales, U, stream=None):
+    nrhs = U.shape[0]
+    _check(lib().helm_fields_unpack16(hd.ptr, nrhs, _dev_any(U16, "U16", U16.dtype, (nrhs, hd.N, 2)),
+                                      C.c_void_p(scales.data_ptr()), _dev_block(U, "U"), _stream(stream)))
+
+
+def _fields_args(hd, U=None, U16=None, scales=None):
+    if (U is None) == (U16 is None):
+        raise ValueError("give the fields as U or as (U16, scales)")
+    if U is not None:
+        return U.shape[0], _dev_block(U, "U"), None, None
+    return U16.shape[0], None, C.c_void_p(U16.data_ptr()), C.c_void_p(scales.data_ptr())
+
+
+def helm_jvp(hd: Handle, dm, JV, U=None, U16=None, scales=None, tol=1e-8, stream=None, **solve_kw) -> dict:
+    """JV = J dm (eq:fwisens) for every field: dm float64 CUDA [N]."""
+    import torch
+    nrhs, up, hp, sp = _fields_args(hd, U, U16, scales)
+    o = _opts(**solve_kw)
+    info, rel, conv = _info(nrhs)
+    st = _check(lib().helm_jvp(hd.ptr, nrhs, up, hp, sp, _dev_any(dm, "dm", torch.float64, (hd.N,)),
+                               _dev_block(JV, "JV"), float(tol), C.byref(o), C.byref(info), _stream(stream)),
+                allow=(HELM_ERR_NOT_CONVERGED,))
+    return _info_dict(st, info, rel, conv)
+
+
+def helm_jtvp(hd: Handle, W, g, U=None, U16=None, scales=None, tol=1e-8, stream=None, **solve_kw) -> dict:
+    """g = Re sum_s J_s^H w_s: W complex128 CUDA [nrhs, N], g float64 CUDA [N]."""
+    import torch
+    nrhs, up, hp, sp = _fields_args(hd, U, U16, scales)
+    o = _opts(**solve_kw)
+    info, rel, conv = _info(nrhs)
+    st = _check(lib().helm_jtvp(hd.ptr, nrhs, up, hp, sp, _dev_block(W, "W"),
+                                _dev_any(g, "g", torch.float64, (hd.N,)), float(tol), C.byref(o),
+                                C.byref(info), _stream(stream)), allow=(HELM_ERR_NOT_CONVERGED,))
+    return _info_dict(st, info, rel, conv)
+
+
+def _opts(restart=5, max_cycles=1000, block_size=1, reorth=0, graph=False, learned_rate=0.0, method="fgmres"):
+    return SolveOpts(restart, max_cycles, block_size, 0, int(reorth), _form(graph), float(learned_rate),
+                     METHOD[method], 0)
+
+
+def _info(nrhs):
+    rel = np.zeros(nrhs)
+    conv = np.zeros(nrhs, np.int32)
+    info = SolveInfo()
+    info.relres = rel.ctypes.data
+    info.converged = conv.ctypes.data
+    return info, rel, conv
+
+
+def _info_dict(st, info, rel, conv):
+    return {"status": st, "cycles": info.cycles, "restarts": info.restarts,
+            "converged_all": bool(info.converged_all), "fallback_used": int(info.fallback_used),
+            "t_solve_ms": info.t_solve_ms, "relres": rel, "converged": conv.astype(bool),
+            "rate_switch": int(info.rate_switch)}
 
 
 def helm_apply(hd: Handle, X, Y, shifted=False, stream=None):

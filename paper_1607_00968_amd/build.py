@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhelm.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["k_level.hip", "k_setup.hip", "k_krylov.hip", "k_bicg.hip", "k_resid.hip", "learned.hip", "helm.cpp"]
+SOURCES = ["k_level.hip", "k_setup.hip", "k_krylov.hip", "k_bicg.hip", "k_resid.hip", "k_sens.hip", "learned.hip", "helm.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

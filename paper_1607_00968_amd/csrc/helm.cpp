@@ -56,6 +56,7 @@ struct Level {
   // coefficients: fine level uses diagonals, coarser levels stencils [N][NS]
   c128* dH = nullptr;
   c128* dM = nullptr;
+  c128* dS = nullptr;  // finest level: omega^2 (1 - i gamma), the sensitivity factor
   c128* dw64 = nullptr;
   c64* dM32 = nullptr;
   c64* dw32 = nullptr;
@@ -138,6 +139,9 @@ struct helm_ctx {
   void* fieldmem = nullptr;
   // partial sums of helm_residual (allocated on its first call)
   double* resid_buf = nullptr;
+  // adjoint solutions of helm_jtvp (allocated on its first call)
+  void* sensbuf = nullptr;
+  size_t sensbytes = 0;
   // cached Krylov workspace
   void* ws = nullptr;
   size_t wsbytes = 0;
@@ -931,6 +935,7 @@ static void free_ctx(helm_ctx* c) {
     Level& L = c->lv[l];
     hipFree(L.dH);
     hipFree(L.dM);
+    hipFree(L.dS);
     hipFree(L.dw64);
     hipFree(L.dM32);
     hipFree(L.dw32);
@@ -944,6 +949,7 @@ static void free_ctx(helm_ctx* c) {
   hipFree(c->cg_mem);
   hipFree(c->ws);
   hipFree(c->resid_buf);
+  hipFree(c->sensbuf);
   if (c->hbuf) hipHostFree(c->hbuf);
   if (c->net) learned::destroy(c->net);
   for (hipEvent_t e : c->evpool) hipEventDestroy(e);
@@ -1034,7 +1040,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     double *dm = nullptr, *dg = nullptr;
     if (hipMalloc(&dm, 8 * N) != hipSuccess || hipMalloc(&dg, 8 * N) != hipSuccess ||
         hipMalloc(&L.dH, 16 * N) != hipSuccess || hipMalloc(&L.dM, 16 * N) != hipSuccess ||
-        hipMalloc(&L.dw64, 16 * N) != hipSuccess) {
+        hipMalloc(&L.dw64, 16 * N) != hipSuccess || hipMalloc(&L.dS, 16 * N) != hipSuccess) {
       hipFree(dm);
       hipFree(dg);
       return bail(fail(HELM_ERR_OOM, "setup: fine coefficients"));
@@ -1042,6 +1048,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     hipMemcpyAsync(dm, d->m, 8 * N, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(dg, d->gamma, 8 * N, hipMemcpyHostToDevice, s);
     launch_fine_coef(c->dim, N, dm, dg, c->omega, c->shift, c->wj[0], L.ih, L.dH, L.dM, L.dw64, s);
+    launch_sens_coef(N, dg, c->omega, L.dS, s);
     hipStreamSynchronize(s);
     hipFree(dm);
     hipFree(dg);
@@ -1489,6 +1496,11 @@ static helm_status bicgstab_solve(helm_ctx* c, int nrhs, const void* Q, void* U,
     launch_to_internal(P64, N, nrhs, P, U, X, s);
   else
     HCHECK(hipMemsetAsync(X, 0, blk, s));
+  if (o.op == HELM_OP_HH) {
+    // H^H U = Q is conj(H) U = Q: solve H conj(U) = conj(Q) (H = H^T)
+    launch_conj((int64_t)N * P, Qi, s);
+    if (o.warm_start) launch_conj((int64_t)N * P, X, s);
+  }
   { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, Qi, part, G1, dq, s); }
   HCHECK(hipMemcpyAsync(hq, dq, 8 * Pa, hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
@@ -1629,6 +1641,7 @@ static helm_status bicgstab_solve(helm_ctx* c, int nrhs, const void* Q, void* U,
     }
     if (diverged) {
       HCHECK(hipMemcpyAsync(X, Xr, blk, hipMemcpyDeviceToDevice, s));
+      if (o.op == HELM_OP_HH) launch_conj((int64_t)N * P, X, s);
       launch_to_abi(P64, N, nrhs, P, X, U, s);
       HCHECK(hipStreamSynchronize(s));
       cleanup();
@@ -1661,6 +1674,7 @@ static helm_status bicgstab_solve(helm_ctx* c, int nrhs, const void* Q, void* U,
       }
     }
   }
+  if (o.op == HELM_OP_HH) launch_conj((int64_t)N * P, X, s);
   launch_to_abi(P64, N, nrhs, P, X, U, s);
   HCHECK(hipEventRecord(e1, s));
   HCHECK(hipEventSynchronize(e1));
@@ -1690,7 +1704,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   helm_status st = check_block(h, nrhs, Q, U);
   if (st != HELM_OK) return st;
   if (!(tol > 0) || !std::isfinite(tol)) return fail(HELM_ERR_INVALID_ARG, "tol must be > 0");
-  helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0};
+  helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0, 0, 0};
   if (opts) o = *opts;
   if (!(o.learned_rate >= 0.0 && o.learned_rate < 1.0))
     return fail(HELM_ERR_INVALID_ARG, "learned_rate must be in [0, 1)");
@@ -1703,6 +1717,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");
   if (o.method != HELM_METHOD_FGMRES && o.method != HELM_METHOD_BICGSTAB)
     return fail(HELM_ERR_INVALID_ARG, "method must be HELM_METHOD_FGMRES or HELM_METHOD_BICGSTAB");
+  if (o.op < HELM_OP_H || o.op > HELM_OP_HH) return fail(HELM_ERR_INVALID_ARG, "op must be HELM_OP_H, _HT or _HH");
   if (o.method == HELM_METHOD_BICGSTAB) return bicgstab_solve(h, nrhs, Q, U, tol, o, pb, workspace, ws_bytes, info, stream);
   hipStream_t s = static_cast<hipStream_t>(stream);
   helm_ctx* c = h;
@@ -1791,6 +1806,11 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     launch_to_internal(P64, N, nrhs, P, U, X, s);
   else
     hipMemsetAsync(X, 0, blk, s);
+  if (o.op == HELM_OP_HH) {
+    // H^H U = Q is conj(H) U = Q: solve H conj(U) = conj(Q) (H = H^T)
+    launch_conj((int64_t)N * P, Qi, s);
+    if (o.warm_start) launch_conj((int64_t)N * P, X, s);
+  }
   { Prof pr_(c, HELM_K_GRAM, s); launch_colnorm2(P64, N, P, Pa, Qi, part, G, dq, s); }
   HCHECK(hipMemcpyAsync(hq, dq, 8 * Pa, hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
@@ -1962,6 +1982,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     for (int i = 0; i <= jlast; ++i) zl.p[i] = Z[i];
     { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(2, pz, P64, N, P, Pa, pb, jlast + 1, zl, Yc, X, s); }
   }
+  if (o.op == HELM_OP_HH) launch_conj((int64_t)N * P, X, s);
   launch_to_abi(P64, N, nrhs, P, X, U, s);
   HCHECK(hipEventRecord(e1, s));
   HCHECK(hipEventSynchronize(e1));
@@ -2002,6 +2023,80 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
   launch_resid_norms(L.geo(1), nrhs, L.ih, L.dH, Q, U, h->resid_buf, s);
   HCHECK(hipGetLastError());
   HCHECK(hipMemcpyAsync(relres, h->resid_buf, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
+helm_status helm_fields_pack16(helm_handle h, int32_t nrhs, const void* U, void* U16, double* scales, void* stream) {
+  helm_status st = check_block(h, nrhs, U, U16);
+  if (st != HELM_OK) return st;
+  if (!scales) return fail(HELM_ERR_INVALID_ARG, "scales is null");
+  launch_pack16(h->lv[0].npts, nrhs, static_cast<const c128*>(U), scales, U16, static_cast<hipStream_t>(stream));
+  HCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+helm_status helm_fields_unpack16(helm_handle h, int32_t nrhs, const void* U16, const double* scales, void* U,
+                                 void* stream) {
+  helm_status st = check_block(h, nrhs, U16, U);
+  if (st != HELM_OK) return st;
+  if (!scales) return fail(HELM_ERR_INVALID_ARG, "scales is null");
+  launch_unpack16(h->lv[0].npts, nrhs, U16, scales, static_cast<c128*>(U), static_cast<hipStream_t>(stream));
+  HCHECK(hipGetLastError());
+  return HELM_OK;
+}
+
+static helm_status check_fields(const void* U, const void* U16, const double* scales) {
+  if ((U == nullptr) == (U16 == nullptr)) return fail(HELM_ERR_INVALID_ARG, "give the fields as U or as U16");
+  if (U16 && !scales) return fail(HELM_ERR_INVALID_ARG, "16-bit fields need their scales");
+  return HELM_OK;
+}
+
+helm_status helm_jvp(helm_handle h, int32_t nrhs, const void* U, const void* U16, const double* scales,
+                     const double* dm, void* JV, double tol, const helm_solve_opts* opts, helm_solve_info* info,
+                     void* stream) {
+  helm_status st = check_block(h, nrhs, U ? U : U16, JV);
+  if (st != HELM_OK) return st;
+  if ((st = check_fields(U, U16, scales)) != HELM_OK) return st;
+  if (!dm) return fail(HELM_ERR_INVALID_ARG, "dm is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0, 0, 0};
+  if (opts) o = *opts;
+  o.op = HELM_OP_H;
+  o.warm_start = 0;
+  // right-hand side omega^2 (1 - i gamma) u dm into JV, then H JV = JV (the
+  // solve copies its right-hand side before it writes its solution)
+  launch_jvp_rhs(h->lv[0].npts, nrhs, h->lv[0].dS, U, U16, scales, dm, static_cast<c128*>(JV), s);
+  HCHECK(hipGetLastError());
+  return helm_solve_block(h, nrhs, JV, JV, tol, &o, nullptr, 0, info, stream);
+}
+
+helm_status helm_jtvp(helm_handle h, int32_t nrhs, const void* U, const void* U16, const double* scales,
+                      const void* W, double* g, double tol, const helm_solve_opts* opts, helm_solve_info* info,
+                      void* stream) {
+  helm_status st = check_block(h, nrhs, U ? U : U16, W);
+  if (st != HELM_OK) return st;
+  if ((st = check_fields(U, U16, scales)) != HELM_OK) return st;
+  if (!g) return fail(HELM_ERR_INVALID_ARG, "g is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t N = h->lv[0].npts;
+  const size_t need = 16 * (size_t)N * nrhs;
+  if (h->sensbytes < need) {
+    hipFree(h->sensbuf);
+    h->sensbuf = nullptr;
+    h->sensbytes = 0;
+    HCHECK(hipMalloc(&h->sensbuf, need));
+    h->sensbytes = need;
+  }
+  helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0, 0, 0};
+  if (opts) o = *opts;
+  o.op = HELM_OP_HH;
+  o.warm_start = 0;
+  c128* Y = static_cast<c128*>(h->sensbuf);
+  st = helm_solve_block(h, nrhs, W, Y, tol, &o, nullptr, 0, info, stream);
+  if (st != HELM_OK) return st;
+  launch_jtvp_accum(N, nrhs, h->lv[0].dS, U, U16, scales, Y, g, s);
+  HCHECK(hipGetLastError());
   HCHECK(hipStreamSynchronize(s));
   return HELM_OK;
 }

@@ -76,6 +76,17 @@ void launch_resid_norms(const Geo& g, int nrhs, const double ih[3], const c128* 
 // columns); looked up once per device.
 hipError_t resid_static_scratch(double** out);
 
+// ---- k_sens.hip -------------------------------------------------------------
+// Sensitivity products (eq:fwisens) and 16-bit fields, ABI layout [nrhs][N].
+void launch_sens_coef(int64_t N, const double* gamma, double omega, c128* dS, hipStream_t s);
+void launch_jvp_rhs(int64_t N, int nrhs, const c128* dS, const void* U, const void* U16, const double* sc,
+                    const double* dm, c128* out, hipStream_t s);
+void launch_jtvp_accum(int64_t N, int nrhs, const c128* dS, const void* U, const void* U16, const double* sc,
+                       const c128* Y, double* g, hipStream_t s);
+void launch_conj(int64_t n, c128* x, hipStream_t s);
+void launch_pack16(int64_t N, int nrhs, const c128* U, double* sc, void* H, hipStream_t s);
+void launch_unpack16(int64_t N, int nrhs, const void* H, const double* sc, c128* U, hipStream_t s);
+
 // ---- k_setup.hip ------------------------------------------------------------
 // Fine-level diagonals from (m, gamma): dH, dM (shifted) and dw = wjac / dM.
 void launch_fine_coef(int dim, int64_t N, const double* m, const double* gamma, double omega, double beta,
