@@ -190,6 +190,14 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
                              const helm_solve_opts* opts, void* workspace, size_t ws_bytes,
                              helm_solve_info* info, void* stream);
 
+/* Set up k hierarchies, one per descriptor (for example one model at the
+ * frequencies of a frequency-continuation sweep, the paper's frequency
+ * continuation algorithm, each frequency with its own hierarchy), as k
+ * calls of helm_setup on `stream`. out: HOST [k]. On an error no handle is
+ * left: the ones already built are destroyed, out[] is NULL and the
+ * message names the instance. */
+helm_status helm_setup_batch(int32_t k, const helm_setup_desc* descs, void* stream, helm_handle* out);
+
 /* Solve k independent instances concurrently (uneven sizes welcome): instance
  * i is helm_solve_block(hs[i], nrhs[i], Q[i], U[i], tol, opts) on a stream
  * owned by hs[i] (created on first use, default priority), driven by a pool of

@@ -25,7 +25,7 @@ __all__ = [
     "helm_residual", "helm_residual_noalloc", "helm_apply", "helm_precond", "helm_level_stencil",
     "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp",
     "helm_level_dims", "helm_coarse_solve", "helm_workspace_size", "helm_solve_batch", "ABI_SYMBOLS",
-    "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture",
+    "Net", "helm_net_nparams", "helm_net_create", "helm_net_capture", "helm_setup_batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,7 +47,7 @@ ABI_SYMBOLS = (
     "helm_net_nparams", "helm_net_create", "helm_net_destroy", "helm_net_set_params",
     "helm_net_get_params", "helm_net_save", "helm_net_forward", "helm_net_loss_grad",
     "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train", "helm_net_train_step",
-    "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp",
+    "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp", "helm_setup_batch",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
                   "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep", "fine_sweep01")
@@ -104,6 +104,7 @@ def lib():
         L.helm_residual.argtypes = [P, I, P, P, P, P]
         L.helm_residual_noalloc.argtypes = [P, I, P, P, P, P]
         L.helm_fields_pack16.argtypes = [P, I, P, P, P, P]
+        L.helm_setup_batch.argtypes = [I, P, P, P]
         L.helm_fields_unpack16.argtypes = [P, I, P, P, P, P]
         L.helm_jvp.argtypes = [P, I, P, P, P, P, P, D, P, P, P]
         L.helm_jtvp.argtypes = [P, I, P, P, P, P, P, D, P, P, P]
@@ -192,10 +193,10 @@ def _per_level(v, levels, typ):
     return (typ * MAX_LEVELS)(*v[:MAX_LEVELS])
 
 
-def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_post=2,
-               jacobi_weight=0.8, precision="fp64", coarse="lu", cycle="V", coarse_iters=20,
-               net=None, stream=None, coarse_restarts=1) -> Handle:
-    """Build the hierarchy. m, gamma: host float64 arrays of N entries."""
+def _setup_desc(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_post=2,
+                jacobi_weight=0.8, precision="fp64", coarse="lu", cycle="V", coarse_iters=20,
+                net=None, coarse_restarts=1):
+    """(descriptor, host buffers it points at) for helm_setup."""
     d = SetupDesc()
     lib().helm_setup_desc_default(C.byref(d))
     d.dim = dim
@@ -224,9 +225,35 @@ def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_pos
         blob = np.ascontiguousarray(np.frombuffer(net, dtype=np.uint8))
         d.net = blob.ctypes.data
         d.net_bytes = blob.nbytes
+    return d, (m, gamma, blob, nn)
+
+
+def helm_setup(dim, n, h, m, gamma, omega, shift=0.2, levels=3, nu_pre=2, nu_post=2,
+               jacobi_weight=0.8, precision="fp64", coarse="lu", cycle="V", coarse_iters=20,
+               net=None, stream=None, coarse_restarts=1) -> Handle:
+    """Build the hierarchy. m, gamma: host float64 arrays of N entries."""
+    d, keep = _setup_desc(dim, n, h, m, gamma, omega, shift, levels, nu_pre, nu_post, jacobi_weight, precision,
+                          coarse, cycle, coarse_iters, net, coarse_restarts)
     out = C.c_void_p()
     _check(lib().helm_setup(C.byref(d), _stream(stream), C.byref(out)))
-    return Handle(out, dim, nn[:dim], levels, precision)
+    return Handle(out, dim, keep[3][:dim], levels, precision)
+
+
+def helm_setup_batch(problems, stream=None, **kw) -> list:
+    """One hierarchy per problem (objects with dim, n, h, m, gamma, omega,
+    shift and levels, e.g. synth.Problem), built by one helm_setup_batch call;
+    kw as for helm_setup (shared by all)."""
+    k = len(problems)
+    descs = (SetupDesc * k)()
+    keep = []
+    for i, p in enumerate(problems):
+        d, kp = _setup_desc(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=p.levels, **kw)
+        descs[i] = d
+        keep.append(kp)
+    out = (C.c_void_p * k)()
+    _check(lib().helm_setup_batch(k, descs, _stream(stream), out))
+    return [Handle(C.c_void_p(out[i]), p.dim, keep[i][3][:p.dim], p.levels, kw.get("precision", "fp64"))
+            for i, p in enumerate(problems)]
 
 
 def helm_workspace_size(hd: Handle, nrhs: int, restart: int = 5) -> int:

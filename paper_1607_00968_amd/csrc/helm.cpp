@@ -2254,6 +2254,26 @@ helm_status helm_net_train(helm_net n, int32_t steps, int32_t batch, double lr, 
 // its own stream once per Arnoldi step, so a thread per active instance keeps
 // the GPU fed with the other instances' kernels meanwhile).
 // ---------------------------------------------------------------------------
+// k hierarchies from k descriptors (e.g. one model at several frequencies,
+// as frequency continuation needs), set up one after another on `stream`.
+helm_status helm_setup_batch(int32_t k, const helm_setup_desc* descs, void* stream, helm_handle* out) {
+  if (k < 1 || !descs || !out) return fail(HELM_ERR_INVALID_ARG, "bad batch set-up arguments");
+  for (int i = 0; i < k; ++i) out[i] = nullptr;
+  for (int i = 0; i < k; ++i) {
+    const helm_status st = helm_setup(&descs[i], stream, &out[i]);
+    if (st != HELM_OK) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + g_err;
+      for (int j = 0; j < i; ++j) {
+        helm_destroy(out[j]);
+        out[j] = nullptr;
+      }
+      g_err = msg;
+      return st;
+    }
+  }
+  return HELM_OK;
+}
+
 helm_status helm_solve_batch(int32_t k, const helm_handle* hs, const int32_t* nrhs, const void* const* Q,
                              void* const* U, double tol, const helm_solve_opts* opts, helm_solve_info* infos,
                              int32_t* status, int32_t max_threads, void* stream) {

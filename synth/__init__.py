@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Problem", "gradient_model_2d", "layered_model", "layer_gamma",
     "omega_for_ppw", "surface_sources", "random_rhs", "gradient_2d", "layered_3d",
-    "training_model", "batch_instances",
+    "training_model", "batch_instances", "frequency_sweep",
 ]
 
 
@@ -242,3 +242,18 @@ def batch_instances(count: int = 48, seed: int = 4000, sizes_2d=None, sizes_3d=N
         out.append(_make(dim, n, v, width, w, grid, f"batch{k}", 3 if w >= 8.0 else 2, 5))
     return out
 
+
+
+def frequency_sweep(base: Problem, freqs=(2.0, 2.5, 3.5, 4.5, 6.0)) -> list:
+    """The problem at several frequencies, as frequency continuation needs:
+    the same model, attenuation and sources, with omega scaled by
+    freqs / max(freqs) from the base problem's omega (which thus belongs to
+    the highest frequency). The default set has the ratios of the paper's
+    frequency list (2.0, 2.5, 3.5, 4.5, 6.0 Hz). Instances are named by
+    their ratio, lowest first."""
+    fmax = max(freqs)
+    out = []
+    for f in sorted(freqs):
+        p = dataclasses.replace(base, omega=base.omega * f / fmax, name=f"{base.name}-f{f:g}")
+        out.append(p)
+    return out

@@ -103,3 +103,14 @@ def test_batch_instances_rules():
         check_sources(p, p.nrhs, 16 if p.dim == 2 else 12)
     low = synth.batch_instances(count=2, sizes_2d=[64], ppw=(6.0, 7.9))
     assert all(p.levels == 2 for p in low)
+
+
+def test_frequency_sweep_keeps_model_and_sources():
+    import synth
+    base = synth.gradient_2d(n=64, nsrc=(2,), levels=3)
+    sw = synth.frequency_sweep(base)
+    assert len(sw) == 5
+    ratios = [p.omega / base.omega for p in sw]
+    assert np.allclose(ratios, np.array([2.0, 2.5, 3.5, 4.5, 6.0]) / 6.0)
+    for p in sw:
+        assert p.m is base.m and p.gamma is base.gamma and p.Q is base.Q and p.levels == base.levels
