@@ -67,8 +67,9 @@ def pack16(U):
     U = np.ascontiguousarray(U, dtype=np.complex128)
     s = np.max(np.maximum(np.abs(U.real), np.abs(U.imag)), axis=1)
     s = np.where(s > 0, s, 1.0)
-    V = U / s[:, None]
-    h = np.stack([V.real.astype(np.float32).astype(np.float16), V.imag.astype(np.float32).astype(np.float16)], -1)
+    vr = U.real / s[:, None]  # real and imaginary parts divided separately, in FP64
+    vi = U.imag / s[:, None]
+    h = np.stack([vr.astype(np.float32).astype(np.float16), vi.astype(np.float32).astype(np.float16)], -1)
     return h, s
 
 
