@@ -77,6 +77,8 @@ def lib():
         L.orc_block_fgmres.argtypes = [P, C.c_int, C.c_int, P, P, C.c_int, C.c_double,
                                        C.c_int, C.c_int, C.POINTER(C.c_int), P, P]
         L.orc_householder_qr.argtypes = [C.c_int64, C.c_int, P, P]
+        L.orc_householder_qr_rr.argtypes = [C.c_int64, C.c_int, P, P, C.c_double]
+        L.orc_householder_qr_rr.restype = C.c_int
         L.orc_lstsq.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -166,6 +168,16 @@ def householder_qr(A):
     R = np.empty((p, p), np.complex128)
     lib().orc_householder_qr(N, p, _p(A), _p(R))
     return A, R.T.copy()  # R returned as a numpy matrix (row, col)
+
+
+def householder_qr_rr(A, tol=1e-13):
+    """Rank-revealing QR of A [p][N] (columns contiguous): (Q [p][N] with zero
+    columns past the rank, R (numpy p x p, original column order), rank)."""
+    A = _c(A).copy()
+    p, N = A.shape
+    R = np.empty((p, p), np.complex128)
+    r = lib().orc_householder_qr_rr(N, p, _p(A), _p(R), float(tol))
+    return A, R.T.copy(), int(r)
 
 
 def lstsq(A, B):

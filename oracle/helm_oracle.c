@@ -703,6 +703,65 @@ void orc_householder_qr(int64_t N, int p, ozc* A, ozc* R) {
   free(has);
 }
 
+/* Rank-revealing Householder QR with column pivoting: at step k the
+ * remaining column of largest norm (rows k..N-1) is brought to position k;
+ * the factorisation stops when that norm is at most tol times the largest
+ * initial column norm (rank r = k). A (N x p, column-major) is replaced by
+ * Q with orthonormal columns 0..r-1 and zero columns r..p-1; R (p x p,
+ * column-major) gets rows 0..r-1 of the pivoted factor with its columns
+ * put back in the original order and zero rows r..p-1, so that the input
+ * equals Q R to within tol. Returns r. A block whose columns are
+ * dependent (duplicate sources) thus keeps only independent directions. */
+int orc_householder_qr_rr(int64_t N, int p, ozc* A, ozc* R, double tol) {
+  ozc* V = (ozc*)calloc((size_t)(N * p), sizeof(ozc));
+  int* perm = (int*)malloc(sizeof(int) * p);
+  double nmax = 0.0;
+  for (int j = 0; j < p; ++j) {
+    perm[j] = j;
+    nmax = fmax(nmax, vnorm(N, A + (int64_t)j * N));
+  }
+  int r = 0;
+  for (int k = 0; k < p && k < N; ++k) {
+    int jm = k;
+    double best = -1.0;
+    for (int j = k; j < p; ++j) {
+      const double nj = vnorm(N - k, A + (int64_t)j * N + k);
+      if (nj > best) {
+        best = nj;
+        jm = j;
+      }
+    }
+    if (!(best > tol * nmax)) break;
+    if (jm != k) {
+      for (int64_t i = 0; i < N; ++i) {
+        const ozc t = A[(int64_t)k * N + i];
+        A[(int64_t)k * N + i] = A[(int64_t)jm * N + i];
+        A[(int64_t)jm * N + i] = t;
+      }
+      const int t = perm[k];
+      perm[k] = perm[jm];
+      perm[jm] = t;
+    }
+    ozc alpha;
+    make_reflector(N - k, A + (int64_t)k * N + k, V + (int64_t)k * N, &alpha);
+    for (int j = k; j < p; ++j) apply_reflector(N - k, V + (int64_t)k * N, A + (int64_t)j * N + k);
+    r = k + 1;
+  }
+  for (int j = 0; j < p; ++j)
+    for (int i = 0; i < p; ++i) R[(int64_t)perm[j] * p + i] = (i < r && i <= j) ? A[(int64_t)j * N + i] : 0;
+  /* Q = H_0 ... H_{r-1} [I_r; 0], zero columns beyond the rank */
+  for (int j = 0; j < p; ++j) {
+    ozc* q = A + (int64_t)j * N;
+    memset(q, 0, sizeof(ozc) * N);
+    if (j < r) q[j] = 1.0;
+  }
+  for (int k = r - 1; k >= 0; --k)
+    for (int j = 0; j < r; ++j) apply_reflector(N - k, V + (int64_t)k * N, A + (int64_t)j * N + k);
+  free(V);
+  free(perm);
+  return r;
+}
+
 void orc_lstsq(int mr, int nc, int k, const ozc* A, const ozc* B, ozc* Y, double* res) {
   ozc* a = (ozc*)malloc(sizeof(ozc) * mr * nc);
   ozc* b = (ozc*)malloc(sizeof(ozc) * mr * k);
@@ -719,7 +778,9 @@ void orc_lstsq(int mr, int nc, int k, const ozc* A, const ozc* B, ozc* Y, double
     for (int i = nc - 1; i >= 0; --i) {
       ozc acc = b[(int64_t)c * mr + i];
       for (int j = i + 1; j < nc; ++j) acc -= a[(int64_t)j * mr + i] * Y[(int64_t)c * nc + j];
-      Y[(int64_t)c * nc + i] = acc / a[(int64_t)i * mr + i];
+      /* a column of zeros (a direction dropped by the rank-revealing QR)
+       * does not change the residual: its coefficient is taken as 0 */
+      Y[(int64_t)c * nc + i] = a[(int64_t)i * mr + i] != 0 ? acc / a[(int64_t)i * mr + i] : 0;
     }
     res[c] = vnorm(mr - nc, b + (int64_t)c * mr + nc);
   }
@@ -762,7 +823,9 @@ int orc_block_fgmres(const orc_hier* Hh, int use_prec, int p, const ozc* Q, ozc*
       done = 1;
       break;
     }
-    orc_householder_qr(N, p, V, S); /* R = V_1 S */
+    /* R = V_1 S; dependent residual columns (e.g. duplicate sources) keep
+     * only their independent directions (zero columns of V_1) */
+    orc_householder_qr_rr(N, p, V, S, 1e-13);
     memset(Hb, 0, sizeof(ozc) * hr * hc);
     int j;
     for (j = 0; j < mm && it < maxit; ++j) {
@@ -798,7 +861,7 @@ int orc_block_fgmres(const orc_hier* Hh, int use_prec, int p, const ozc* Q, ozc*
       }
       ozc* Vn = V + (int64_t)(j + 1) * blk;
       memcpy(Vn, W, sizeof(ozc) * blk);
-      orc_householder_qr(N, p, Vn, Hij); /* W = V_{j+1} H_{j+1,j} */
+      orc_householder_qr_rr(N, p, Vn, Hij, 1e-13); /* W = V_{j+1} H_{j+1,j} */
       for (int b = 0; b < p; ++b)
         for (int a = 0; a < p; ++a) Hb[(int64_t)(j * p + b) * hr + (j + 1) * p + a] = Hij[b * p + a];
       it++;

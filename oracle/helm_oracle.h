@@ -127,7 +127,13 @@ int orc_block_fgmres(const orc_hier* H, int use_prec, int p, const ozc* Q, ozc* 
 /* Householder QR of an N x p column-major complex matrix: A is replaced by Q
  * (N x p, orthonormal columns), R (p x p, column-major upper) written out. */
 void orc_householder_qr(int64_t N, int p, ozc* A, ozc* R);
-/* min ||B - A Y||_F with A m x n (m >= n, full rank), B m x k, column-major.
+/* Rank-revealing Householder QR with column pivoting (stops at a remaining
+ * column norm <= tol * largest column norm): A becomes Q (zero columns past
+ * the rank), R (p x p, column-major) the factor in the original column order
+ * with zero rows past the rank. Returns the rank. */
+int orc_householder_qr_rr(int64_t N, int p, ozc* A, ozc* R, double tol);
+/* min ||B - A Y||_F with A m x n (m >= n, full rank apart from columns of
+ * zeros, whose coefficients are 0), B m x k, column-major.
  * Y (n x k) written out; res (k) = column norms of the residual. */
 void orc_lstsq(int mrows, int ncols, int k, const ozc* A, const ozc* B, ozc* Y, double* res);
 

@@ -97,6 +97,15 @@ MUTANTS = [
      "orc_apply_fine(&Hh->g[0], Hh->m, Hh->gamma, Hh->omega, 0.0, p, X, V);",
      "orc_apply_fine(&Hh->g[0], Hh->m, Hh->gamma, Hh->omega, Hh->beta, p, X, V);", 0,
      [lambda: pins.test_fgmres_manufactured_solution(1)]),
+    # deflation of dependent directions (rank-revealing QR)
+    ("rank-revealing QR keeps the pivoted column order in R", "helm_oracle.c",
+     "R[(int64_t)perm[j] * p + i] = (i < r && i <= j)", "R[(int64_t)j * p + i] = (i < r && i <= j)", 0,
+     [pins.test_householder_qr_rank_revealing, lambda: pins.test_fgmres_duplicate_and_dependent_sources(5)]),
+    ("least squares divides by a dropped direction's zero diagonal", "helm_oracle.c",
+     "a[(int64_t)i * mr + i] != 0 ? acc / a[(int64_t)i * mr + i] : 0",
+     "acc / a[(int64_t)i * mr + i]", 0, [lambda: pins.test_fgmres_duplicate_and_dependent_sources(5)]),
+    ("rank-revealing QR without pivoting", "helm_oracle.c", "if (nj > best) {", "if (j == k) {", 0,
+     [pins.test_householder_qr_rank_revealing]),
     # the network oracle
     ("convolution taps mirrored", "conv_oracle.c",
      "const int xx = X + t % 3 - 1, yy = Y + (t / 3) % 3 - 1, zz = Z + t / 9 - 1;",

@@ -280,6 +280,38 @@ def test_householder_qr():
     assert np.allclose(np.tril(R, -1), 0)
 
 
+def test_householder_qr_rank_revealing():
+    """Rank-revealing QR (the block method's deflation of dependent
+    directions): duplicate and combined columns are dropped, Q spans the
+    columns' space with orthonormal columns up to the rank and zero columns
+    past it, R has zero rows past the rank, and Q R reproduces the input."""
+    a = crand(3, 300)
+    A = np.stack([a[0], a[1], a[0], a[0] + 2 * a[1], a[2]])  # rank 3
+    Q, R, r = oracle.householder_qr_rr(A)
+    assert r == 3 == np.linalg.matrix_rank(A.T)
+    Qm = Q.T
+    assert np.allclose(Qm.conj().T @ Qm, np.diag([1, 1, 1, 0, 0]), atol=1e-13)
+    assert np.abs(Qm[:, 3:]).max() == 0.0 and np.abs(R[3:]).max() == 0.0
+    assert np.allclose(Qm @ R, A.T, atol=1e-12 * np.abs(A).max())
+    # duplicate columns keep identical coefficients
+    assert np.allclose(R[:, 0], R[:, 2], atol=1e-13 * np.abs(R).max())
+    # a dependence weaker than the tolerance is kept as a direction
+    B = A.copy()
+    B[2] = a[0] + 1e-9 * crand(1, 300)[0]
+    Qb, Rb, rb = oracle.householder_qr_rr(B)
+    assert rb == 4
+    assert np.allclose(Qb.T @ Rb, B.T, atol=1e-12 * np.abs(B).max())
+    # full rank: the same factor as the unpivoted QR up to column phases
+    C = crand(4, 200)
+    Qc, Rc, rc = oracle.householder_qr_rr(C)
+    Q0, R0 = oracle.householder_qr(C)
+    assert rc == 4
+    assert np.allclose(Qc.T @ Rc, C.T, atol=1e-12)
+    assert np.allclose(np.abs(Qc.conj() @ Qc.T), np.eye(4), atol=1e-13)
+    # the same column space as the unpivoted Q
+    assert np.allclose(Q0.T @ (Q0.conj() @ Qc.T), Qc.T, atol=1e-12)
+
+
 def test_lstsq_matches_numpy():
     A = crand(14, 9)
     B = crand(14, 3)
@@ -592,6 +624,34 @@ def test_fgmres_converged_columns_meet_tolerance_and_dense_solution():
     A = sparse_H(2, p.n, p.h, p.m, p.gamma, p.omega, 0.0)
     Xd = spl.splu(A.tocsc()).solve(p.Q.T).T
     assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < 1e-6
+
+
+@pytest.mark.parametrize("restart", [5, 12])
+def test_fgmres_duplicate_and_dependent_sources(restart):
+    """A block with a duplicate source and a combination of two sources
+    (rank 2 of 4): the rank-revealing QR drops the dependent directions,
+    the duplicate's solution equals the first source's, the combination's
+    equals the same combination of solutions, and every column meets the
+    tolerance against the sparse direct solve, as the single sources do
+    when solved alone."""
+    p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
+    H = oracle.setup_problem(p)
+    q0, q1 = p.Q[0], p.Q[1]
+    Q = np.stack([q0, q1, q0, q0 + 2 * q1])
+    X, it, rr, conv = H.fgmres(Q, tol=1e-9, restart=restart, maxit=300)
+    assert conv and rr.max() <= 1e-9 and np.isfinite(X).all()
+    scale = np.abs(X).max()
+    assert np.allclose(X[2], X[0], atol=1e-10 * scale)
+    assert np.allclose(X[3], X[0] + 2 * X[1], atol=1e-7 * scale)
+    A = sparse_H(2, p.n, p.h, p.m, p.gamma, p.omega, 0.0)
+    Xd = spl.splu(A.tocsc()).solve(Q.T).T
+    assert (np.linalg.norm(X - Xd, axis=1) / np.linalg.norm(Xd, axis=1)).max() < 1e-6
+    Xs, _, rs, cs = H.fgmres(p.Q, tol=1e-9, restart=restart, maxit=300)
+    assert cs
+    assert np.linalg.norm(X[:2] - Xs) / np.linalg.norm(Xs) < 1e-6
+    # the duplicate block takes no more cycles than the independent pair
+    itp = H.fgmres(p.Q, tol=1e-9, restart=restart, maxit=300)[1]
+    assert it <= itp + restart
 
 
 def test_fgmres_warm_start_is_a_shifted_cold_solve():
