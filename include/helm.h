@@ -53,7 +53,7 @@ typedef enum {
   HELM_ERR_OOM = 2,           /* device allocation failed                   */
   HELM_ERR_DEVICE = 3,        /* a HIP runtime call or kernel launch failed */
   HELM_ERR_NOT_CONVERGED = 4, /* U holds the last iterate, info is filled   */
-  HELM_ERR_BREAKDOWN = 5,     /* rank-deficient block, or a Krylov breakdown or divergence
+  HELM_ERR_BREAKDOWN = 5,     /* a block BiCGSTAB breakdown (e.g. dependent sources in one block), or a divergence
                                  that could not be handled (U holds the last good iterate) */
   HELM_ERR_NONFINITE = 6,     /* NaN/Inf in m, gamma or Q                    */
   HELM_ERR_UNSUPPORTED = 7    /* valid request the library does not support */
@@ -111,7 +111,12 @@ void helm_setup_desc_default(helm_setup_desc* d);
 typedef struct {
   int32_t restart;     /* m of FGMRES(m), 1..31 (paper: 5) */
   int32_t max_cycles;  /* cap on preconditioner applications (Arnoldi steps) */
-  int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs) */
+  int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs). FGMRES
+                          orthonormalises each new block by CholQR and deflates: a column
+                          whose part independent of the block's earlier columns is at most
+                          1e-6 of its norm is dropped from the basis (a second CholQR pass
+                          follows such a drop, or a near-dependence), so duplicate or
+                          dependent sources in one block are solved */
   int32_t warm_start;  /* 1: U holds an initial guess */
   int32_t reorth;      /* 0: one block Gram-Schmidt pass; 1: always two; 2: a second
                           pass only where the norm fell below half (block size 1) */

@@ -1795,7 +1795,10 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   const int ldh = (m + 1) * pb;
   const int64_t hstride = (int64_t)ldh * m * pb;
   const Geo g0 = L0.geo(P);
-  const double chol_tol = 1e-26;
+  // CholQR deflation: a column whose part independent of the columns
+  // before it has a squared norm at most 1e-12 of its own (1e-6 in norm),
+  // or 1e-26 of the group's largest, is dropped from the basis
+  const double chol_tol = 1e-26, chol_rtol = 1e-12;
 
   hipEvent_t e0, e1;
   HCHECK(hipEventCreate(&e0));
@@ -1825,6 +1828,33 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   std::vector<double> relres(Pa, 0.0);
   std::vector<int> hact(ng, 1);
   const double tol2 = tol * tol;
+  // W = Q R by CholQR (first pass into R, Q into Vb, W is consumed); where a
+  // group dropped a column or lost orthogonality, a second pass
+  // Q1 = Q2 R2 restores it and R becomes R2 R (R2 kept in the second
+  // Gram slot of G).
+  auto cholqr = [&](void*& Vb, c128* Rout) -> helm_status {
+    PtrList wl{};
+    wl.p[0] = W;
+    { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, wl, W, part, G, s); }
+    launch_cholqr_small(ng, pb, G, Rout, Rinv, dflag, chol_tol, chol_rtol, s);
+    hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+    { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, Vb, s); }
+    HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    bool ill = false;
+    for (int gg = 0; gg < ng; ++gg) ill = ill || (hact[gg] && hflag[gg]);
+    if (!ill) return HELM_OK;
+    c128* R2 = G + (size_t)P * pb;
+    PtrList ql{};
+    ql.p[0] = Vb;
+    { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, ql, Vb, part, G, s); }
+    launch_cholqr_small(ng, pb, G, R2, Rinv, dflag, chol_tol, chol_rtol, s);
+    hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
+    { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, ql, Rinv, W, s); }
+    std::swap(Vb, W);
+    launch_rmul_small(ng, pb, R2, Rout, s);
+    return HELM_OK;
+  };
   for (;;) {
     // true FP64 residual R = Q - H X into V0
     launch_fine(1, P64, P64, pv, P64, c->dim, g0, X, Qi, V[0], L0.dH, nullptr, L0.ih, s);
@@ -1867,31 +1897,23 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
     hipLaunchKernelGGL(k_set_active, dim3((ng + 255) / 256), dim3(256), 0, s, ng, pb, tol2, dr, dq, dact);
     // V0 S = R: CholQR, or plain normalisation for block size 1
     {
-      PtrList xl{};
-      xl.p[0] = V[0];
+      HCHECK(hipMemcpyAsync(hact.data(), dact, 4 * ng, hipMemcpyDeviceToHost, s));
       if (pb == 1) {
         // unnormalised basis: v~_0 = r with nu_0 = ||r|| (no scaling pass)
         launch_lazy_start(Pa, dr, dnu, S, dflag, s);
       } else {
-        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, xl, V[0], part, G, s); }
-        launch_cholqr_small(ng, pb, G, S, Rinv, dflag, chol_tol, s);
-        hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, xl, Rinv, W, s); }
+        // R = V_0 S; dependent residual columns (duplicate or combined
+        // sources) leave zero columns in V_0
         std::swap(V[0], W);
-      }
-      HCHECK(hipMemcpyAsync(hflag, dflag, 4 * ng, hipMemcpyDeviceToHost, s));
-      HCHECK(hipMemsetAsync(Hb, 0, 16 * (size_t)hstride * ng, s));
-      HCHECK(hipStreamSynchronize(s));
-      HCHECK(hipMemcpy(hact.data(), dact, 4 * ng, hipMemcpyDeviceToHost));
-      for (int gg = 0; gg < ng; ++gg)
-        if (hact[gg] && hflag[gg]) {
+        st = cholqr(V[0], S);
+        if (st != HELM_OK) {
           hipEventDestroy(e0);
           hipEventDestroy(e1);
-          return fail(HELM_ERR_BREAKDOWN,
-                      "rank-deficient residual block in group %d (duplicate or dependent right-hand sides); "
-                      "use block_size 1",
-                      gg);
+          return st;
         }
+      }
+      HCHECK(hipMemsetAsync(Hb, 0, 16 * (size_t)hstride * ng, s));
+      HCHECK(hipStreamSynchronize(s));
     }
     int jlast = -1;
     for (int j = 0; j < m; ++j) {
@@ -1953,12 +1975,12 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
           const int64_t ne = (int64_t)(j + 1) * Pa * pb;
           hipLaunchKernelGGL(helm::k_add_c128, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, ne, G, Gc);
         }
-        PtrList wl{};
-        wl.p[0] = W;
-        { Prof pr_(c, HELM_K_GRAM, s); launch_gram(P64, N, P, Pa, pb, 1, wl, W, part, G, s); }
-        launch_cholqr_small(ng, pb, G, Rm, Rinv, dflag, chol_tol, s);
-        hipLaunchKernelGGL(k_zero_inactive, dim3((P * pb + 255) / 256), dim3(256), 0, s, ng, pb, Pa, 1, dact, Rinv);
-        { Prof pr_(c, HELM_K_UPDATE, s); launch_block_update(1, P64, P64, N, P, Pa, pb, 1, wl, Rinv, V[j + 1], s); }
+        st = cholqr(V[j + 1], Rm);  // W = V_{j+1} H_{j+1,j}
+        if (st != HELM_OK) {
+          hipEventDestroy(e0);
+          hipEventDestroy(e1);
+          return st;
+        }
       }
       if (pb > 1) hipLaunchKernelGGL(k_hscatter, dim3(ng), dim3(256), 0, s, pb, j, Pa, Gc, Rm, Hb, ldh, hstride);
       launch_block_ls(ng, pb, j, Hb, ldh, hstride, S, Yc, 0, dest, lsw, dact, s);
@@ -1969,8 +1991,11 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       bool conv = true;
       for (int cidx = 0; cidx < Pa; ++cidx)
         if (hq[cidx] > 0 && hest[cidx] > tol * std::sqrt(hq[cidx])) conv = false;
+      // block size 1: a vanishing new basis vector ends the cycle (the
+      // Krylov space is invariant); larger blocks drop dependent columns
       bool brk = false;
-      for (int gg = 0; gg < ng; ++gg) brk = brk || (hact[gg] && hflag[gg]);
+      if (pb == 1)
+        for (int gg = 0; gg < ng; ++gg) brk = brk || (hact[gg] && hflag[gg]);
       jlast = j;
       if (conv || brk || j == m - 1 || cycles >= o.max_cycles) break;
     }

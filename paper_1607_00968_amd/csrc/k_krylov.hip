@@ -251,17 +251,30 @@ void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, i
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G = R^H R per group (one workgroup each), R upper, and R^-1.
+// Cholesky G = R^H R per group (one workgroup each), R upper, and R^-1, with
+// deflation of dependent columns. Column j's reduced diagonal d_j (the
+// squared norm of its part independent of the columns before it) is
+// compared with rtol times its own squared norm G_jj and with tol times the
+// largest G_aa: at or below either, column j is dropped (row j of R and
+// row and column j of R^-1 are zero, so the basis gets a zero column and
+// W = Q R holds for column j to within sqrt(d_j)). flag[g] = 1 when a
+// column was dropped or a kept one has d_j < 1e-4 G_jj (the product
+// W R^-1 then has lost orthogonality of order eps G_jj / d_j, and a second
+// pass is advised), else 0.
 // G layout: Gm[a][b] = G[(g*pb + b)*pb + a]. Outputs: R[g][a][b] row-major,
 // RinvC in update layout: RinvC[(g*pb + b)*pb + a] = Rinv[a][b].
 // ---------------------------------------------------------------------------
+constexpr int CHOL_MAXPB = 64;
 __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __restrict__ G, c128* __restrict__ R,
-                                                      c128* __restrict__ RinvC, int* __restrict__ flag, double tol) {
+                                                      c128* __restrict__ RinvC, int* __restrict__ flag, double tol,
+                                                      double rtol) {
   extern __shared__ cx<double> sm[];
   cx<double>* A = sm;             // pb x pb working copy (upper part becomes R)
   cx<double>* Ri = sm + pb * pb;  // pb x pb inverse
   __shared__ double dmax;
-  __shared__ int bad;
+  __shared__ double gd[CHOL_MAXPB];
+  __shared__ int drp[CHOL_MAXPB];
+  __shared__ int ill;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   for (int e = tid; e < pb * pb; e += blockDim.x) {
@@ -269,22 +282,31 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __rest
     A[e] = tcx(G[((int64_t)g * pb + b) * pb + a]);
   }
   if (tid == 0) {
-    bad = 0;
+    ill = 0;
     dmax = 0.0;
   }
   __syncthreads();
   if (tid == 0)
-    for (int a = 0; a < pb; ++a) dmax = fmax(dmax, A[a * pb + a].re);
+    for (int a = 0; a < pb; ++a) {
+      gd[a] = A[a * pb + a].re;
+      dmax = fmax(dmax, gd[a]);
+    }
   __syncthreads();
   for (int j = 0; j < pb; ++j) {
-    // A[j][j] <- sqrt(A[j][j]) (already reduced by previous rows)
+    // A[j][j] <- sqrt(A[j][j]) (already reduced by previous rows), or drop
     if (tid == 0) {
       const double d = A[j * pb + j].re;
-      if (!(d > tol * dmax) || !(dmax > 0.0)) bad = 1;
-      A[j * pb + j] = {sqrt(fmax(d, 0.0)), 0.0};
+      const int dr = !(d > tol * dmax) || !(d > rtol * gd[j]);
+      drp[j] = dr;
+      if (dr || d < 1e-4 * gd[j]) ill = 1;
+      A[j * pb + j] = {dr ? 0.0 : sqrt(d), 0.0};
     }
     __syncthreads();
-    if (bad) break;
+    if (drp[j]) {
+      for (int b = j + 1 + tid; b < pb; b += blockDim.x) A[j * pb + b] = {0.0, 0.0};
+      __syncthreads();
+      continue;  // a zero row of R changes no later column
+    }
     const double inv = 1.0 / A[j * pb + j].re;
     for (int b = j + 1 + tid; b < pb; b += blockDim.x) A[j * pb + b] = inv * A[j * pb + b];
     __syncthreads();
@@ -298,22 +320,19 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __rest
     }
     __syncthreads();
   }
-  if (bad) {
-    if (tid == 0) flag[g] = 1;
-    for (int e = tid; e < pb * pb; e += blockDim.x) {
-      R[(int64_t)g * pb * pb + e] = c128{0.0, 0.0};
-      RinvC[(int64_t)g * pb * pb + e] = c128{0.0, 0.0};
-    }
-    return;
-  }
-  if (tid == 0) flag[g] = 0;
-  // Ri = R^-1 by back substitution, one column per lane
+  if (tid == 0) flag[g] = ill;
+  // Ri = R^-1 on the kept columns by back substitution, one column per lane;
+  // rows and columns of dropped columns are zero (a dropped l contributes
+  // nothing to the sums below because Ri[l][b] = 0)
   for (int b = tid; b < pb; b += blockDim.x) {
     for (int a = pb - 1; a >= 0; --a) {
+      if (a > b || drp[a] || drp[b]) {
+        Ri[a * pb + b] = {0.0, 0.0};
+        continue;
+      }
       cx<double> s = {a == b ? 1.0 : 0.0, 0.0};
       for (int l = a + 1; l <= b; ++l) s = s - A[a * pb + l] * Ri[l * pb + b];
-      const double inv = 1.0 / A[a * pb + a].re;
-      Ri[a * pb + b] = a > b ? cx<double>{0.0, 0.0} : inv * s;
+      Ri[a * pb + b] = (1.0 / A[a * pb + a].re) * s;
     }
   }
   __syncthreads();
@@ -324,9 +343,36 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __rest
   }
 }
 
-void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, hipStream_t s) {
+void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, double rtol,
+                         hipStream_t s) {
+  if (pb < 1 || pb > CHOL_MAXPB) fatal_combo("launch_cholqr_small");
   const size_t shm = sizeof(cx<double>) * 2 * pb * pb;
-  hipLaunchKernelGGL(k_cholqr_small, dim3(ng), dim3(256), shm, s, pb, G, R, Rinv, flag, tol);
+  hipLaunchKernelGGL(k_cholqr_small, dim3(ng), dim3(256), shm, s, pb, G, R, Rinv, flag, tol, rtol);
+}
+
+// R <- R2 R per group (both upper triangular, row-major [g][a][b]): the
+// factor of a block after a second CholQR pass (W = Q1 R, Q1 = Q2 R2).
+__global__ __launch_bounds__(256) void k_rmul_small(int pb, const c128* __restrict__ R2, c128* __restrict__ R) {
+  extern __shared__ cx<double> sm[];
+  cx<double>* A = sm;
+  cx<double>* B = sm + pb * pb;
+  const int64_t o = (int64_t)blockIdx.x * pb * pb;
+  for (int e = threadIdx.x; e < pb * pb; e += blockDim.x) {
+    A[e] = tcx(R2[o + e]);
+    B[e] = tcx(R[o + e]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < pb * pb; e += blockDim.x) {
+    const int a = e / pb, b = e % pb;
+    cx<double> acc = {0.0, 0.0};
+    for (int l = a; l <= b; ++l) cfmac(acc, A[a * pb + l], B[l * pb + b]);
+    R[o + e] = fcx(acc);
+  }
+}
+
+void launch_rmul_small(int ng, int pb, const c128* R2, c128* R, hipStream_t s) {
+  const size_t shm = sizeof(cx<double>) * 2 * pb * pb;
+  hipLaunchKernelGGL(k_rmul_small, dim3(ng), dim3(256), shm, s, pb, R2, R);
 }
 
 // ---------------------------------------------------------------------------

@@ -129,7 +129,9 @@ void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, i
 // Per group g < ng: Cholesky G_g = R^H R (pb x pb, G layout [c][a] of one X),
 // R and Rinv written [g][pb][pb] row-major (row a, col b). flag[g] = 1 on
 // breakdown (pivot <= tol * max diagonal).
-void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, hipStream_t s);
+void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, double rtol,
+                         hipStream_t s);
+void launch_rmul_small(int ng, int pb, const c128* R2, c128* R, hipStream_t s);
 // Block FGMRES least squares per group: Hbar_g is ((j+2)pb x (j+1)pb),
 // column-major with leading dimension ldh, stored at Hb + g*hstride; S_g the
 // pb x pb first block (row-major). Writes Y_g ((j+1)pb x pb, column-major
