@@ -111,7 +111,7 @@ void helm_setup_desc_default(helm_setup_desc* d);
 typedef struct {
   int32_t restart;     /* m of FGMRES(m), 1..31 (paper: 5) */
   int32_t max_cycles;  /* cap on preconditioner applications (Arnoldi steps) */
-  int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 32 (0 = nrhs). FGMRES
+  int32_t block_size;  /* RHS per Krylov block; must divide nrhs, <= 64 (0 = nrhs). FGMRES
                           orthonormalises each new block by CholQR and deflates: a column
                           whose part independent of the block's earlier columns is at most
                           1e-6 of its norm is dropped from the basis (a second CholQR pass

@@ -1711,7 +1711,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
   const int m = o.restart;
   if (m < 1 || m >= MAXPTR) return fail(HELM_ERR_INVALID_ARG, "restart must be 1..%d", MAXPTR - 1);
   const int pb = o.block_size <= 0 ? nrhs : o.block_size;
-  if (pb < 1 || nrhs % pb != 0 || pb > 32) return fail(HELM_ERR_INVALID_ARG, "block_size must divide nrhs and be <= 32");
+  if (pb < 1 || nrhs % pb != 0 || pb > 64) return fail(HELM_ERR_INVALID_ARG, "block_size must divide nrhs and be <= 64");
   if (o.max_cycles < 1) return fail(HELM_ERR_INVALID_ARG, "max_cycles must be >= 1");
   if (o.reorth < 0 || o.reorth > 2) return fail(HELM_ERR_INVALID_ARG, "reorth must be 0, 1 or 2");
   if (o.graph < 0 || o.graph > 2) return fail(HELM_ERR_INVALID_ARG, "graph must be 0, 1 or 2");

@@ -22,8 +22,10 @@ __device__ inline c128 fcd(const cx<double>& v) { return c128{v.re, v.im}; }
 // X_g = sgn * A_g^-1 B_g per group (one workgroup each) by Gaussian
 // elimination with partial pivoting; an inactive group, or a pivot below
 // 1e-13 of the largest entry of A_g (flag[g] = 1), gives X_g = 0. The group
-// size is at most BICG_MAXPB (the block-size limit of the solver).
-constexpr int BICG_MAXPB = 32;
+// size is at most BICG_MAXPB (the block-size limit of the solver); the four
+// working matrices take 128 KB of static LDS at 64 columns (gfx950 gives a
+// workgroup up to 160 KB).
+constexpr int BICG_MAXPB = 64;
 __global__ __launch_bounds__(64) void k_bicg_solve(int pb, double sgn, const c128* __restrict__ A,
                                                    const c128* __restrict__ B, c128* __restrict__ X,
                                                    const int* __restrict__ act, int* __restrict__ flag) {

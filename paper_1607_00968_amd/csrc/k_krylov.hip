@@ -264,13 +264,14 @@ void launch_block_update(int mode, Prec px, Prec py, int64_t N, int ld, int P, i
 // G layout: Gm[a][b] = G[(g*pb + b)*pb + a]. Outputs: R[g][a][b] row-major,
 // RinvC in update layout: RinvC[(g*pb + b)*pb + a] = Rinv[a][b].
 // ---------------------------------------------------------------------------
+// The working matrices are static LDS sized for the largest group (2 x 64 KB
+// at 64 columns; gfx950 gives a workgroup up to 160 KB).
 constexpr int CHOL_MAXPB = 64;
 __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __restrict__ G, c128* __restrict__ R,
                                                       c128* __restrict__ RinvC, int* __restrict__ flag, double tol,
                                                       double rtol) {
-  extern __shared__ cx<double> sm[];
-  cx<double>* A = sm;             // pb x pb working copy (upper part becomes R)
-  cx<double>* Ri = sm + pb * pb;  // pb x pb inverse
+  __shared__ cx<double> A[CHOL_MAXPB * CHOL_MAXPB];   // pb x pb working copy (upper part becomes R)
+  __shared__ cx<double> Ri[CHOL_MAXPB * CHOL_MAXPB];  // pb x pb inverse
   __shared__ double dmax;
   __shared__ double gd[CHOL_MAXPB];
   __shared__ int drp[CHOL_MAXPB];
@@ -346,16 +347,14 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int pb, const c128* __rest
 void launch_cholqr_small(int ng, int pb, const c128* G, c128* R, c128* Rinv, int* flag, double tol, double rtol,
                          hipStream_t s) {
   if (pb < 1 || pb > CHOL_MAXPB) fatal_combo("launch_cholqr_small");
-  const size_t shm = sizeof(cx<double>) * 2 * pb * pb;
-  hipLaunchKernelGGL(k_cholqr_small, dim3(ng), dim3(256), shm, s, pb, G, R, Rinv, flag, tol, rtol);
+  hipLaunchKernelGGL(k_cholqr_small, dim3(ng), dim3(256), 0, s, pb, G, R, Rinv, flag, tol, rtol);
 }
 
 // R <- R2 R per group (both upper triangular, row-major [g][a][b]): the
 // factor of a block after a second CholQR pass (W = Q1 R, Q1 = Q2 R2).
 __global__ __launch_bounds__(256) void k_rmul_small(int pb, const c128* __restrict__ R2, c128* __restrict__ R) {
-  extern __shared__ cx<double> sm[];
-  cx<double>* A = sm;
-  cx<double>* B = sm + pb * pb;
+  __shared__ cx<double> A[CHOL_MAXPB * CHOL_MAXPB];
+  __shared__ cx<double> B[CHOL_MAXPB * CHOL_MAXPB];
   const int64_t o = (int64_t)blockIdx.x * pb * pb;
   for (int e = threadIdx.x; e < pb * pb; e += blockDim.x) {
     A[e] = tcx(R2[o + e]);
@@ -371,8 +370,8 @@ __global__ __launch_bounds__(256) void k_rmul_small(int pb, const c128* __restri
 }
 
 void launch_rmul_small(int ng, int pb, const c128* R2, c128* R, hipStream_t s) {
-  const size_t shm = sizeof(cx<double>) * 2 * pb * pb;
-  hipLaunchKernelGGL(k_rmul_small, dim3(ng), dim3(256), shm, s, pb, R2, R);
+  if (pb < 1 || pb > CHOL_MAXPB) fatal_combo("launch_rmul_small");
+  hipLaunchKernelGGL(k_rmul_small, dim3(ng), dim3(256), 0, s, pb, R2, R);
 }
 
 // ---------------------------------------------------------------------------

@@ -255,6 +255,43 @@ def test_duplicate_and_dependent_sources_in_one_block(precision):
         assert rel(Uh[c], Uh1[c]) < 1e-5, c
 
 
+_B64 = {}
+
+
+def _block64_oracle(p, Qb):
+    """The oracle's block FGMRES(5) solution of the 64-column block (computed
+    once for the parametrised cases)."""
+    if "X" not in _B64:
+        Xo, it, rr, conv = oracle.setup_problem(p).fgmres(Qb, tol=1e-10, restart=5, maxit=400)
+        assert conv
+        _B64["X"] = Xo
+    return _B64["X"]
+
+
+@pytest.mark.parametrize("method,precision", [("fgmres", "fp64"), ("fgmres", "mixed"), ("bicgstab", "fp64")])
+def test_block_of_64_columns(method, precision):
+    """One block of 64 right-hand sides (the largest block size; the paper's
+    tables go up to 64 sources): every column meets the tolerance by the
+    oracle's FP64 operator and matches the oracle's block FGMRES solution
+    (tolerance 1e-10, same block of 64) within 1e-5 at a GPU tolerance of
+    1e-8."""
+    p = synth.gradient_2d(n=64, nsrc=(2,), levels=3)
+    rng = np.random.default_rng(64)
+    Qb = rng.standard_normal((64, p.N)) + 1j * rng.standard_normal((64, p.N))
+    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, levels=3, precision=precision)
+    Q = dev(Qb)
+    U = torch.zeros_like(Q)
+    info = pk.helm_solve_block(hd, Q, U, tol=1e-8, restart=5, block_size=64, method=method)
+    assert info["converged_all"]
+    Uh = host(U)
+    g = oracle.grid(p.dim, p.n, p.h)
+    R = Qb - oracle.apply_fine(g, p.m, p.gamma, p.omega, 0.0, Uh)
+    assert (np.linalg.norm(R, axis=1) / np.linalg.norm(Qb, axis=1)).max() <= 1e-8
+    Xo = _block64_oracle(p, Qb)
+    err = np.linalg.norm(Uh - Xo, axis=1) / np.linalg.norm(Xo, axis=1)
+    assert err.max() < 1e-5, err.max()
+
+
 def test_nonfinite_rhs_rejected():
     p = synth.gradient_2d(n=32, nsrc=(2,), levels=3)
     Qn = p.Q.copy()
