@@ -344,3 +344,55 @@ def test_bicgstab_unmutated_copy_passes(tmp_path):
     finally:
         bpins.ob = saved
         sys.modules.pop("oracle.bicgstab_copy", None)
+
+
+# Planted mistakes in the oracle's sensitivity products and 16-bit storage
+# (oracle/sens.py).
+import test_oracle_sens as spins  # noqa: E402
+
+SENS_MUTANTS = [
+    ("damping factor with the wrong sign", "(1.0 - 1j * hier._gamma)", "(1.0 + 1j * hier._gamma)",
+     [lambda: spins.test_jvp_equals_central_difference(spins.setup_problem())]),
+    ("adjoint products without the field's conjugate", "np.conj(dH_dm_factor(hier)[None, :] * U) * Y",
+     "dH_dm_factor(hier)[None, :] * U * Y", [lambda: spins.test_adjoint_identities(spins.setup_problem())]),
+    ("adjoint solve without the conjugations", 'return np.conj(solve(hier, np.conj(B), tol, "H"))',
+     'return solve(hier, B, tol, "H")', [lambda: spins.test_adjoint_identities(spins.setup_problem())]),
+    ("16-bit scale from the modulus", "np.max(np.maximum(np.abs(U.real), np.abs(U.imag)), axis=1)",
+     "np.max(np.abs(U), axis=1)", [spins.test_pack16_bounds]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", SENS_MUTANTS, ids=[m[0] for m in SENS_MUTANTS])
+def test_sens_pins_catch_planted_mistake(tmp_path, name, old, new, checks):
+    with open(os.path.join(SRC, "sens.py")) as fh:
+        text = fh.read()
+    changed = plant(text, old, new, 0)
+    assert changed != text
+    mod = _load_module_copy(tmp_path, "sens.py", changed, "sens_mutant")
+    saved = spins.sens
+    spins.sens = mod
+    caught = []
+    try:
+        for check in checks:
+            try:
+                check()
+            except AssertionError as e:
+                caught.append(str(e)[:80])
+    finally:
+        spins.sens = saved
+        sys.modules.pop("oracle.sens_mutant", None)
+    assert caught, f"no pin caught the planted mistake: {name}"
+
+
+def test_sens_unmutated_copy_passes(tmp_path):
+    with open(os.path.join(SRC, "sens.py")) as fh:
+        mod = _load_module_copy(tmp_path, "sens.py", fh.read(), "sens_copy")
+    saved = spins.sens
+    spins.sens = mod
+    try:
+        for m in SENS_MUTANTS:
+            for check in m[3]:
+                check()
+    finally:
+        spins.sens = saved
+        sys.modules.pop("oracle.sens_copy", None)

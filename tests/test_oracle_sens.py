@@ -20,8 +20,18 @@ from oracle import sens
 RNG = np.random.default_rng(4242)
 
 
+_SETUP = []
+
+
 @pytest.fixture(scope="module")
 def setup():
+    return setup_problem()
+
+
+def setup_problem():
+    """The pins' 2D problem, its fields and a model perturbation (built once)."""
+    if _SETUP:
+        return _SETUP[0]
     p = synth.gradient_2d(n=48, nsrc=(2,), levels=3)
     g = oracle.grid(p.dim, p.n, p.h)
     h = oracle.Hierarchy(g, p.m, p.gamma, p.omega, p.shift, 3)
@@ -29,7 +39,8 @@ def setup():
     # a smooth real model perturbation
     x = np.linspace(0, 1, p.n[0] - 1)
     dm = (np.sin(3 * np.pi * x)[:, None] * np.cos(2 * np.pi * x)[None, :]).ravel() * 0.05 * p.m.max()
-    return p, g, h, U, dm
+    _SETUP.append((p, g, h, U, dm))
+    return _SETUP[0]
 
 
 def test_jvp_equals_central_difference(setup):
