@@ -592,15 +592,8 @@ __device__ inline void ld_u(const S* p, bool ok, int x, int y, int z, const SC* 
   }
 }
 
-// Waves per SIMD the 16-row tile asks the compiler for: 8 (at most 64 VGPRs,
-// two 1024-lane workgroups per CU) for the FP32 sweeps, which fit without
-// spilling (the compiler's resource remarks are checked for scratch).
-template <class S, class T, int TY, int PRO> constexpr int t16_waves() {
-  return TY == 16 && PRO != 1 && sizeof(S) == 8 && sizeof(T) == 4 ? 8 : 1;
-}
-
 template <class S, class T, int MODE, int TY, class SC = S, int PRO = 0>
-__global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
+__global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb, const S* __restrict__ u,
                                                       const S* __restrict__ f, S* __restrict__ out,
                                                       const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw,
                                                       T ihx, T ihy, T ihz, const SC* __restrict__ ec, Geo gc) {
@@ -709,9 +702,23 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
   const S* up = ub + ((int64_t)z0 * plane + icol) * g.P + c;
   const S* rpp = ub + ((int64_t)z0 * plane + rcol) * g.P + c;
   const S* fp = f + ((int64_t)z0 * plane + icol) * g.P + c;
-  ld_u<K, S, SC, T, PRO, LDSC>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, dw, (int64_t)(z0 - 1) * plane + icol,
-                               c, um, lc);
-  ld_u<K, S, SC, T, PRO, LDSC>(up, inb, x, y, z0, ec, gc, dw, (int64_t)z0 * plane + icol, c, uc, lc);
+  // RAWC (PRO = 2): the own column keeps f itself at z and z + 1 (uc, un)
+  // with the point's w D^-1 (wc, wn; 0 outside the grid), loaded one plane
+  // ahead, and the zero-guess sweep's value w D^-1 f at z - 1 (um). That
+  // value is formed where it is used (the same product ld_u forms, so the
+  // results are unchanged), and f(z) needs no second load.
+  constexpr bool RAWC = PRO == 2 && !PF;
+  cx<T> wc{}, wn{};
+  if (RAWC) {
+    ld_u<K, S, SC, T, PRO, LDSC>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, dw,
+                                 (int64_t)(z0 - 1) * plane + icol, c, um, lc);
+    ldKz<K, S, T>(up, inb, uc);
+    if (inb) wc = dw[(int64_t)z0 * plane + icol];
+  } else {
+    ld_u<K, S, SC, T, PRO, LDSC>(up - sz, inb && z0 > 0, x, y, z0 - 1, ec, gc, dw,
+                                 (int64_t)(z0 - 1) * plane + icol, c, um, lc);
+    ld_u<K, S, SC, T, PRO, LDSC>(up, inb, x, y, z0, ec, gc, dw, (int64_t)z0 * plane + icol, c, uc, lc);
+  }
   if (PF) {
     ld_u<K, S, SC, T, PRO>(up + sz, inb && z0 + 1 < g.nz, x, y, z0 + 1, ec, gc, dw, (int64_t)(z0 + 1) * plane + icol,
                            c, un);
@@ -733,7 +740,20 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
   int lo = me - RYS;
   asm volatile("" : "+v"(lo));
   cx<LE>* const nb = sm + lo;
+  // When each plane's other operands are issued (loads complete in issue
+  // order, so an operand issued before the u loads is waited for with them):
+  //  EF: f, D and w D^-1 right after the plane's LDS stores, so that their
+  //      latency overlaps the barrier (sweeps and residuals; measured at
+  //      192^3 x 64: the plain sweep 2.45 -> 2.25 ms, the prolongation-fused
+  //      one 2.42 -> 2.32 ms; issued with the u loads instead, the fused one
+  //      took 2.63 ms);
+  //  EF2: D ahead of the u loads (RAWC, which needs neither f nor w D^-1
+  //      after the barrier: nothing is loaded there; 1.82 -> 1.76 ms).
+  constexpr bool EF = !RAWC && !PF && MODE != 0;
+  constexpr bool EF2 = RAWC;
   for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
+    cx<T> de{}, we{};
+    if (EF2 && inb) de = dg[(int64_t)z * plane + icol];
     if (PF) {
       const bool more = z + 1 < z1;
       ld_u<K, S, SC, T, PRO>(up + 2 * sz, inb && z + 2 < g.nz, x, y, z + 2, ec, gc, dw,
@@ -742,8 +762,14 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
                              rn);
       if (MODE != 0) ldKz<K, S, T>(fp + sz, inb && more, fn);
     } else {
-      ld_u<K, S, SC, T, PRO, LDSC>(up + sz, inb && z + 1 < g.nz, x, y, z + 1, ec, gc, dw,
-                                   (int64_t)(z + 1) * plane + icol, c, un, lc);
+      if (RAWC) {
+        const bool okn = inb && z + 1 < g.nz;
+        ldKz<K, S, T>(up + sz, okn, un);
+        wn = okn ? dw[(int64_t)(z + 1) * plane + icol] : cx<T>{};
+      } else {
+        ld_u<K, S, SC, T, PRO, LDSC>(up + sz, inb && z + 1 < g.nz, x, y, z + 1, ec, gc, dw,
+                                     (int64_t)(z + 1) * plane + icol, c, un, lc);
+      }
       ld_u<K, S, SC, T, PRO, LDSC>(rpp, rin, rx, ry, z, ec, gc, dw, (int64_t)z * plane + rcol, c, rc, lc);
       // the coarse plane the next step adds (the upper parent of z + 2) goes
       // to the slot no plane of this step uses; the barrier below orders it
@@ -754,17 +780,29 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
 #pragma unroll
       for (int k = 0; k < K; ++k) sm[ro + k] = cx<LE>{(LE)rc[k].re, (LE)rc[k].im};
     }
+    // the own point's u at z (RAWC: formed from f, where it is used)
 #pragma unroll
-    for (int k = 0; k < K; ++k) nb[RYS + k] = cx<LE>{(LE)uc[k].re, (LE)uc[k].im};
+    for (int k = 0; k < K; ++k) {
+      const cx<T> v = RAWC ? wc * uc[k] : uc[k];
+      nb[RYS + k] = cx<LE>{(LE)v.re, (LE)v.im};
+    }
+    if (EF && inb) {
+      const int64_t ir = (int64_t)z * plane + icol;
+      ldK<K, S, T>(f + ir * g.P + c, fc);
+      de = dg[ir];
+      if (MODE == 2) we = dw[ir];
+    }
     __syncthreads();
     if (inb) {
       const int64_t ir = (int64_t)z * plane + icol;
-      const cx<T> d = dg[ir];
+      const cx<T> d = EF || EF2 ? de : dg[ir];
       cx<T> acc[K], sum[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        acc[k] = d * uc[k];
-        sum[k] = ihz * (um[k] + un[k]) + ihy * (wid<T>(nb[k]) + wid<T>(nb[2 * RYS + k]));
+        const cx<T> us = RAWC ? wc * uc[k] : uc[k];
+        const cx<T> zp = RAWC ? wn * un[k] : un[k];
+        acc[k] = d * us;
+        sum[k] = ihz * (um[k] + zp) + ihy * (wid<T>(nb[k]) + wid<T>(nb[2 * RYS + k]));
         sum[k] = sum[k] + ihx * wid<T>(nb[RYS - RX + k]);
         sum[k] = sum[k] + ihx * wid<T>(nb[RYS + RX + k]);
         acc[k] = acc[k] - sum[k];
@@ -773,17 +811,21 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
       if (MODE == 0) {
         stK<K, S, T>(out + o, acc);
       } else {
-        // f after the barrier (issuing it with the u loads was measured
-        // slower: it lengthens the wait before the LDS stores)
-        if (!PF) ldK<K, S, T>(f + o, fc);
+        // f: RAWC holds it, EF has issued it, PF prefetched it; else now
+        if (RAWC) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) fc[k] = uc[k];
+        } else if (!PF && !EF && !EF2) {
+          ldK<K, S, T>(f + o, fc);
+        }
         cx<T> res[K];
         if (MODE == 1) {
 #pragma unroll
           for (int k = 0; k < K; ++k) res[k] = fc[k] - acc[k];
         } else {
-          const cx<T> w = dw[ir];
+          const cx<T> w = RAWC ? wc : (EF || EF2 ? we : dw[ir]);
 #pragma unroll
-          for (int k = 0; k < K; ++k) res[k] = uc[k] + w * (fc[k] - acc[k]);
+          for (int k = 0; k < K; ++k) res[k] = (RAWC ? wc * uc[k] : uc[k]) + w * (fc[k] - acc[k]);
         }
         stK<K, S, T>(out + o, res);
       }
@@ -791,7 +833,7 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      um[k] = uc[k];
+      um[k] = RAWC ? wc * uc[k] : uc[k];
       uc[k] = un[k];
       if (PF) {
         un[k] = unn[k];
@@ -799,6 +841,7 @@ __global__ __launch_bounds__(64 * TY, (t16_waves<S, T, TY, PRO>())) void k_fine_
         fc[k] = fn[k];
       }
     }
+    if (RAWC) wc = wn;
   }
 }
 
