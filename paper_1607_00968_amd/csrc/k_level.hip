@@ -986,6 +986,16 @@ __global__ __launch_bounds__(512) void k_resid_restrict(Geo gf, Geo gc, int ncg,
 #pragma unroll
       for (int k = 0; k < K; ++k) su[o + k] = uc[i][k];
     }
+    // f and D of the plane are issued before the barrier, so that their
+    // latency overlaps it (as in the LDS-tiled sweeps)
+    cx<T> fv[NT][K], dv[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      if (threadIdx.x + 512 * i >= NRES || !rin[i]) continue;
+      const int64_t ir = (int64_t)zf * plane + rcol[i];
+      dv[i] = dg[ir];
+      ldK<K, S, T>(f + ir * gf.P + c, fv[i]);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -993,10 +1003,7 @@ __global__ __launch_bounds__(512) void k_resid_restrict(Geo gf, Geo gc, int ncg,
       cx<T> res[K];
       if (rin[i]) {
         const int o = ((ry[i] + 1) * RU + rx[i] + 1) * CG + sl * K;
-        const int64_t ir = (int64_t)zf * plane + rcol[i];
-        const cx<T> d = dg[ir];
-        cx<T> fv[K];
-        ldK<K, S, T>(f + ir * gf.P + c, fv);
+        const cx<T> d = dv[i];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           cx<T> acc = d * uc[i][k];
@@ -1004,7 +1011,7 @@ __global__ __launch_bounds__(512) void k_resid_restrict(Geo gf, Geo gc, int ncg,
           sum = sum + ihx * su[o - CG + k];
           sum = sum + ihx * su[o + CG + k];
           acc = acc - sum;
-          res[k] = fv[k] - acc;
+          res[k] = fv[i][k] - acc;
         }
       } else {
 #pragma unroll
