@@ -153,13 +153,28 @@ __global__ __launch_bounds__(256) void k_conv3(ConvArgs a) {
 constexpr int CT_X = 8, CT_Y = 8, CT_Z = 4;
 constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_V = CH_X * CH_Y * CH_Z;
 constexpr int CCH = 16;
+// LDS layout of the halo and the weights, chosen for the A and B fragment
+// reads (8 B per lane; a 32-lane pass spans 16 rows of 32 B for two lane
+// groups kg): an A fragment's 16 voxels are two x-rows of 8, 10 voxels apart,
+// and at 32 B per voxel both rows fell on the same 32 banks. Each halo row of
+// CH_X voxels is therefore followed by 16 B of padding, which moves the
+// second row to the other 32 banks. A B fragment's 16 weight rows (32 B
+// each) wrapped the same way; rows 8..15 of every 16 keep their two 16-B
+// halves swapped. The values and the MFMA order are unchanged.
+constexpr int CH_PAD_U4 = CH_V * 2 + CH_Y * CH_Z;  // halo size in 16-B units
+__device__ inline int halo_u4(int hv) { return hv * 2 + hv / CH_X; }
+// bf16 offset of voxel v (row r = v / CH_X) of the padded halo
+__device__ inline int halo_el(int v, int r) { return v * CCH + r * 8; }
+// bf16 offset of 8-B chunk kg of weight row `row` (rows 8..15 of each 16 swapped)
+__device__ inline int wrow_el(int row, int kg) { return row * CCH + 4 * (kg ^ (((row >> 3) & 1) << 1)); }
+__device__ inline int wrow_u4(int row, int half) { return row * 2 + (half ^ ((row >> 3) & 1)); }
 
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
                                                    int64_t per) {
   extern __shared__ uint4 lds_u4[];
-  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH]
-  bf16* ws = xs + CH_V * CCH;                  // [9][N][CCH]
+  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH], rows padded
+  bf16* ws = xs + CH_PAD_U4 * 8;               // [9][N][CCH]
   constexpr int N = NT * 16;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= ntiles) return;  // whole workgroup leaves together
@@ -198,14 +213,14 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty,
           if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
             val = *reinterpret_cast<const uint4*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi +
                                                   a.offi + c0 + half * 8);
-          lds_u4[hv * 2 + half] = val;
+          lds_u4[halo_u4(hv) + half] = val;
         }
       }
       // weights of the taps of this plane: rows (tap, n), 16 channels each
       for (int e = threadIdx.x; e < 9 * N * 2; e += 256) {
         const int row = e >> 1, half = e & 1;
         const int tap = pz * 9 + row / N, n = row % N;
-        lds_u4[CH_V * 2 + e] =
+        lds_u4[CH_PAD_U4 + wrow_u4(row, half)] =
             *reinterpret_cast<const uint4*>(a.W + ((int64_t)tap * N + n) * a.Cin + c0 + half * 8);
       }
       __syncthreads();
@@ -216,10 +231,11 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty,
         short4_ Bv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-          Bv[nt] = *reinterpret_cast<const short4_*>(ws + (tt * N + nt * 16 + ml) * CCH + kg * 4);
+          Bv[nt] = *reinterpret_cast<const short4_*>(ws + wrow_el(tt * N + nt * 16 + ml, kg));
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-          const short4_ A = *reinterpret_cast<const short4_*>(xs + (hb[mt] + toff) * CCH + kg * 4);
+          const int v = hb[mt] + toff;
+          const short4_ A = *reinterpret_cast<const short4_*>(xs + halo_el(v, v / CH_X) + kg * 4);
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
             acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv[nt], acc[mt][nt], 0, 0, 0);
@@ -256,8 +272,8 @@ template <int NT, int FLIP>
 __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
                                                   int64_t per) {
   extern __shared__ uint4 lds_u4[];
-  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH]
-  bf16* ws = xs + CH_V * CCH;                  // [27][N][CCH]
+  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH], rows padded
+  bf16* ws = xs + CH_PAD_U4 * 8;               // [27][N][CCH]
   constexpr int N = NT * 16;
   constexpr int SG = FLIP ? -1 : 1;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -290,26 +306,29 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
       if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
         val = *reinterpret_cast<const uint4*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi +
                                               a.offi + c0 + half * 8);
-      lds_u4[hv * 2 + half] = val;
+      lds_u4[halo_u4(hv) + half] = val;
     }
     for (int e = threadIdx.x; e < 27 * N * 2; e += 256) {
       const int row = e >> 1, half = e & 1;  // row = tap * N + n
-      lds_u4[CH_V * 2 + e] = *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
+      lds_u4[CH_PAD_U4 + wrow_u4(row, half)] =
+          *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
     }
     __syncthreads();
 #pragma unroll 1
     for (int txy = 0; txy < 9; ++txy) {
       const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
       const int hoff = SG * dxt + CH_X * (SG * dyt);
+      const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
       short4_ Bt[3][NT];  // z taps dz = -1, 0, 1
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-          Bt[k][nt] = *reinterpret_cast<const short4_*>(ws + ((txy + 9 * k) * N + nt * 16 + ml) * CCH + kg * 4);
+          Bt[k][nt] = *reinterpret_cast<const short4_*>(ws + wrow_el((txy + 9 * k) * N + nt * 16 + ml, kg));
 #pragma unroll
       for (int p = 0; p < CH_Z; ++p) {
-        const short4_ A = *reinterpret_cast<const short4_*>(xs + (hxy + hoff + CH_X * CH_Y * p) * CCH + kg * 4);
+        const short4_ A = *reinterpret_cast<const short4_*>(
+            xs + halo_el(hxy + hoff + CH_X * CH_Y * p, rxy + CH_Y * p) + kg * 4);
 #pragma unroll
         for (int z = 0; z < CT_Z; ++z) {
           const int dzin = p - 1 - z;  // input plane offset seen from output plane z
@@ -346,7 +365,7 @@ static void conv3_zr_launch(const ConvArgs& a, hipStream_t s) {
   const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
   const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
   const int64_t per = (ntiles + 7) / 8;
-  const size_t lds = sizeof(bf16) * (CH_V * CCH + 27 * NT * 16 * CCH);
+  const size_t lds = sizeof(bf16) * (CH_PAD_U4 * 8 + 27 * NT * 16 * CCH);
   hipLaunchKernelGGL((k_conv3_zr<NT, FLIP>), dim3((unsigned)(8 * per)), dim3(256), lds, s, a, ntx, nty, ntz, ntiles,
                      per);
 }
@@ -436,7 +455,7 @@ static void conv3_lds_launch(const ConvArgs& a, hipStream_t s) {
   const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
   const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
   const int64_t per = (ntiles + 7) / 8;
-  const size_t lds = sizeof(bf16) * (CH_V * CCH + 9 * NT * 16 * CCH);
+  const size_t lds = sizeof(bf16) * (CH_PAD_U4 * 8 + 9 * NT * 16 * CCH);
   hipLaunchKernelGGL(k_conv3_lds<NT>, dim3((unsigned)(8 * per)), dim3(256), lds, s, a, ntx, nty, ntz, ntiles, per);
 }
 
