@@ -32,6 +32,11 @@
  *    synchronise it.
  *  - The caller owns Q, U and any workspace; the handle owns the hierarchy.
  *  - One handle must not be used by two threads at once.
+ *  - Debugging aid: with the environment variable HELM_SENTINEL=1 (read at
+ *    every allocation), each device buffer the library allocates starts
+ *    filled with 0xFF bytes (NaN in FP64, FP32 and BF16) instead of whatever
+ *    the allocator returns, so a read of memory no kernel has written shows
+ *    as a non-finite result. Results are otherwise unchanged.
  */
 #ifndef HELM_H
 #define HELM_H

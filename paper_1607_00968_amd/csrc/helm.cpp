@@ -26,6 +26,19 @@ namespace helm {
   std::abort();
 }
 
+hipError_t dmalloc_raw(void** p, size_t bytes) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess || bytes == 0) return e;
+  const char* v = std::getenv("HELM_SENTINEL");
+  if (v && v[0] == '1') {
+    // synchronous fill before the memory is handed out
+    const hipError_t f = hipMemset(*p, 0xFF, bytes);
+    if (f != hipSuccess) return f;
+    return hipDeviceSynchronize();
+  }
+  return hipSuccess;
+}
+
 static thread_local std::string g_err;
 
 helm_status fail(helm_status st, const char* fmt, ...) {
@@ -623,7 +636,7 @@ static helm_status run_persist(helm_ctx* c, int P, const void* f, void* out, voi
       need = std::max(need, (items + 255) / 256);
     }
     helm_ctx::CyclePlan np{P, f, out, tmp, nullptr, (int)ph.size(), (int)std::min<int64_t>(need, gmax)};
-    HCHECK(hipMalloc(&np.d, sizeof(Phase) * ph.size()));
+    HCHECK(dmalloc(&np.d, sizeof(Phase) * ph.size()));
     const hipError_t e = hipMemcpy(np.d, ph.data(), sizeof(Phase) * ph.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(np.d);
@@ -714,7 +727,7 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
   }
   size_t total = 0;
   for (int l = 0; l < c->L; ++l) total += 5 * ((psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256);
-  HCHECK(hipMalloc(&c->fieldmem, total));
+  HCHECK(dmalloc(&c->fieldmem, total));
   char* p = static_cast<char*>(c->fieldmem);
   c->kbuf.assign(c->L, nullptr);
   for (int l = 0; l < c->L; ++l) {
@@ -729,7 +742,7 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
   if (c->coarse == HELM_COARSE_GMRES || c->coarse == HELM_COARSE_LEARNED) {
     hipFree(c->cg_mem);
     c->cg_mem = nullptr;
-    HCHECK(hipMalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
+    HCHECK(dmalloc(&c->cg_mem, coarse_gmres_bytes(c, P)));
   }
   hipFree(c->kmem);
   c->kmem = nullptr;
@@ -737,7 +750,7 @@ static helm_status ensure_fields(helm_ctx* c, int P) {
   if (c->cycle == HELM_CYCLE_K && c->L > 2) {
     size_t kt = 0;
     for (int l = 1; l < c->L - 1; ++l) kt += kcycle_bytes(c, l, P);
-    HCHECK(hipMalloc(&c->kmem, kt));
+    HCHECK(dmalloc(&c->kmem, kt));
     char* q = static_cast<char*>(c->kmem);
     for (int l = 1; l < c->L - 1; ++l) {
       c->klev[l] = q;
@@ -1038,9 +1051,9 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   {
     Level& L = c->lv[0];
     double *dm = nullptr, *dg = nullptr;
-    if (hipMalloc(&dm, 8 * N) != hipSuccess || hipMalloc(&dg, 8 * N) != hipSuccess ||
-        hipMalloc(&L.dH, 16 * N) != hipSuccess || hipMalloc(&L.dM, 16 * N) != hipSuccess ||
-        hipMalloc(&L.dw64, 16 * N) != hipSuccess || hipMalloc(&L.dS, 16 * N) != hipSuccess) {
+    if (dmalloc(&dm, 8 * N) != hipSuccess || dmalloc(&dg, 8 * N) != hipSuccess ||
+        dmalloc(&L.dH, 16 * N) != hipSuccess || dmalloc(&L.dM, 16 * N) != hipSuccess ||
+        dmalloc(&L.dw64, 16 * N) != hipSuccess || dmalloc(&L.dS, 16 * N) != hipSuccess) {
       hipFree(dm);
       hipFree(dg);
       return bail(fail(HELM_ERR_OOM, "setup: fine coefficients"));
@@ -1053,7 +1066,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     hipFree(dm);
     hipFree(dg);
     if (c->precision == HELM_MIXED) {
-      if (hipMalloc(&L.dM32, 8 * N) != hipSuccess || hipMalloc(&L.dw32, 8 * N) != hipSuccess)
+      if (dmalloc(&L.dM32, 8 * N) != hipSuccess || dmalloc(&L.dw32, 8 * N) != hipSuccess)
         return bail(fail(HELM_ERR_OOM, "setup: fine FP32 coefficients"));
       launch_narrow(N, L.dM, L.dM32, s);
       launch_narrow(N, L.dw64, L.dw32, s);
@@ -1063,7 +1076,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
   for (int l = 1; l < c->L; ++l) {
     Level& L = c->lv[l];
     Level& F = c->lv[l - 1];
-    if (hipMalloc(&L.st64, 16 * L.npts * NS) != hipSuccess || hipMalloc(&L.dw64, 16 * L.npts) != hipSuccess)
+    if (dmalloc(&L.st64, 16 * L.npts * NS) != hipSuccess || dmalloc(&L.dw64, 16 * L.npts) != hipSuccess)
       return bail(fail(HELM_ERR_OOM, "setup: level %d stencil", l));
     if (l == 1)
       launch_galerkin_from_fine(c->dim, F.geo(4), L.geo(4), F.dM, F.ih, L.st64, s);
@@ -1071,7 +1084,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
       launch_galerkin_from_gal(c->dim, F.geo(4), L.geo(4), F.st64, L.st64, s);
     launch_gal_dw(c->dim, L.npts, L.st64, c->wj[l], L.dw64, s);
     if (c->precision == HELM_MIXED) {
-      if (hipMalloc(&L.st32, 8 * L.npts * NS) != hipSuccess || hipMalloc(&L.dw32, 8 * L.npts) != hipSuccess)
+      if (dmalloc(&L.st32, 8 * L.npts * NS) != hipSuccess || dmalloc(&L.dw32, 8 * L.npts) != hipSuccess)
         return bail(fail(HELM_ERR_OOM, "setup: level %d FP32 stencil", l));
       launch_narrow(L.npts * NS, L.st64, L.st32, s);
       launch_narrow(L.npts, L.dw64, L.dw32, s);
@@ -1086,8 +1099,8 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     if (n > 32768) return bail(fail(HELM_ERR_UNSUPPORTED, "coarsest grid has %lld unknowns (> 32768)", (long long)n));
     const int nb = 32;  // pivot block held in LDS by one workgroup
     c128* work = nullptr;
-    if (hipMalloc(&c->Minv64, 16 * n * n) != hipSuccess ||
-        hipMalloc(&work, 16 * (2 * n * nb + nb * nb + 1)) != hipSuccess) {
+    if (dmalloc(&c->Minv64, 16 * n * n) != hipSuccess ||
+        dmalloc(&work, 16 * (2 * n * nb + nb * nb + 1)) != hipSuccess) {
       hipFree(work);
       return bail(fail(HELM_ERR_OOM, "setup: coarsest inverse (%lld unknowns)", (long long)n));
     }
@@ -1096,7 +1109,7 @@ helm_status helm_setup(const helm_setup_desc* d, void* stream, helm_handle* out)
     hipFree(work);
     if (rc != 0) return bail(fail(HELM_ERR_DEVICE, "setup: coarsest inversion failed (%d)", rc));
     if (c->precision == HELM_MIXED) {
-      if (hipMalloc(&c->Minv32, 8 * n * n) != hipSuccess) return bail(fail(HELM_ERR_OOM, "setup: FP32 coarsest inverse"));
+      if (dmalloc(&c->Minv32, 8 * n * n) != hipSuccess) return bail(fail(HELM_ERR_OOM, "setup: FP32 coarsest inverse"));
       launch_narrow(n * n, c->Minv64, c->Minv32, s);
       hipStreamSynchronize(s);
       hipFree(c->Minv64);
@@ -1193,8 +1206,8 @@ static helm_status check_block(helm_handle h, int32_t nrhs, const void* a, const
 
 // Scratch for the ABI helpers: internal copies of two blocks.
 static helm_status tmp_blocks(helm_ctx* c, int P, int64_t N, c128** A, c128** B) {
-  HCHECK(hipMalloc(A, 16 * N * P));
-  if (hipMalloc(B, 16 * N * P) != hipSuccess) {
+  HCHECK(dmalloc(A, 16 * N * P));
+  if (dmalloc(B, 16 * N * P) != hipSuccess) {
     hipFree(*A);
     return fail(HELM_ERR_OOM, "temporary block");
   }
@@ -1438,7 +1451,7 @@ static helm_status bicgstab_solve(helm_ctx* c, int nrhs, const void* Q, void* U,
       hipFree(c->ws);
       c->ws = nullptr;
       c->wsbytes = 0;
-      HCHECK(hipMalloc(&c->ws, w.end));
+      HCHECK(dmalloc(&c->ws, w.end));
       c->wsbytes = w.end;
     }
     base = static_cast<char*>(c->ws);
@@ -1748,7 +1761,7 @@ helm_status helm_solve_block(helm_handle h, int32_t nrhs, const void* Q, void* U
       hipFree(c->ws);
       c->ws = nullptr;
       c->wsbytes = 0;
-      HCHECK(hipMalloc(&c->ws, w.end));
+      HCHECK(dmalloc(&c->ws, w.end));
       c->wsbytes = w.end;
     }
     base = static_cast<char*>(c->ws);
@@ -2043,7 +2056,7 @@ helm_status helm_residual(helm_handle h, int32_t nrhs, const void* Q, const void
   // size (RESID_MAX_COLS columns), allocated on the first call and kept
   if (!h->resid_buf) {
     const size_t n = (size_t)RESID_MAX_COLS * (2 * RESID_MAX_CHUNKS + 1);
-    HCHECK(hipMalloc(&h->resid_buf, sizeof(double) * n));
+    HCHECK(dmalloc(&h->resid_buf, sizeof(double) * n));
   }
   launch_resid_norms(L.geo(1), nrhs, L.ih, L.dH, Q, U, h->resid_buf, s);
   HCHECK(hipGetLastError());
@@ -2110,7 +2123,7 @@ helm_status helm_jtvp(helm_handle h, int32_t nrhs, const void* U, const void* U1
     hipFree(h->sensbuf);
     h->sensbuf = nullptr;
     h->sensbytes = 0;
-    HCHECK(hipMalloc(&h->sensbuf, need));
+    HCHECK(dmalloc(&h->sensbuf, need));
     h->sensbytes = need;
   }
   helm_solve_opts o{5, 1000, 0, 0, 2, 0, 0.0, 0, 0};

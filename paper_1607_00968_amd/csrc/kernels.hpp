@@ -18,6 +18,15 @@ struct PtrList {
 
 [[noreturn]] void fatal_combo(const char* where);
 
+// Device allocation for every buffer of the library. With HELM_SENTINEL=1 in
+// the environment (read at each call) the new memory is filled with 0xFF
+// bytes, a NaN in FP64, FP32 and BF16, so that a kernel reading memory no
+// kernel has written shows up as a non-finite result (write-coverage check).
+hipError_t dmalloc_raw(void** p, size_t bytes);
+template <class T> inline hipError_t dmalloc(T** p, size_t bytes) {
+  return dmalloc_raw(reinterpret_cast<void**>(p), bytes);
+}
+
 // ---- k_level.hip ------------------------------------------------------------
 // Tile shape of the 3D finest-level marching kernel (rows per lane 1/2/4,
 // planes per z-chunk); results do not depend on it.

@@ -1056,13 +1056,13 @@ helm_status create(int D, int max_batch, uint64_t seed, hipStream_t s, Net** out
     return st;
   };
   const size_t pb = al(4 * (size_t)n->np);
-  if (hipMalloc(&n->p, 4 * pb) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network parameters"));
+  if (dmalloc(&n->p, 4 * pb) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network parameters"));
   n->g = n->p + pb / 4;
   n->am = n->g + pb / 4;
   n->av = n->am + pb / 4;
   int64_t nw = 0;
   for (int l = 0; l < NLAYER; ++l) nw += al(2 * 27LL * L_CIN[l] * L_COUT[l]);
-  if (hipMalloc(&n->wmem, 2 * nw) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network weights"));
+  if (dmalloc(&n->wmem, 2 * nw) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network weights"));
   char* w = static_cast<char*>(n->wmem);
   for (int l = 0; l < NLAYER; ++l) {
     const size_t b = al(2 * 27LL * L_CIN[l] * L_COUT[l]);
@@ -1078,7 +1078,7 @@ helm_status create(int D, int max_batch, uint64_t seed, hipStream_t s, Net** out
                           al(4)};
   size_t tot = 0;
   for (size_t b : sizes) tot += b;
-  if (hipMalloc(&n->amem, tot) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network activations (%zu bytes)", tot));
+  if (dmalloc(&n->amem, tot) != hipSuccess) return bail(fail(HELM_ERR_OOM, "network activations (%zu bytes)", tot));
   char* a = static_cast<char*>(n->amem);
   void** slots[] = {(void**)&n->x0, (void**)&n->a1, (void**)&n->c1, (void**)&n->p1, (void**)&n->a2, (void**)&n->c2,
                     (void**)&n->p2, (void**)&n->a4, (void**)&n->a5, (void**)&n->a6, (void**)&n->a7, (void**)&n->a8,
@@ -1267,7 +1267,7 @@ static helm_status ensure_backward(Net* n) {
                           al(2 * BV * 16),   al(2 * BV * 16)};
   size_t tot = 0;
   for (size_t b : sizes) tot += b;
-  if (hipMalloc(&n->bmem, tot) != hipSuccess) return fail(HELM_ERR_OOM, "network gradients (%zu bytes)", tot);
+  if (dmalloc(&n->bmem, tot) != hipSuccess) return fail(HELM_ERR_OOM, "network gradients (%zu bytes)", tot);
   char* a = static_cast<char*>(n->bmem);
   void** slots[] = {(void**)&n->dout, (void**)&n->tgt, (void**)&n->wpart, (void**)&n->hpart, (void**)&n->g9,
                     (void**)&n->g8,   (void**)&n->gc1, (void**)&n->g7,    (void**)&n->g6,    (void**)&n->gc2,
@@ -1375,8 +1375,8 @@ helm_status bind(Net* n, const Coarse& g, hipStream_t s) {
   hipFree(n->mask);
   n->dgn = nullptr;
   n->mask = nullptr;
-  LCHECK(hipMalloc(&n->dgn, 8 * n->Nc));
-  LCHECK(hipMalloc(&n->mask, n->V));
+  LCHECK(dmalloc(&n->dgn, 8 * n->Nc));
+  LCHECK(dmalloc(&n->mask, n->V));
   hipLaunchKernelGGL(k_net_dgn, g1(n->Nc), dim3(256), 0, s, n->Nc, 27, g.st, g.H2, n->dgn);
   hipLaunchKernelGGL(k_net_mask, g1(n->V), dim3(256), 0, s, n->D, n->box, n->mask);
   LCHECK(hipStreamSynchronize(s));
@@ -1393,10 +1393,10 @@ static helm_status ensure_cols(Net* n, int P) {
   n->part = nullptr;
   n->hn2 = nullptr;
   n->Pmax = 0;
-  LCHECK(hipMalloc(&n->n2, 3 * 8 * (size_t)P + 256));
+  LCHECK(dmalloc(&n->n2, 3 * 8 * (size_t)P + 256));
   n->sc = n->n2 + P;
   n->os = n->sc + P;
-  LCHECK(hipMalloc(&n->part, 16 * (size_t)(gram_part_elems(P) + P)));
+  LCHECK(dmalloc(&n->part, 16 * (size_t)(gram_part_elems(P) + P)));
   n->Gs = n->part + gram_part_elems(P);
   n->bad = reinterpret_cast<int*>(n->os + P);
   LCHECK(hipHostMalloc(&n->hn2, 8 * (size_t)P));
@@ -1460,8 +1460,8 @@ helm_status capture_begin(Net* n, int max_pairs) {
   n->ts = nullptr;
   n->cap_max = n->cap_n = 0;
   n->cap_seen = 0;
-  LCHECK(hipMalloc(&n->xs, 8 * n->V * (size_t)max_pairs));
-  LCHECK(hipMalloc(&n->ts, 8 * n->V * (size_t)max_pairs));
+  LCHECK(dmalloc(&n->xs, 8 * n->V * (size_t)max_pairs));
+  LCHECK(dmalloc(&n->ts, 8 * n->V * (size_t)max_pairs));
   n->cap_max = max_pairs;
   n->cap_box = n->box;
   return HELM_OK;
@@ -1563,9 +1563,9 @@ helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double
   n->idx = nullptr;
   n->rot = nullptr;
   n->hist = nullptr;
-  LCHECK(hipMalloc(&n->idx, 4 * (size_t)steps * batch));
-  LCHECK(hipMalloc(&n->rot, 8 * (size_t)steps * batch));
-  LCHECK(hipMalloc(&n->hist, 4 * (size_t)steps));
+  LCHECK(dmalloc(&n->idx, 4 * (size_t)steps * batch));
+  LCHECK(dmalloc(&n->rot, 8 * (size_t)steps * batch));
+  LCHECK(dmalloc(&n->hist, 4 * (size_t)steps));
   std::vector<int> idx((size_t)steps * batch);
   std::vector<float> rot(2 * idx.size());
   std::mt19937_64 rng(seed);
