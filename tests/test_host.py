@@ -64,14 +64,18 @@ def test_bench_reads_the_traffic_of_each_committed_tile():
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    text = open(os.path.join(ROOT, "profiles", "fine_sweep_mixed_192x64_traffic.md")).read()
-    tiles = re.findall(r"^traffic: .*tile=(\d+)x(\d+)", text, flags=re.M)
-    assert tiles
-    for ry, zc in tiles:
-        v = bench.committed_traffic("mixed", 192, 64, (int(ry), int(zc)))
-        assert v is not None and 10_758_392_824 < v < 2 * 10_758_392_824
+    text = open(os.path.join(ROOT, "profiles", "fine_kernels_mixed_192x64_traffic.md")).read()
+    lines = re.findall(r"^traffic: .*kernel=(\w+) .*tile=(\d+)x(\d+) bytes_per_launch=(\d+) algorithmic=(\d+)",
+                       text, flags=re.M)
+    assert lines
+    kb = bench.fine_kernel_bytes("mixed", 191 ** 3, 95 ** 3, 64)
+    for kernel, ry, zc, byts, alg in lines:
+        # each line's algorithmic bytes are the bench's own count for that class
+        assert int(alg) == kb[kernel], kernel
+        v = bench.committed_traffic("mixed", 192, 64, (int(ry), int(zc)), kernel)
+        assert v == int(byts) and kb[kernel] < v < 2 * kb[kernel], kernel
     assert bench.committed_traffic("mixed", 192, 64, (4, 7)) is None
-    assert bench.committed_traffic("fp64", 192, 64, (int(tiles[0][0]), int(tiles[0][1]))) is None
+    assert bench.committed_traffic("fp64", 192, 64, (int(lines[0][1]), int(lines[0][2]))) is None
 
 
 def _setup_case(**over):
