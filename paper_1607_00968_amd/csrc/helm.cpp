@@ -473,7 +473,8 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
 }
 
 // k steps of GMRES from zero on the coarsest grid, one independent GMRES per
-// column (classical Gram-Schmidt, applied twice), least squares by Givens
+// column (one classical Gram-Schmidt pass; the basis vectors after the first
+// are normalised lazily, see launch_cg_lazy_coef), least squares by Givens
 // rotations. No host synchronisation: the step count is fixed. `out` may be
 // the buffer `f` (f is read only before the first step).
 static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, int k, hipStream_t s) {
@@ -492,21 +493,25 @@ static void coarse_gmres(helm_ctx* c, int P, const void* f, void* out, int k, hi
   double* b2 = reinterpret_cast<double*>(Gs + 2 * P);
   double* hn2 = b2 + P;
   double* sc = hn2 + P;
+  double* nu = sc + P;  // (k + 1) P norms of the stored basis vectors
   auto vec = [&](int i) { return static_cast<void*>(V + vb * i); };
   launch_colnorm2(p, N, P, P, f, part, Gs, b2, s);
   launch_inv_sqrt(P, b2, sc, s);
   launch_scale_cols(p, N, P, P, sc, f, vec(0), s);
+  launch_cg_lazy_init(P, b2, nu, s);
   PtrList vl{};
   for (int j = 0; j < k; ++j) {
     vl.p[j] = vec(j);
     level_op(c, l, 0, P, vec(j), nullptr, vec(j + 1), s);
-    // one classical Gram-Schmidt pass; the update also yields ||w||^2
+    // one classical Gram-Schmidt pass; the update scales its output by
+    // 1/nu_j and yields nu_{j+1}^2
     launch_gram(p, N, P, P, 1, j + 1, vl, vec(j + 1), part, Gc, s);
-    launch_update_norm(p, N, P, P, j + 1, vl, Gc, vec(j + 1), part, Gs, hn2, s);
-    launch_cg_hcol(P, j, k, Gc, hn2, H, sc, s);
-    launch_scale_cols(p, N, P, P, sc, vec(j + 1), vec(j + 1), s);
+    launch_cg_lazy_coef(P, j, Gc, nu, sc, s);
+    launch_update_norm(p, N, P, P, j + 1, vl, Gc, vec(j + 1), part, Gs, hn2, s, sc);
+    launch_cg_lazy_hcol(P, j, k, Gc, hn2, nu, H, s);
   }
   launch_cg_ls(P, k, H, b2, Gc, Yc, s);  // Gc (2 (k+1) P entries) is free after the loop
+  launch_lazy_y(P, k, nu, Yc, s);        // coefficients of the stored s_j = nu_j v_j
   launch_block_update(1, p, p, N, P, P, 1, k, vl, Yc, out, s);
 }
 
@@ -520,7 +525,7 @@ static size_t coarse_gmres_bytes(const helm_ctx* c, int P) {
   const int l = c->L - 1, k = coarse_gmres_cap(c);
   const size_t vb = (psize(field_prec(c, l)) * c->lv[l].npts * P + 255) / 256 * 256;
   return vb * (k + 1) + 16 * ((size_t)P * (k + 1) * k + 3 * (size_t)(k + 1) * P + gram_part_elems(P) + 2 * P) +
-         8 * 3 * (size_t)P + 256;
+         8 * 3 * (size_t)P + 8 * (size_t)(k + 1) * P + 256;
 }
 
 static void coarsest_solve(helm_ctx* c, int P, const void* f, void* out, hipStream_t s) {

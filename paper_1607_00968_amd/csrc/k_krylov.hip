@@ -533,7 +533,7 @@ void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const
 template <class S, int KX>
 __global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int P, int with_norm, PtrList X,
                                                           const c128* __restrict__ C, S* __restrict__ Y,
-                                                          c128* __restrict__ part) {
+                                                          c128* __restrict__ part, const double* __restrict__ osc) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int PT = 256 / P;
@@ -551,6 +551,7 @@ __global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int
       coef[i] = tcx(C[(int64_t)i * P + c]);
       xp[i] = static_cast<const S*>(X.p[i]) + c;
     }
+    const double sc = osc ? osc[c] : 1.0;
     for (int64_t n = nb0 + r; n < nb1; n += PT) {
       const int64_t e = n * ld + c;
       const S yv = Y[e];
@@ -560,6 +561,7 @@ __global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int
       cx<double> y = {(double)yv.re, (double)yv.im};
 #pragma unroll
       for (int i = 0; i < KX; ++i) cfma(y, cx<double>{-(double)xv[i].re, -(double)xv[i].im}, coef[i]);
+      if (osc) y = sc * y;
       const S out = S{(E)y.re, (E)y.im};
       Y[e] = out;
       nrm += (double)out.re * (double)out.re + (double)out.im * (double)out.im;
@@ -577,12 +579,12 @@ __global__ __launch_bounds__(256) void k_update_norm_part(int64_t N, int ld, int
 
 template <class S>
 static void update_norm_dispatch(int kx, int nblk, hipStream_t s, int64_t N, int ld, int P, int with_norm,
-                                 const PtrList& X, const c128* C, void* Y, c128* part) {
+                                 const PtrList& X, const c128* C, void* Y, c128* part, const double* osc) {
   switch (kx) {
 #define HELM_KX(v)                                                                                             \
   case v:                                                                                                      \
     hipLaunchKernelGGL((k_update_norm_part<S, v>), dim3(nblk), dim3(256), 0, s, N, ld, P, with_norm, X, C, \
-                       (S*)Y, part);                                                                           \
+                       (S*)Y, part, osc);                                                                      \
     break;
     HELM_KX(1) HELM_KX(2) HELM_KX(3) HELM_KX(4) HELM_KX(5) HELM_KX(6) HELM_KX(7) HELM_KX(8)
     HELM_KX(9) HELM_KX(10) HELM_KX(11) HELM_KX(12) HELM_KX(13) HELM_KX(14) HELM_KX(15) HELM_KX(16)
@@ -592,7 +594,7 @@ static void update_norm_dispatch(int kx, int nblk, hipStream_t s, int64_t N, int
 }
 
 void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& X, const c128* C, void* Y,
-                        c128* part, c128* G, double* nrm2, hipStream_t s) {
+                        c128* part, c128* G, double* nrm2, hipStream_t s, const double* osc) {
   if (P > 256 || k > MAXPTR) fatal_combo("launch_update_norm");
   const int nblk = part_blocks(N, P);
   // at most 16 vectors per pass; the norm comes from the last pass
@@ -601,10 +603,12 @@ void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& 
     PtrList sub{};
     for (int i = 0; i < kx; ++i) sub.p[i] = X.p[i0 + i];
     const int last = i0 + 16 >= k;
+    // the output scale applies once, in the last pass
+    const double* sc = last ? osc : nullptr;
     if (p == P64)
-      update_norm_dispatch<c128>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part);
+      update_norm_dispatch<c128>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part, sc);
     else if (p == P32)
-      update_norm_dispatch<c64>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part);
+      update_norm_dispatch<c64>(kx, nblk, s, N, ld, P, last, sub, C + (int64_t)i0 * P, Y, part, sc);
     else
       fatal_combo("launch_update_norm");
   }
@@ -721,6 +725,60 @@ __global__ void k_cg_hcol(int P, int j, int k, const c128* __restrict__ Gc, cons
 void launch_cg_hcol(int P, int j, int k, const c128* Gc, const double* hn2, c128* H, double* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_hcol, dim3((P + 63) / 64), dim3(64), 0, s, P, j, k, Gc, hn2, H, sc);
 }
+// Lazy normalisation of the coarsest GMRES: the stored basis vector s_i has
+// norm nu_i (nu[i P + c]; nu_0 = 1, or 0 for a zero column) and the
+// orthonormal basis is v_i = s_i / nu_i. With w = M s_j and G_i = s_i^H w,
+// the Hessenberg entries are h_ij = G_i / (nu_i nu_j), and
+//   s_{j+1} = (w - sum_i s_i G_i / nu_i^2) / nu_j = M v_j - sum_i v_i h_ij
+// has norm h_{j+1,j} = nu_{j+1}: the scaling rides on the update's single
+// pass (its output scale) instead of a pass of its own, and the stored
+// vectors keep the size of an Arnoldi residual.
+__global__ void k_cg_lazy_init(int P, const double* __restrict__ b2, double* __restrict__ nu) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < P) nu[c] = b2[c] > 0.0 ? 1.0 : 0.0;
+}
+void launch_cg_lazy_init(int P, const double* b2, double* nu, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_lazy_init, dim3((P + 63) / 64), dim3(64), 0, s, P, b2, nu);
+}
+// Before step j's update: C_i = G_i / nu_i^2 in place (i <= j), osc = 1/nu_j.
+__global__ void k_cg_lazy_coef(int P, int j, c128* __restrict__ Gc, const double* __restrict__ nu,
+                               double* __restrict__ osc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  for (int i = 0; i <= j; ++i) {
+    const double ni = nu[(int64_t)i * P + c];
+    const double a = ni > 0.0 ? 1.0 / (ni * ni) : 0.0;
+    const c128 g = Gc[(int64_t)i * P + c];
+    Gc[(int64_t)i * P + c] = c128{a * g.re, a * g.im};
+  }
+  const double nj = nu[(int64_t)j * P + c];
+  osc[c] = nj > 0.0 ? 1.0 / nj : 0.0;
+}
+void launch_cg_lazy_coef(int P, int j, c128* Gc, const double* nu, double* osc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_lazy_coef, dim3((P + 63) / 64), dim3(64), 0, s, P, j, Gc, nu, osc);
+}
+// After it: column j of every column's Hessenberg (layout of k_cg_hcol),
+// h_ij = C_i nu_i / nu_j, h_{j+1,j} = nu_{j+1} = sqrt(hn2).
+__global__ void k_cg_lazy_hcol(int P, int j, int k, const c128* __restrict__ Gc, const double* __restrict__ hn2,
+                               double* __restrict__ nu, c128* __restrict__ H) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P) return;
+  c128* h = H + (int64_t)c * (k + 1) * k + (int64_t)j * (k + 1);
+  const double nj = nu[(int64_t)j * P + c];
+  for (int i = 0; i <= j; ++i) {
+    const double a = nj > 0.0 ? nu[(int64_t)i * P + c] / nj : 0.0;
+    const c128 g = Gc[(int64_t)i * P + c];
+    h[i] = c128{a * g.re, a * g.im};
+  }
+  const double nn = sqrt(fmax(hn2[c], 0.0));
+  h[j + 1] = c128{nn, 0.0};
+  nu[(int64_t)(j + 1) * P + c] = nn;
+}
+void launch_cg_lazy_hcol(int P, int j, int k, const c128* Gc, const double* hn2, double* nu, c128* H,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_lazy_hcol, dim3((P + 63) / 64), dim3(64), 0, s, P, j, k, Gc, hn2, nu, H);
+}
+
 // sc[c] = 1/sqrt(b2[c]) (0 for a zero column)
 __global__ void k_inv_sqrt(int P, const double* __restrict__ b2, double* __restrict__ sc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;

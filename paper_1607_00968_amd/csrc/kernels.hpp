@@ -161,7 +161,11 @@ void launch_scale_cols(Prec p, int64_t N, int ld, int P, const double* sc, const
 // Block size 1: Y -= sum_i X_i C_i (per column) and nrm2[c] = ||Y_c||^2 after
 // the update (part: gram_part_elems scratch; G: P complex scratch).
 void launch_update_norm(Prec p, int64_t N, int ld, int P, int k, const PtrList& X, const c128* C, void* Y,
-                        c128* part, c128* G, double* nrm2, hipStream_t s);
+                        c128* part, c128* G, double* nrm2, hipStream_t s, const double* osc = nullptr);
+void launch_cg_lazy_init(int P, const double* b2, double* nu, hipStream_t s);
+void launch_cg_lazy_coef(int P, int j, c128* Gc, const double* nu, double* osc, hipStream_t s);
+void launch_cg_lazy_hcol(int P, int j, int k, const c128* Gc, const double* hn2, double* nu, c128* H,
+                         hipStream_t s);
 // R = ||w||, Rinv = 1/||w|| per column from n2; flag where n2 <= tol*ref2.
 void launch_norm_to_r(int P, const double* n2, const double* ref2, double tol, c128* R, c128* Rinv, int* flag,
                       hipStream_t s);
