@@ -748,9 +748,10 @@ __global__ __launch_bounds__(64 * TY) void k_fine_t16(Geo g, ZTiles zt, int nyb,
   //      one 2.42 -> 2.32 ms; issued with the u loads instead, the fused one
   //      took 2.63 ms);
   //  EF2: D ahead of the u loads (RAWC, which needs neither f nor w D^-1
-  //      after the barrier: nothing is loaded there; 1.82 -> 1.76 ms).
+  //      after the barrier: nothing is loaded there; 1.82 -> 1.76 ms; and
+  //      the operator apply, which has no f).
   constexpr bool EF = !RAWC && !PF && MODE != 0;
-  constexpr bool EF2 = RAWC;
+  constexpr bool EF2 = RAWC || (MODE == 0 && !PF);
   for (int z = z0; z < z1; ++z, up += sz, rpp += sz, fp += sz) {
     cx<T> de{}, we{};
     if (EF2 && inb) de = dg[(int64_t)z * plane + icol];
