@@ -378,6 +378,16 @@ void helm_net_destroy(helm_net n);
  * resets the optimiser state. */
 helm_status helm_net_set_params(helm_net n, const float* params);
 helm_status helm_net_get_params(helm_net n, float* params);
+/* Training checkpoint (the Adam update of helm_net_train_step and
+ * helm_net_train). state: HOST [3 * helm_net_nparams()] FP32 = the
+ * parameters, then Adam's first moments, then its second moments; step: the
+ * update count t of the bias correction. get_state copies them out;
+ * set_state restores them (parameters and first moments finite, second
+ * moments finite and >= 0, step >= 0, else an error and nothing changes), so
+ * that training resumed from a checkpoint takes the same updates, bitwise, as
+ * training that never stopped. */
+helm_status helm_net_get_state(helm_net n, float* state, int64_t* step);
+helm_status helm_net_set_state(helm_net n, const float* state, int64_t step);
 /* Serialise: blob == NULL returns the size in *bytes; otherwise writes
  * "HNET", uint32 1, int64 nparams, float params[] into blob (HOST). */
 helm_status helm_net_save(helm_net n, void* blob, size_t* bytes);

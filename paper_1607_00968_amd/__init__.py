@@ -45,7 +45,8 @@ ABI_SYMBOLS = (
     "helm_profile_enable", "helm_profile_read", "helm_fine_tile", "helm_set_fine_tile",
     "helm_status_string", "helm_last_error",
     "helm_net_nparams", "helm_net_create", "helm_net_destroy", "helm_net_set_params",
-    "helm_net_get_params", "helm_net_save", "helm_net_forward", "helm_net_loss_grad",
+    "helm_net_get_params", "helm_net_get_state", "helm_net_set_state", "helm_net_save", "helm_net_forward",
+    "helm_net_loss_grad",
     "helm_net_capture", "helm_net_pairs", "helm_net_pool_read", "helm_net_train", "helm_net_train_step",
     "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp", "helm_setup_batch",
 )
@@ -127,6 +128,8 @@ def lib():
         L.helm_net_destroy.argtypes = [P]
         L.helm_net_set_params.argtypes = [P, P]
         L.helm_net_get_params.argtypes = [P, P]
+        L.helm_net_get_state.argtypes = [P, P, P]
+        L.helm_net_set_state.argtypes = [P, P, C.c_int64]
         L.helm_net_save.argtypes = [P, P, C.POINTER(C.c_size_t)]
         L.helm_net_forward.argtypes = [P, I, P, P, P]
         L.helm_net_loss_grad.argtypes = [P, I, P, P, P, P, C.POINTER(D), P]
@@ -540,6 +543,21 @@ class Net:
         p = np.empty(helm_net_nparams(), dtype=np.float32)
         _check(lib().helm_net_get_params(self.ptr, C.c_void_p(p.ctypes.data)))
         return p
+
+    def get_state(self):
+        """Training checkpoint: (float32 [3 * nparams] = parameters, Adam's
+        first and second moments; the Adam step count)."""
+        st = np.empty(3 * helm_net_nparams(), dtype=np.float32)
+        t = C.c_int64(0)
+        _check(lib().helm_net_get_state(self.ptr, C.c_void_p(st.ctypes.data), C.byref(t)))
+        return st, t.value
+
+    def set_state(self, state, step: int):
+        """Restore a checkpoint from get_state."""
+        st = np.ascontiguousarray(state, dtype=np.float32)
+        if st.size != 3 * helm_net_nparams():
+            raise ValueError("wrong state size")
+        _check(lib().helm_net_set_state(self.ptr, C.c_void_p(st.ctypes.data), int(step)))
 
     def save(self) -> bytes:
         n = C.c_size_t(0)

@@ -2227,6 +2227,16 @@ helm_status helm_net_get_params(helm_net n, float* params) {
   return learned::get_params(n->n, params, n->s);
 }
 
+helm_status helm_net_get_state(helm_net n, float* state, int64_t* step) {
+  if (!n || !state || !step) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  return learned::get_state(n->n, state, step, n->s);
+}
+
+helm_status helm_net_set_state(helm_net n, const float* state, int64_t step) {
+  if (!n || !state) return fail(HELM_ERR_INVALID_ARG, "null argument");
+  return learned::set_state(n->n, state, step, n->s);
+}
+
 helm_status helm_net_save(helm_net n, void* blob, size_t* bytes) {
   if (!n || !bytes) return fail(HELM_ERR_INVALID_ARG, "null argument");
   if (!blob) {

@@ -1143,6 +1143,32 @@ helm_status get_params(Net* n, float* host, hipStream_t s) {
   return HELM_OK;
 }
 
+// Training checkpoint: parameters, Adam first and second moments (3 np FP32
+// values) and the step count.
+helm_status get_state(Net* n, float* host, int64_t* step, hipStream_t s) {
+  LCHECK(hipMemcpyAsync(host, n->p, 4 * n->np, hipMemcpyDeviceToHost, s));
+  LCHECK(hipMemcpyAsync(host + n->np, n->am, 4 * n->np, hipMemcpyDeviceToHost, s));
+  LCHECK(hipMemcpyAsync(host + 2 * n->np, n->av, 4 * n->np, hipMemcpyDeviceToHost, s));
+  LCHECK(hipStreamSynchronize(s));
+  *step = n->adam_t;
+  return HELM_OK;
+}
+
+helm_status set_state(Net* n, const float* host, int64_t step, hipStream_t s) {
+  if (step < 0) return fail(HELM_ERR_INVALID_ARG, "Adam step count must be >= 0");
+  for (int64_t k = 0; k < 3 * n->np; ++k)
+    if (!std::isfinite(host[k])) return fail(HELM_ERR_NONFINITE, "training state entry %lld is not finite", (long long)k);
+  for (int64_t k = 2 * n->np; k < 3 * n->np; ++k)
+    if (host[k] < 0.f) return fail(HELM_ERR_INVALID_ARG, "Adam second moment %lld is negative", (long long)(k - 2 * n->np));
+  LCHECK(hipMemcpyAsync(n->p, host, 4 * n->np, hipMemcpyHostToDevice, s));
+  LCHECK(hipMemcpyAsync(n->am, host + n->np, 4 * n->np, hipMemcpyHostToDevice, s));
+  LCHECK(hipMemcpyAsync(n->av, host + 2 * n->np, 4 * n->np, hipMemcpyHostToDevice, s));
+  n->adam_t = step;
+  pack_weights(n, s);
+  LCHECK(hipStreamSynchronize(s));
+  return HELM_OK;
+}
+
 size_t blob_bytes() { return 16 + 4 * (size_t)nparams_total(); }
 
 helm_status write_blob(Net* n, void* blob, hipStream_t s) {

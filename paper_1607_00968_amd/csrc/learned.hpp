@@ -35,6 +35,8 @@ helm_status create(int D, int max_batch, uint64_t seed, hipStream_t s, Net** out
 void destroy(Net* n);
 helm_status set_params(Net* n, const float* host, hipStream_t s);
 helm_status get_params(Net* n, float* host, hipStream_t s);
+helm_status get_state(Net* n, float* host, int64_t* step, hipStream_t s);
+helm_status set_state(Net* n, const float* host, int64_t step, hipStream_t s);
 // Weights blob: "HNET", uint32 version 1, int64 nparams, float params[].
 size_t blob_bytes();
 helm_status write_blob(Net* n, void* blob, hipStream_t s);

@@ -103,3 +103,46 @@ def test_train_step_matches_oracle_adam():
     # the first step moves every parameter with a nonzero gradient by about lr
     moved = np.abs(params[0] - p0)[np.abs(grads[0]) > 1e-4]
     assert np.allclose(moved, lr, rtol=1e-3)
+
+
+def test_training_resumes_bitwise_from_a_checkpoint():
+    """helm_net_get_state / helm_net_set_state: two Adam steps, a checkpoint,
+    two more steps; a second network restored from the checkpoint takes the
+    same two steps to bitwise the same parameters and moments. Invalid
+    states are refused and change nothing."""
+    D, B = 8, 2
+    rng = np.random.default_rng(11)
+    mask = torch.from_numpy((rng.uniform(size=D ** 3) > 0.2).astype(np.uint8)).cuda()
+    batches = [(torch.from_numpy(rng.standard_normal((B, D ** 3, 4)).astype(np.float32)).cuda(),
+                torch.from_numpy(rng.standard_normal((B, D ** 3, 2)).astype(np.float32)).cuda()) for _ in range(4)]
+    a = pk.helm_net_create(D, B, seed=21)
+    for x, t in batches[:2]:
+        a.train_step(x, t, mask, lr=3e-3)
+    state, step = a.get_state()
+    n = pk.helm_net_nparams()
+    assert step == 2 and state.shape == (3 * n,)
+    assert np.array_equal(state[:n], a.get_params())
+    assert (state[2 * n:] >= 0).all() and np.abs(state[n:2 * n]).max() > 0
+    for x, t in batches[2:]:
+        a.train_step(x, t, mask, lr=3e-3)
+    b = pk.helm_net_create(D, B, seed=99)
+    b.set_state(state, step)
+    for x, t in batches[2:]:
+        b.train_step(x, t, mask, lr=3e-3)
+    sa, ta = a.get_state()
+    sb, tb = b.get_state()
+    assert ta == tb == 4 and np.array_equal(sa, sb)
+    bad = state.copy()
+    bad[2 * n + 5] = -1.0
+    with pytest.raises(pk.HelmError) as e:
+        b.set_state(bad, 2)
+    assert e.value.status == pk.HELM_ERR_INVALID_ARG
+    bad = state.copy()
+    bad[7] = np.nan
+    with pytest.raises(pk.HelmError) as e:
+        b.set_state(bad, 2)
+    assert e.value.status == pk.HELM_ERR_NONFINITE
+    with pytest.raises(pk.HelmError):
+        b.set_state(state, -1)
+    sc, tc = b.get_state()
+    assert tc == 4 and np.array_equal(sc, sb)
