@@ -136,16 +136,23 @@ def test_vcycle_fp64_matches_oracle(dim, n, levels, coarse, nrhs):
     assert rel(host(Z), ho.vcycle(F)) <= 1e-9
 
 
-@pytest.mark.parametrize("dim,n,levels,coarse", [(2, 32, 3, "lu"), (3, 32, 3, "gmres")])
+@pytest.mark.parametrize("dim,n,levels,coarse", [(2, 32, 3, "lu"), (3, 32, 3, "gmres"), (2, 64, 3, "lu"),
+                                                 (3, 48, 3, "gmres")])
 def test_vcycle_mixed_close_to_oracle(dim, n, levels, coarse):
-    """FP32 cycle with BF16 fields at levels >= 2: not a parity target, but
-    the preconditioner must stay within a few BF16 units of the FP64 one."""
+    """FP32 cycle with BF16 fields below the finest level against the FP64
+    oracle's cycle, per column. The fields of the coarse levels are stored in
+    BF16 (round to nearest even: a relative error of at most 2^-9 per value),
+    and the coarse correction carries that error into the output; the FP32
+    arithmetic adds about 1e-7. Measured 1.1e-3 to 1.9e-3 (0.6 to 0.95 BF16
+    units) over these cases and seeds; the bound is two BF16 units, 2^-8."""
     p = small_problem(dim, n, levels)
     hd, ho = setup_both(p, levels, precision="mixed", coarse=coarse)
     F = crand(4, p.N)
     Z = torch.empty((4, p.N), dtype=torch.complex128, device="cuda")
     pk.helm_precond(hd, dev(F), Z)
-    assert rel(host(Z), ho.vcycle(F)) <= 3e-2
+    Zh, Zo = host(Z), ho.vcycle(F)
+    for c in range(4):
+        assert rel(Zh[c], Zo[c]) <= 2.0 ** -8, (c, rel(Zh[c], Zo[c]))
 
 
 def check_solution(p, U, tol_res, Uref=None, err_tol=None):
