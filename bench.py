@@ -145,29 +145,65 @@ def train_in_child(args):
     return blob, info
 
 
+class GroupSolver:
+    """The 64 independent single-column solves (block size 1) of the workload
+    in `groups` concurrent groups: one handle (hierarchy) and one stream per
+    group, solved together by helm_solve_batch, so that one group's
+    latency-bound coarsest phase overlaps another's bandwidth-bound sweeps.
+    groups = 1 is one helm_solve_block over all columns. make() builds a
+    handle of the configuration; solve(U) fills U (all columns) and returns
+    the per-group infos."""
+
+    def __init__(self, args, p, Q, pk, torch, make, groups):
+        self.args, self.pk, self.torch, self.Q = args, pk, torch, Q
+        if p.nrhs % groups:
+            raise ValueError("--groups must divide the source count")
+        self.w = p.nrhs // groups
+        self.hs = [make() for _ in range(groups)]
+        self.tiles = [pk.helm_fine_tile(h, self.w) for h in self.hs]  # autotunes once per width
+        self.Qs = [Q[i * self.w:(i + 1) * self.w].contiguous() for i in range(groups)]
+
+    def solve(self, U, tol=1e-6):
+        a, pk = self.args, self.pk
+        if len(self.hs) == 1:
+            return [pk.helm_solve_block(self.hs[0], self.Q, U, tol=tol, restart=a.restart,
+                                        max_cycles=a.max_cycles, block_size=a.block_size, reorth=a.reorth)]
+        Us = [self.torch.zeros_like(q) for q in self.Qs]
+        infos = pk.helm_solve_batch(self.hs, self.Qs, Us, tol=tol, restart=a.restart, max_cycles=a.max_cycles,
+                                    block_size=a.block_size, reorth=a.reorth, max_threads=len(self.hs))
+        for i, u in enumerate(Us):
+            U[i * self.w:(i + 1) * self.w].copy_(u)
+        return infos
+
+    def close(self):
+        for h in self.hs:
+            h.close()
+        self.hs = []
+
+
 def fp64_compare(args, p, Q, pk, torch, Um=None):
-    """The plain FP64 GPU solver (GMRES(20) coarsest) on the same block: one
-    untimed warm-up solve, then one timed solve. With Um (the mixed-precision
+    """The plain FP64 GPU solver (GMRES(20) coarsest) on the same block, in
+    the same concurrent groups as the headline: one untimed warm-up solve,
+    then one timed solve. With Um (the mixed-precision
     result), the FP64 solve is continued to a 1e-10 relative residual
     (untimed, warm start) and the per-RHS relative error of Um and of the FP64
     1e-6 result against that reference is reported."""
-    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
-                       precision="fp64", coarse="gmres", coarse_iters=20)
-    pk.helm_fine_tile(hd, p.nrhs)
+    make = lambda: pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                                 precision="fp64", coarse="gmres", coarse_iters=20)
+    gs = GroupSolver(args, p, Q, pk, torch, make, args.groups)
     U = torch.zeros_like(Q)
-
-    def solve():
-        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
-                                   block_size=args.block_size, reorth=args.reorth)
-    solve()
+    gs.solve(U)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = solve()
+    infos = gs.solve(U)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = {"value": round(p.nrhs / dt, 4) if info["converged_all"] else 0.0, "unit": "RHS/s",
-           "cycles": info["cycles"], "max_relres": float(info["relres"].max())}
+    gs.close()
+    ok = all(i["converged_all"] for i in infos)
+    out = {"value": round(p.nrhs / dt, 4) if ok else 0.0, "unit": "RHS/s",
+           "cycles": max(i["cycles"] for i in infos), "max_relres": max(float(i["relres"].max()) for i in infos)}
     if Um is not None:
+        hd = make()  # one handle for the continuation of all columns
         Uref = U.clone()
         ref = pk.helm_solve_block(hd, Q, Uref, tol=1e-10, restart=args.restart, max_cycles=4000,
                                   block_size=args.block_size, reorth=args.reorth, warm_start=True)
@@ -180,31 +216,31 @@ def fp64_compare(args, p, Q, pk, torch, Um=None):
             "mixed_learned": {"max": float(em.max()), "median": float(sorted(em)[len(em) // 2])},
             "fp64_at_1e-6": {"max": float(e64.max()), "median": float(sorted(e64)[len(e64) // 2])}}
         del Uref
+        hd.close()
     return out
 
 
 def mixed_gmres_compare(args, p, Q, pk, torch):
     """The mixed-precision solver with the GMRES(20) coarsest solve from zero
-    (no network) and the same kernels, block size and orthogonalisation: one
-    untimed warm-up solve, then one timed solve. The learned coarsest
+    (no network) and the same kernels, block size, orthogonalisation and
+    concurrent groups: one untimed warm-up solve, then one timed solve. The learned coarsest
     correction's gain is the ratio of the two RHS/s figures."""
-    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
-                       precision="mixed", coarse="gmres", coarse_iters=20)
-    tile = pk.helm_fine_tile(hd, p.nrhs)
+    make = lambda: pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                                 precision="mixed", coarse="gmres", coarse_iters=20)
+    gs = GroupSolver(args, p, Q, pk, torch, make, args.groups)
     U = torch.zeros_like(Q)
-
-    def solve():
-        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
-                                   block_size=args.block_size, reorth=args.reorth)
-    solve()
+    gs.solve(U)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = solve()
+    infos = gs.solve(U)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": round(p.nrhs / dt, 4) if info["converged_all"] else 0.0, "unit": "RHS/s",
-            "cycles": info["cycles"], "max_relres": float(info["relres"].max()),
-            "coarsest": "GMRES(20) from zero", "fine_tile_rows_planes": list(tile)}
+    tile = gs.tiles[0]
+    gs.close()
+    ok = all(i["converged_all"] for i in infos)
+    return {"value": round(p.nrhs / dt, 4) if ok else 0.0, "unit": "RHS/s",
+            "cycles": max(i["cycles"] for i in infos), "max_relres": max(float(i["relres"].max()) for i in infos),
+            "coarsest": "GMRES(20) from zero", "fine_tile_rows_planes": list(tile), "groups": args.groups}
 
 
 def run_batch(args, pk, synth, np, torch):
@@ -394,6 +430,8 @@ def main():
     ap.add_argument("--mf-n", type=int, default=128, help="cells per axis of the multi-frequency workload")
     ap.add_argument("--threads", type=int, default=16, help="host threads of the batch workload")
     ap.add_argument("--reorth", type=int, default=0)
+    ap.add_argument("--groups", type=int, default=2,
+                    help="concurrent groups of single-column solves (one handle and stream each)")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--cpu-sample", action="store_true",
                     help="(internal) time the oracle's sample on the CPU and print JSON; no GPU")
@@ -453,39 +491,49 @@ def main():
         note(f"training the coarsest-grid network on {args.train_models} models at {args.train_n}^3")
         net_blob, net_info = train_in_child(args)
         note(f"trained in {net_info['train_s']} s, loss {net_info['loss_first']} -> {net_info['loss_last']}")
-    t0 = time.perf_counter()
-    hd = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
-                       precision=args.precision, coarse=args.coarse, coarse_iters=args.coarse_iters,
-                       net=net_blob, coarse_restarts=args.coarse_restarts)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
+    def make():
+        return pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                             precision=args.precision, coarse=args.coarse, coarse_iters=args.coarse_iters,
+                             net=net_blob, coarse_restarts=args.coarse_restarts)
+
     Q = torch.from_numpy(p.Q).cuda()
     U = torch.zeros_like(Q)
-    tile = pk.helm_fine_tile(hd, p.nrhs)  # autotunes the finest-level stencil tile once
-
-    def step():
-        return pk.helm_solve_block(hd, Q, U, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
-                                   block_size=args.block_size, reorth=args.reorth)
+    t0 = time.perf_counter()
+    gs = GroupSolver(args, p, Q, pk, torch, make, args.groups)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
 
     note("tuned; warm-up")
     for _ in range(args.warmup):
-        step()
+        gs.solve(U)
     note("timed steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = [step() for _ in range(args.steps)]
+    steps = [gs.solve(U) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
-    cycles = [i["cycles"] for i in infos]
+    gtiles = gs.tiles
+    gs.close()
+    infos = [i for st in steps for i in st]
+    cycles = [max(i["cycles"] for i in st) for st in steps]
     ok = all(i["converged_all"] for i in infos)
     relres = max(float(i["relres"].max()) for i in infos)
     value = p.nrhs * args.steps / dt if ok else 0.0
 
-    # one more step with per-kernel HIP events (recorded on the solve's
-    # stream around every launch) for the roofline and the time per class;
-    # kept out of the timed steps above
+    # one more solve, of all 64 columns on one handle and one stream, with
+    # per-kernel HIP events (recorded on the solve's stream around every
+    # launch) for the roofline and the time per class; kept out of the timed
+    # steps above (with concurrent groups, events on one stream would also
+    # time the other groups' kernels)
     note("profiled step")
+    hd = make()
+    tile = pk.helm_fine_tile(hd, p.nrhs)  # autotunes the finest-level stencil tile once
+    Up = torch.zeros_like(Q)
+
+    def step():
+        return pk.helm_solve_block(hd, Q, Up, tol=1e-6, restart=args.restart, max_cycles=args.max_cycles,
+                                   block_size=args.block_size, reorth=args.reorth)
     pk.helm_profile_enable(hd, True)
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
@@ -494,6 +542,8 @@ def main():
     tp1 = time.perf_counter()
     stats = pk.helm_profile_read(hd)
     pk.helm_profile_enable(hd, False)
+    hd.close()
+    del Up
 
     # roofline of the dominant finest-level kernel (the HBM-bound class with
     # the most time in the profiled step), and the fraction of every class
@@ -520,8 +570,13 @@ def main():
             "fine_kernels": fine}
     per_step = {k: round(v[1], 2) for k, v in stats.items()}
 
-    blk = ("64 single-column FGMRES({r}) solves sharing every launch (block size 1)" if args.block_size == 1
+    blk = ("64 single-column FGMRES({r}) solves (block size 1)" if args.block_size == 1
            else f"block FGMRES({{r}}), blocks of {args.block_size}").format(r=args.restart)
+    if args.groups > 1:
+        blk += (f" in {args.groups} concurrent groups of {p.nrhs // args.groups} columns (one handle and "
+                f"stream each; the columns of a group share every launch)")
+    else:
+        blk += " sharing every launch"
     out = {
         "metric": "RHS solved/sec to 1e-6 rel. residual, 3D 192\u00b3 x 64 src; mixed+learned vs FP64",
         "value": round(value, 4), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
@@ -539,6 +594,7 @@ def main():
                    "precision": args.precision, "block_size": args.block_size, "reorth": args.reorth,
                    "cycles_per_step": cycles, "max_relres": relres, "converged": ok,
                    "setup_s": round(t_setup, 2), "fine_tile_rows_planes": list(tile),
+                   "groups": args.groups, "group_tiles": [list(t) for t in gtiles],
                    "kernel_ms_profiled_step": per_step,
                    "fallbacks": sum(i["fallback_used"] for i in infos)},
         "roofline": roof,
