@@ -65,6 +65,8 @@ def fine_kernel_bytes(prec, N, Nc, P):
     return {
         "fine_sweep": fine_sweep_bytes(prec, N, P),             # u, f -> u
         "fine_sweep01": N * (2 * s * P + coef),                 # f -> u (two sweeps from zero)
+        # f -> u (two sweeps from zero) and r_c (restricted residual); D and w/D
+        "fine_pre_rr": N * (2 * s * P + 2 * coef) + Nc * sc * P,
         "fine_sweep0": N * (2 * s * P + coef),                  # f -> u
         "fine_prosweep": fine_sweep_bytes(prec, N, P) + Nc * sc * P,  # u, f, e_c -> u
         "fine_resid": N * (2 * s * P + coef) + Nc * sc * P,     # u, f -> r_c (restricted)

@@ -334,6 +334,8 @@ enum {
   HELM_K_FINE_PROSWEEP,  /* the first post-smoothing sweep with the prolongation fused in */
   HELM_K_FINE_SWEEP01,   /* the zero-guess sweep and the next sweep fused in one pass (3D,
                             LDS-blocked tiles) */
+  HELM_K_FINE_PRE_RR,    /* the two pre-sweeps from a zero guess, the residual and the
+                            restriction fused in one pass (3D, exactly two pre-sweeps) */
   HELM_K_NCLASS
 };
 typedef struct {

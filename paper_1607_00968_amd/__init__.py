@@ -51,7 +51,8 @@ ABI_SYMBOLS = (
     "helm_fields_pack16", "helm_fields_unpack16", "helm_jvp", "helm_jtvp", "helm_setup_batch",
 )
 KERNEL_CLASSES = ("fine_sweep", "fine_resid", "outer_apply", "transfer", "coarse_sweep",
-                  "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep", "fine_sweep01")
+                  "coarsest", "gram", "update", "fine_sweep0", "fine_prosweep", "fine_sweep01",
+                  "fine_pre_rr")
 
 
 class HelmError(RuntimeError):

@@ -382,7 +382,15 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   void* b = (a == out) ? tmp : out;
   Level& C = c->lv[l + 1];
   const Prec pf = field_prec(c, l), pc = field_prec(c, l + 1), pt = comp_prec(c);
-  if (npre >= 1) {
+  bool fused = false;
+  if (npre == 2 && l == 0 && c->dim == 3 && !c->plan && can_pre_rr(pf, pc, pt, L.geo(P))) {
+    // both pre-sweeps from a zero guess, the residual and the restriction in
+    // one pass: b = JAC(w D^-1 f), C.F = R (f - M b)
+    Prof pr(c, HELM_K_FINE_PRE_RR, s);
+    const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;
+    fused = launch_pre_rr(pf, pc, pt, L.geo(P), C.geo(P), f, b, C.F, diag, level_dw(c, 0), L.ih, s);
+    std::swap(a, b);
+  } else if (npre >= 1) {
     int k1 = 1;
     if (l == 0 && c->dim == 3 && npre >= 2 && !c->plan && can_sweep01(pf, pt, L.geo(P))) {
       // the zero-guess sweep and the next one in one pass: b = JAC(w D^-1 f),
@@ -402,8 +410,7 @@ static void cycle_rec(helm_ctx* c, int l, int P, const void* f, void* out, void*
   } else {
     zero_field(c, l, P, a, s);
   }
-  bool fused = false;
-  if (l == 0 && c->dim == 3 && !c->plan && can_resid_restrict(pf, pc, pt, L.geo(P))) {
+  if (!fused && l == 0 && c->dim == 3 && !c->plan && can_resid_restrict(pf, pc, pt, L.geo(P))) {
     // residual and restriction in one pass (counted as the fine residual)
     Prof pr(c, HELM_K_FINE_RESID, s);
     const void* diag = c->precision == HELM_FP64 ? (const void*)L.dM : (const void*)L.dM32;

@@ -1082,6 +1082,288 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
 }
 
 // ---------------------------------------------------------------------------
+// Fused pre-smoothing, residual and restriction on the finest 3D level (the
+// cycle with two pre-sweeps): from f alone, u1 = (w/D) f (the sweep from a
+// zero guess), u2 = u1 + (w/D)(f - M u1) (the second sweep), then
+// r = f - M u2 and r_c = R r, in one pass. The tile is that of
+// k_resid_restrict (8 x 8 coarse nodes, one 64-byte column group, a chunk of
+// RZC coarse planes): the residual needs u2 on the 19 x 19 points around its
+// 17 x 17 fine points, and u2 there needs u1 on 21 x 21. Marching through the
+// fine planes t, a workgroup forms u1(t) (LDS, with its ring), then u2(t) on
+// 19 x 19 (kept one plane in LDS for the residual's in-plane neighbours),
+// writes the u2 points the tile owns, and forms the residual of plane t - 1
+// with the restriction of k_resid_restrict. Every value is formed with the
+// operations, and in the order, of the sweep kernels and of
+// k_resid_restrict, so u2 and r_c are bitwise those of the unfused path;
+// u2 is written but never re-read, and f is read once.
+// ---------------------------------------------------------------------------
+constexpr int RV = RU + 2;  // fine u1 points per axis (the ring of the u2 region)
+// Lanes per workgroup: 1024 for FP32 fields (two u2 tasks per lane, within
+// 128 VGPRs); FP64 fields need more registers per task and run 512 lanes.
+template <class T> constexpr int prr_lanes() { return sizeof(T) == 4 ? 1024 : 512; }
+
+template <class S, class SO, class T, int PRR_L = prr_lanes<T>()>
+__global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int nxb, int nyb, int64_t ntiles, int per,
+                                                const S* __restrict__ f, S* __restrict__ u2o, SO* __restrict__ rc,
+                                                const cx<T>* __restrict__ dg, const cx<T>* __restrict__ dw, T ihx,
+                                                T ihy, T ihz) {
+  constexpr int CG = 64 / (int)sizeof(S);  // columns per group
+  constexpr int K = CG / 4;                 // columns per lane (16 B)
+  constexpr int NU = RU * RU * 4;           // u2 tasks (point, slot)
+  constexpr int NT = (NU + PRR_L - 1) / PRR_L;  // u2 tasks per lane
+  constexpr int NRV = 4 * RV - 4;           // ring points of the u1 region
+  // plane rings: u1 of t (and t - 1, the z - 1 neighbour of u2(t)), u2 of
+  // t - 1 (and t - 2, the z - 1 neighbour of r(t - 1)), by plane parity
+  __shared__ cx<T> sv2[2][RV * RV * CG];  // u1, with the ring
+  __shared__ cx<T> su2[2][RU * RU * CG];  // u2
+  __shared__ cx<T> sr[RF * RF * CG];      // r(t - 1)
+  const int64_t t0 = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t0 >= ntiles) return;  // whole workgroup leaves together
+  int64_t tt = t0;
+  const int cgi = (int)(tt % ncg);
+  tt /= ncg;
+  const int yb = (int)(tt % nyb);
+  tt /= nyb;
+  const int xb = (int)(tt % nxb);
+  const int zci = (int)(tt / nxb);
+  const int Z0 = zci * RZC, Z1 = Z0 + RZC < gc.nz ? Z0 + RZC : gc.nz;
+  const bool last_chunk = Z1 == gc.nz;
+  const int fx0 = 2 * RT * xb, fy0 = 2 * RT * yb;  // fine origin of the residual region
+  const int sl = threadIdx.x & 3;                  // the same slot for all of a lane's tasks
+  const int c = cgi * CG + sl * K;
+  const int64_t plane = (int64_t)gf.nx * gf.ny;
+  // u2 tasks of this lane: point (ux, uy) of the 19 x 19 region (fine
+  // (fx0 - 1 + ux, fy0 - 1 + uy)); the inner 17 x 17 are residual points
+  int ux[NT], uy[NT];
+  bool uon[NT], uin[NT], res[NT], own[NT];
+  int64_t ucol[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int task = threadIdx.x + PRR_L * i;
+    const int p = task >> 2;
+    uon[i] = task < NU;
+    ux[i] = p % RU;
+    uy[i] = p / RU;
+    const int gx = fx0 - 1 + ux[i], gy = fy0 - 1 + uy[i];
+    uin[i] = uon[i] && gx >= 0 && gx < gf.nx && gy >= 0 && gy < gf.ny;
+    res[i] = uon[i] && ux[i] >= 1 && ux[i] <= RF && uy[i] >= 1 && uy[i] <= RF;
+    // the u2 points this tile writes: its 16 x 16 core (every fine point once)
+    own[i] = uin[i] && ux[i] >= 1 && ux[i] <= 2 * RT && uy[i] >= 1 && uy[i] <= 2 * RT;
+    ucol[i] = uin[i] ? (int64_t)gy * gf.nx + gx : 0;
+  }
+  // ring task of this lane (lanes 0 .. 4*NRV-1): u1-region coordinates (hx, hy)
+  const int rp = threadIdx.x >> 2;
+  int hx, hy;
+  if (rp < RV) {
+    hx = rp;
+    hy = 0;
+  } else if (rp < 2 * RV) {
+    hx = rp - RV;
+    hy = RV - 1;
+  } else if (rp < 2 * RV + RU) {
+    hx = 0;
+    hy = rp - 2 * RV + 1;
+  } else {
+    hx = RV - 1;
+    hy = rp - 2 * RV - RU + 1;
+  }
+  const bool ring = rp < NRV;
+  const int gxr = fx0 - 2 + hx, gyr = fy0 - 2 + hy;
+  const bool ringin = ring && gxr >= 0 && gxr < gf.nx && gyr >= 0 && gyr < gf.ny;
+  const int64_t ringcol = ringin ? (int64_t)gyr * gf.nx + gxr : 0;
+  // accumulation task (lanes 0..255): coarse node (ax, ay) of the tile
+  const int aq = threadIdx.x >> 2;
+  const int ax = aq % RT, ay = aq / RT;
+  const int X = RT * xb + ax, Y = RT * yb + ay;
+  const bool acc_on = threadIdx.x < 4 * RT * RT && X < gc.nx && Y < gc.ny;
+  // per task: f at t - 1 (residual), t, t + 1; w/D at t, t + 1; D at t - 1
+  // (residual) and t
+  cx<T> fR[NT][K], fA[NT][K], fB[NT][K];
+  cx<T> wA[NT], wB[NT], dA[NT], dR[NT];
+  const int zf0 = 2 * Z0, zf1 = 2 * Z1;  // residual planes of this chunk (inclusive)
+  const int tb = zf0 - 1, te = zf1 + 1;  // u2 planes this chunk forms
+  auto ok_plane = [&](int z) { return z >= 0 && z < gf.nz; };
+  // prologue: u1(tb - 1) of the own points into its plane slot (only the own
+  // point of it is read), f and w/D of plane tb
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const bool okm = uin[i] && ok_plane(tb - 1), okc = uin[i] && ok_plane(tb);
+    cx<T> fm[K];
+    ldKz<K, S, T>(f + ((int64_t)(tb - 1) * plane + ucol[i]) * gf.P + c, okm, fm);
+    const cx<T> wm = okm ? dw[(int64_t)(tb - 1) * plane + ucol[i]] : cx<T>{};
+    if (uon[i]) {
+      const int o = ((uy[i] + 1) * RV + ux[i] + 1) * CG + sl * K;
+#pragma unroll
+      for (int k = 0; k < K; ++k) sv2[(tb - 1) & 1][o + k] = wm * fm[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) fR[i][k] = cx<T>{};
+    ldKz<K, S, T>(f + ((int64_t)tb * plane + ucol[i]) * gf.P + c, okc, fA[i]);
+    wA[i] = okc ? dw[(int64_t)tb * plane + ucol[i]] : cx<T>{};
+    dR[i] = cx<T>{};
+  }
+  cx<T> accA[K], accB[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) accA[k] = accB[k] = {(T)0, (T)0};
+  for (int t = tb; t <= te; ++t) {
+    cx<T>* const sv = sv2[t & 1];        // u1(t)
+    const cx<T>* const svm = sv2[(t - 1) & 1];  // u1(t - 1)
+    cx<T>* const su = su2[(t - 1) & 1];  // u2(t - 1); u2(t) goes to the other slot
+    const cx<T>* const sum2 = su2[t & 1];  // u2(t - 2)
+    // plane t + 1 of f and w/D (own points), D at t, and the u1 ring of t
+    cx<T> fr[K], wr{};
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const bool okn = uin[i] && ok_plane(t + 1), okc = uin[i] && ok_plane(t);
+      ldKz<K, S, T>(f + ((int64_t)(t + 1) * plane + ucol[i]) * gf.P + c, okn, fB[i]);
+      wB[i] = okn ? dw[(int64_t)(t + 1) * plane + ucol[i]] : cx<T>{};
+      dA[i] = okc ? dg[(int64_t)t * plane + ucol[i]] : cx<T>{};
+    }
+    if (ring) {
+      const bool ok = ringin && ok_plane(t);
+      ldKz<K, S, T>(f + ((int64_t)t * plane + ringcol) * gf.P + c, ok, fr);
+      wr = ok ? dw[(int64_t)t * plane + ringcol] : cx<T>{};
+    }
+    // u1(t) into LDS: own points and the ring (the sweep from zero, w/D f)
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      if (!uon[i]) continue;
+      const int o = ((uy[i] + 1) * RV + ux[i] + 1) * CG + sl * K;
+#pragma unroll
+      for (int k = 0; k < K; ++k) sv[o + k] = wA[i] * fA[i][k];
+    }
+    if (ring) {
+      const int o = (hy * RV + hx) * CG + sl * K;
+#pragma unroll
+      for (int k = 0; k < K; ++k) sv[o + k] = wr * fr[k];
+    }
+    __syncthreads();
+    // u2(t) on the 19 x 19 region: the second sweep, as the LDS-tiled sweep
+    // forms it (0 outside the grid)
+    const bool tin = ok_plane(t);
+    const bool t_own = t >= zf0 && (t < zf1 || (last_chunk && t == zf1)) && tin;
+    cx<T> u2c[NT][K];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) u2c[i][k] = cx<T>{};
+      if (!uin[i] || !tin) continue;
+      const int o = ((uy[i] + 1) * RV + ux[i] + 1) * CG + sl * K;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const cx<T> us = wA[i] * fA[i][k];
+        const cx<T> zp = wB[i] * fB[i][k];
+        cx<T> acc = dA[i] * us;
+        cx<T> sum = ihz * (svm[o + k] + zp) + ihy * (sv[o - RV * CG + k] + sv[o + RV * CG + k]);
+        sum = sum + ihx * sv[o - CG + k];
+        sum = sum + ihx * sv[o + CG + k];
+        acc = acc - sum;
+        u2c[i][k] = us + wA[i] * (fA[i][k] - acc);
+      }
+      if (own[i] && t_own) stK<K, S, T>(u2o + ((int64_t)t * plane + ucol[i]) * gf.P + c, u2c[i]);
+    }
+    // the residual of plane t - 1 (u2 of t - 1 in LDS, of t - 2 and t in
+    // registers), as k_resid_restrict forms it, into sr
+    const int zr = t - 1;
+    const bool do_res = zr >= zf0 && zr <= zf1;
+    if (do_res) {
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        if (!res[i]) continue;
+        cx<T> rv[K];
+        if (uin[i]) {
+          const int o = (uy[i] * RU + ux[i]) * CG + sl * K;
+          const cx<T> d = dR[i];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            cx<T> acc = d * su[o + k];
+            cx<T> sum = ihz * (sum2[o + k] + u2c[i][k]) + ihy * (su[o - RU * CG + k] + su[o + RU * CG + k]);
+            sum = sum + ihx * su[o - CG + k];
+            sum = sum + ihx * su[o + CG + k];
+            acc = acc - sum;
+            rv[k] = fR[i][k] - acc;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) rv[k] = {(T)0, (T)0};
+        }
+        const int orr = ((uy[i] - 1) * RF + ux[i] - 1) * CG + sl * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sr[orr + k] = rv[k];
+      }
+    }
+    __syncthreads();
+    if (do_res && acc_on) {
+      // fine plane zf = 2 Z + 1 + dz: odd planes are dz = 0 of Z = (zf - 1) / 2;
+      // even planes close Z = zf / 2 - 1 (dz = +1) and open Z = zf / 2 (dz = -1)
+      const int zf = zr;
+      const bool odd = zf & 1;
+      const int nrole = odd ? 1 : 2;
+      for (int role = 0; role < nrole; ++role) {
+        const int dz = odd ? 0 : (role == 0 ? 1 : -1);
+        const int Zc = odd ? (zf - 1) / 2 : (role == 0 ? zf / 2 - 1 : zf / 2);
+        if (Zc < Z0 || Zc >= Z1) continue;
+        cx<T>* acc = role == 0 ? accA : accB;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const T w = (dx ? (T)0.5 : (T)1) * (dy ? (T)0.5 : (T)1) * (dz ? (T)0.5 : (T)1);
+            const int o = ((2 * ay + 1 + dy) * RF + 2 * ax + 1 + dx) * CG + sl * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * sr[o + k];
+          }
+        if (dz == 1) {  // Zc complete
+          cx<T> outv[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) outv[k] = (T)0.125 * accA[k];
+          const int64_t I = ((int64_t)Zc * gc.ny + Y) * gc.nx + X;
+          st_own<K, SO, T>(rc + I * gc.P + c, outv);
+        }
+      }
+      if (!odd) {  // the plane opened on accB continues on accA
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          accA[k] = accB[k];
+          accB[k] = {(T)0, (T)0};
+        }
+      }
+    }
+    // u2(t) into the slot of u2(t - 2) (every reader of it has passed the
+    // barrier above); shift the planes
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      if (uon[i]) {
+        const int o = (uy[i] * RU + ux[i]) * CG + sl * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) su2[t & 1][o + k] = u2c[i][k];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        fR[i][k] = fA[i][k];
+        fA[i][k] = fB[i][k];
+      }
+      dR[i] = dA[i];
+      wA[i] = wB[i];
+    }
+  }
+}
+
+template <class S, class SO, class T>
+static void pre_rr_launch(const Geo& gf, const Geo& gc, const void* f, void* u2, void* rc, const void* dg,
+                          const void* dw, const double ih[3], hipStream_t s) {
+  constexpr int CG = 64 / (int)sizeof(S);
+  const int ncg = gf.P / CG;
+  const int nxb = (gc.nx + RT - 1) / RT, nyb = (gc.ny + RT - 1) / RT, nzc = (gc.nz + RZC - 1) / RZC;
+  const int64_t ntiles = (int64_t)ncg * nxb * nyb * nzc;
+  const int per = (int)((ntiles + 7) / 8);
+  hipLaunchKernelGGL((k_pre_rr<S, SO, T>), dim3((unsigned)(8 * (int64_t)per)), dim3(prr_lanes<T>()), 0, s, gf, gc,
+                     ncg, nxb, nyb,
+                     ntiles, per, (const S*)f, (S*)u2, (SO*)rc, (const cx<T>*)dg, (const cx<T>*)dw, (T)ih[0],
+                     (T)ih[1], (T)ih[2]);
+}
+
+// ---------------------------------------------------------------------------
 // 3D Galerkin-level operator (27-point stencil), z-marching through LDS: a
 // 256-lane workgroup owns an 8 x 8 tile of grid columns for one 128-byte group
 // of right-hand sides (32 BF16 pairs, 16 complex64 or 8 complex128) and a
@@ -1282,6 +1564,28 @@ bool launch_resid_restrict(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& 
   }
   if (pf == P64 && pc == P64 && pt == P64 && gf.P % 4 == 0) {
     resid_restrict_launch<c128, c128, double>(gf, gc, u, f, rc, dg, ih, s);
+    return true;
+  }
+  return false;
+}
+
+bool can_pre_rr(Prec pf, Prec pc, Prec pt, const Geo& gf) {
+  return can_sweep01(pf, pt, gf) && can_resid_restrict(pf, pc, pt, gf);
+}
+
+bool launch_pre_rr(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* f, void* u2, void* rc,
+                   const void* dg, const void* dw, const double ih[3], hipStream_t s) {
+  if (!can_pre_rr(pf, pc, pt, gf)) return false;
+  if (pf == P32 && pc == PBF && pt == P32) {
+    pre_rr_launch<c64, cbf, float>(gf, gc, f, u2, rc, dg, dw, ih, s);
+    return true;
+  }
+  if (pf == P32 && pc == P32 && pt == P32) {
+    pre_rr_launch<c64, c64, float>(gf, gc, f, u2, rc, dg, dw, ih, s);
+    return true;
+  }
+  if (pf == P64 && pc == P64 && pt == P64) {
+    pre_rr_launch<c128, c128, double>(gf, gc, f, u2, rc, dg, dw, ih, s);
     return true;
   }
   return false;

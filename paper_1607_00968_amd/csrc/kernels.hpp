@@ -51,6 +51,13 @@ bool launch_prolong_sweep(Prec pc, Prec pf, Prec pt, const Geo& gf, const Geo& g
 // out = JAC(w D^-1 f), bitwise the zero-guess sweep followed by a sweep.
 // Available (can_sweep01) for the LDS-blocked tiles and FP32 / FP64 fields.
 bool can_sweep01(Prec pf, Prec pt, const Geo& g);
+// The two pre-sweeps from a zero guess, the residual and the restriction in
+// one pass on the finest 3D level (k_pre_rr): u2 (the second sweep's result)
+// into u2, the restricted residual into rc; bitwise the sweep01 +
+// resid_restrict pair. Available where both of those are.
+bool can_pre_rr(Prec pf, Prec pc, Prec pt, const Geo& gf);
+bool launch_pre_rr(Prec pf, Prec pc, Prec pt, const Geo& gf, const Geo& gc, const void* f, void* u2, void* rc,
+                   const void* dg, const void* dw, const double ih[3], hipStream_t s);
 void launch_sweep01(Prec pf, Prec pt, const Geo& g, const void* f, void* out, const void* dg, const void* dw,
                     const double ih[3], hipStream_t s);
 FineTile get_fine_tile();
