@@ -262,8 +262,12 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty,
     }
 }
 
-// Same tiling with plane reuse, for NT <= 2 (all 27 taps of weights fit in
-// LDS next to the halo). Wave w owns a 16-voxel xy patch (rows 2w, 2w+1 of
+// Same tiling with plane reuse, for NT <= 2. The halo is staged in LDS. With
+// 16 output channels the B fragments of the weights (27 x 16 rows of 32 B per
+// chunk, read by every workgroup) come from the caches, so that the LDS holds
+// only the halo (20 KB: eight workgroups per CU; 463 -> 385 us per launch at
+// 48^3 x 64); with 32 they are staged in LDS next to it (reading them from
+// the caches was slower there, 130 -> 159 us). Wave w owns a 16-voxel xy patch (rows 2w, 2w+1 of
 // the 8x8 block) through all 4 output planes. For each in-plane tap offset it
 // walks the 6 halo planes once: every input fragment it reads from LDS feeds
 // the MFMAs of up to 3 output planes (one per z tap), which halves the LDS
@@ -273,9 +277,10 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
                                                   int64_t per) {
   extern __shared__ uint4 lds_u4[];
   bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH], rows padded
-  bf16* ws = xs + CH_PAD_U4 * 8;               // [27][N][CCH]
+  bf16* ws = xs + CH_PAD_U4 * 8;               // [27][N][CCH] when staged
   constexpr int N = NT * 16;
   constexpr int SG = FLIP ? -1 : 1;
+  constexpr bool WLDS = NT >= 2;  // weights staged in LDS
   const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= ntiles) return;  // whole workgroup leaves together
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -308,11 +313,12 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
                                               a.offi + c0 + half * 8);
       lds_u4[halo_u4(hv) + half] = val;
     }
-    for (int e = threadIdx.x; e < 27 * N * 2; e += 256) {
-      const int row = e >> 1, half = e & 1;  // row = tap * N + n
-      lds_u4[CH_PAD_U4 + wrow_u4(row, half)] =
-          *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
-    }
+    if (WLDS)
+      for (int e = threadIdx.x; e < 27 * N * 2; e += 256) {
+        const int row = e >> 1, half = e & 1;  // row = tap * N + n
+        lds_u4[CH_PAD_U4 + wrow_u4(row, half)] =
+            *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
+      }
     __syncthreads();
 #pragma unroll 1
     for (int txy = 0; txy < 9; ++txy) {
@@ -324,7 +330,9 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-          Bt[k][nt] = *reinterpret_cast<const short4_*>(ws + wrow_el((txy + 9 * k) * N + nt * 16 + ml, kg));
+          Bt[k][nt] = WLDS ? *reinterpret_cast<const short4_*>(ws + wrow_el((txy + 9 * k) * N + nt * 16 + ml, kg))
+                           : *reinterpret_cast<const short4_*>(
+                                 a.W + (int64_t)((txy + 9 * k) * N + nt * 16 + ml) * a.Cin + c0 + kg * 4);
 #pragma unroll
       for (int p = 0; p < CH_Z; ++p) {
         const short4_ A = *reinterpret_cast<const short4_*>(
@@ -365,7 +373,7 @@ static void conv3_zr_launch(const ConvArgs& a, hipStream_t s) {
   const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
   const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
   const int64_t per = (ntiles + 7) / 8;
-  const size_t lds = sizeof(bf16) * (CH_PAD_U4 * 8 + 27 * NT * 16 * CCH);
+  const size_t lds = sizeof(bf16) * (CH_PAD_U4 * 8 + (NT >= 2 ? 27 * NT * 16 * CCH : 0));
   hipLaunchKernelGGL((k_conv3_zr<NT, FLIP>), dim3((unsigned)(8 * per)), dim3(256), lds, s, a, ntx, nty, ntz, ntiles,
                      per);
 }
