@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   // t - 1 (and t - 2, the z - 1 neighbour of r(t - 1)), by plane parity
   __shared__ cx<T> sv2[2][RV * RV * CG];  // u1, with the ring
   __shared__ cx<T> su2[2][RU * RU * CG];  // u2
-  __shared__ cx<T> sr[RF * RF * CG];      // r(t - 1)
+  __shared__ cx<T> sr2[2][RF * RF * CG];  // r(t - 1) (and r(t - 2), restricted one plane later)
   const int64_t t0 = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t0 >= ntiles) return;  // whole workgroup leaves together
   int64_t tt = t0;
@@ -1205,6 +1205,48 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   cx<T> accA[K], accB[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) accA[k] = accB[k] = {(T)0, (T)0};
+  // the restriction of residual plane zf (sr: that plane), as k_resid_restrict
+  // adds it
+  auto restrict_plane = [&](int zf, const cx<T>* sr) {
+    if (zf < zf0 || zf > zf1 || !acc_on) return;
+    // fine plane zf = 2 Z + 1 + dz: odd planes are dz = 0 of Z = (zf - 1) / 2;
+    // even planes close Z = zf / 2 - 1 (dz = +1) and open Z = zf / 2 (dz = -1)
+    const bool odd = zf & 1;
+    const int nrole = odd ? 1 : 2;
+    for (int role = 0; role < nrole; ++role) {
+      const int dz = odd ? 0 : (role == 0 ? 1 : -1);
+      const int Zc = odd ? (zf - 1) / 2 : (role == 0 ? zf / 2 - 1 : zf / 2);
+      if (Zc < Z0 || Zc >= Z1) continue;
+      cx<T>* acc = role == 0 ? accA : accB;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const T w = (dx ? (T)0.5 : (T)1) * (dy ? (T)0.5 : (T)1) * (dz ? (T)0.5 : (T)1);
+          const int o = ((2 * ay + 1 + dy) * RF + 2 * ax + 1 + dx) * CG + sl * K;
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * sr[o + k];
+        }
+      if (dz == 1) {  // Zc complete
+        cx<T> outv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) outv[k] = (T)0.125 * accA[k];
+        const int64_t I = ((int64_t)Zc * gc.ny + Y) * gc.nx + X;
+        st_own<K, SO, T>(rc + I * gc.P + c, outv);
+      }
+    }
+    if (!odd) {  // the plane opened on accB continues on accA
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        accA[k] = accB[k];
+        accB[k] = {(T)0, (T)0};
+      }
+    }
+  };
+  // One barrier per plane: after it, every lane's u1(t) and ring are in LDS,
+  // and so are u2(t - 1) and the residual of plane t - 2 (written during the
+  // previous plane), which is restricted first. Each buffer alternates by
+  // plane parity, so what one plane writes is read after the next barrier.
   for (int t = tb; t <= te; ++t) {
     cx<T>* const sv = sv2[t & 1];        // u1(t)
     const cx<T>* const svm = sv2[(t - 1) & 1];  // u1(t - 1)
@@ -1238,6 +1280,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
       for (int k = 0; k < K; ++k) sv[o + k] = wr * fr[k];
     }
     __syncthreads();
+    restrict_plane(t - 2, sr2[(t - 1) & 1]);
     // u2(t) on the 19 x 19 region: the second sweep, as the LDS-tiled sweep
     // forms it (0 outside the grid)
     const bool tin = ok_plane(t);
@@ -1289,48 +1332,12 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
         }
         const int orr = ((uy[i] - 1) * RF + ux[i] - 1) * CG + sl * K;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sr[orr + k] = rv[k];
+        for (int k = 0; k < K; ++k) sr2[t & 1][orr + k] = rv[k];
       }
     }
-    __syncthreads();
-    if (do_res && acc_on) {
-      // fine plane zf = 2 Z + 1 + dz: odd planes are dz = 0 of Z = (zf - 1) / 2;
-      // even planes close Z = zf / 2 - 1 (dz = +1) and open Z = zf / 2 (dz = -1)
-      const int zf = zr;
-      const bool odd = zf & 1;
-      const int nrole = odd ? 1 : 2;
-      for (int role = 0; role < nrole; ++role) {
-        const int dz = odd ? 0 : (role == 0 ? 1 : -1);
-        const int Zc = odd ? (zf - 1) / 2 : (role == 0 ? zf / 2 - 1 : zf / 2);
-        if (Zc < Z0 || Zc >= Z1) continue;
-        cx<T>* acc = role == 0 ? accA : accB;
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const T w = (dx ? (T)0.5 : (T)1) * (dy ? (T)0.5 : (T)1) * (dz ? (T)0.5 : (T)1);
-            const int o = ((2 * ay + 1 + dy) * RF + 2 * ax + 1 + dx) * CG + sl * K;
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc[k] = acc[k] + w * sr[o + k];
-          }
-        if (dz == 1) {  // Zc complete
-          cx<T> outv[K];
-#pragma unroll
-          for (int k = 0; k < K; ++k) outv[k] = (T)0.125 * accA[k];
-          const int64_t I = ((int64_t)Zc * gc.ny + Y) * gc.nx + X;
-          st_own<K, SO, T>(rc + I * gc.P + c, outv);
-        }
-      }
-      if (!odd) {  // the plane opened on accB continues on accA
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          accA[k] = accB[k];
-          accB[k] = {(T)0, (T)0};
-        }
-      }
-    }
-    // u2(t) into the slot of u2(t - 2) (every reader of it has passed the
-    // barrier above); shift the planes
+    // u2(t) into the slot of u2(t - 2) (its only reader in this plane is this
+    // lane's own residual above; the neighbours of u2(t - 2) were read before
+    // this plane's barrier); shift the planes
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
       if (uon[i]) {
@@ -1347,6 +1354,9 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
       wA[i] = wB[i];
     }
   }
+  // the residual of the last plane, written before the loop ended
+  __syncthreads();
+  restrict_plane(te - 1, sr2[te & 1]);
 }
 
 template <class S, class SO, class T>
