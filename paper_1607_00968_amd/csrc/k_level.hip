@@ -46,6 +46,15 @@ template <int K, class S, class T> __device__ inline void ldKz(const S* p, bool 
     for (int k = 0; k < K; ++k) o[k] = {(T)0, (T)0};
   }
 }
+// A workgroup barrier that orders LDS accesses only. __syncthreads() also
+// waits for every outstanding global load of the lane; this one lets loads
+// issued before it (operands of a later step that no other lane writes) stay
+// in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 template <int K, class S, class T> __device__ inline void stK(S* p, const cx<T>* o) {
 #pragma unroll
   for (int k = 0; k < K; k += St<S>::R) st16<T>(p + k, o + k);
@@ -1100,7 +1109,7 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
 constexpr int RV = RU + 2;  // fine u1 points per axis (the ring of the u2 region)
 // Lanes per workgroup: 1024 for FP32 fields (two u2 tasks per lane, within
 // 128 VGPRs); FP64 fields need more registers per task and run 512 lanes.
-template <class T> constexpr int prr_lanes() { return sizeof(T) == 4 ? 1024 : 512; }
+template <class T> constexpr int prr_lanes() { return sizeof(T) == 4 ? 768 : 512; }
 
 template <class S, class SO, class T, int PRR_L = prr_lanes<T>()>
 __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int nxb, int nyb, int64_t ntiles, int per,
@@ -1177,20 +1186,37 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   const int X = RT * xb + ax, Y = RT * yb + ay;
   const bool acc_on = threadIdx.x < 4 * RT * RT && X < gc.nx && Y < gc.ny;
   // per task: f at t - 1 (residual), t, t + 1; w/D at t, t + 1; D at t - 1
-  // (residual) and t
+  // (residual) and t; the ring's f and w/D at t
   cx<T> fR[NT][K], fA[NT][K], fB[NT][K];
   cx<T> wA[NT], wB[NT], dA[NT], dR[NT];
+  cx<T> frA[K], wrA{};
   const int zf0 = 2 * Z0, zf1 = 2 * Z1;  // residual planes of this chunk (inclusive)
   const int tb = zf0 - 1, te = zf1 + 1;  // u2 planes this chunk forms
   auto ok_plane = [&](int z) { return z >= 0 && z < gf.nz; };
+  // Every global load is issued by every lane, from a clamped address, and
+  // zeroed where it lies outside the grid or the lane has no such task: with
+  // no load behind a branch, a wait for one plane's operands leaves the next
+  // plane's loads in flight.
+  auto ld_f = [&](int z, int64_t col, bool ok, cx<T>* o) {
+    const int zc = z < 0 ? 0 : (z >= gf.nz ? gf.nz - 1 : z);
+    ldK<K, S, T>(f + ((int64_t)zc * plane + col) * gf.P + c, o);
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = ok ? o[k] : cx<T>{};
+  };
+  auto ld_c = [&](const cx<T>* a, int z, int64_t col, bool ok) {
+    const int zc = z < 0 ? 0 : (z >= gf.nz ? gf.nz - 1 : z);
+    const cx<T> v = a[(int64_t)zc * plane + col];
+    return ok ? v : cx<T>{};
+  };
   // prologue: u1(tb - 1) of the own points into its plane slot (only the own
-  // point of it is read), f and w/D of plane tb
+  // point of it is read); f and w/D of planes tb and tb + 1, D and the ring of
+  // plane tb
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
-    const bool okm = uin[i] && ok_plane(tb - 1), okc = uin[i] && ok_plane(tb);
+    const bool okm = uin[i] && ok_plane(tb - 1), okc = uin[i] && ok_plane(tb), okn = uin[i] && ok_plane(tb + 1);
     cx<T> fm[K];
-    ldKz<K, S, T>(f + ((int64_t)(tb - 1) * plane + ucol[i]) * gf.P + c, okm, fm);
-    const cx<T> wm = okm ? dw[(int64_t)(tb - 1) * plane + ucol[i]] : cx<T>{};
+    ld_f(tb - 1, ucol[i], okm, fm);
+    const cx<T> wm = ld_c(dw, tb - 1, ucol[i], okm);
     if (uon[i]) {
       const int o = ((uy[i] + 1) * RV + ux[i] + 1) * CG + sl * K;
 #pragma unroll
@@ -1198,9 +1224,17 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) fR[i][k] = cx<T>{};
-    ldKz<K, S, T>(f + ((int64_t)tb * plane + ucol[i]) * gf.P + c, okc, fA[i]);
-    wA[i] = okc ? dw[(int64_t)tb * plane + ucol[i]] : cx<T>{};
+    ld_f(tb, ucol[i], okc, fA[i]);
+    wA[i] = ld_c(dw, tb, ucol[i], okc);
+    ld_f(tb + 1, ucol[i], okn, fB[i]);
+    wB[i] = ld_c(dw, tb + 1, ucol[i], okn);
+    dA[i] = ld_c(dg, tb, ucol[i], okc);
     dR[i] = cx<T>{};
+  }
+  {
+    const bool ok = ringin && ok_plane(tb);
+    ld_f(tb, ringcol, ok, frA);
+    wrA = ld_c(dw, tb, ringcol, ok);
   }
   cx<T> accA[K], accB[K];
 #pragma unroll
@@ -1247,25 +1281,13 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   // and so are u2(t - 1) and the residual of plane t - 2 (written during the
   // previous plane), which is restricted first. Each buffer alternates by
   // plane parity, so what one plane writes is read after the next barrier.
+  // The barrier orders LDS only: every global load is issued one plane before
+  // its use and stays in flight across it.
   for (int t = tb; t <= te; ++t) {
     cx<T>* const sv = sv2[t & 1];        // u1(t)
     const cx<T>* const svm = sv2[(t - 1) & 1];  // u1(t - 1)
     cx<T>* const su = su2[(t - 1) & 1];  // u2(t - 1); u2(t) goes to the other slot
     const cx<T>* const sum2 = su2[t & 1];  // u2(t - 2)
-    // plane t + 1 of f and w/D (own points), D at t, and the u1 ring of t
-    cx<T> fr[K], wr{};
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const bool okn = uin[i] && ok_plane(t + 1), okc = uin[i] && ok_plane(t);
-      ldKz<K, S, T>(f + ((int64_t)(t + 1) * plane + ucol[i]) * gf.P + c, okn, fB[i]);
-      wB[i] = okn ? dw[(int64_t)(t + 1) * plane + ucol[i]] : cx<T>{};
-      dA[i] = okc ? dg[(int64_t)t * plane + ucol[i]] : cx<T>{};
-    }
-    if (ring) {
-      const bool ok = ringin && ok_plane(t);
-      ldKz<K, S, T>(f + ((int64_t)t * plane + ringcol) * gf.P + c, ok, fr);
-      wr = ok ? dw[(int64_t)t * plane + ringcol] : cx<T>{};
-    }
     // u1(t) into LDS: own points and the ring (the sweep from zero, w/D f)
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -1277,9 +1299,24 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     if (ring) {
       const int o = (hy * RV + hx) * CG + sl * K;
 #pragma unroll
-      for (int k = 0; k < K; ++k) sv[o + k] = wr * fr[k];
+      for (int k = 0; k < K; ++k) sv[o + k] = wrA * frA[k];
     }
-    __syncthreads();
+    // the loads of the next plane: its ring and D, f and w/D of plane t + 2
+    cx<T> frB[K], wrB{};
+    {
+      const bool ok = ringin && ok_plane(t + 1);
+      ld_f(t + 1, ringcol, ok, frB);
+      wrB = ld_c(dw, t + 1, ringcol, ok);
+    }
+    cx<T> fC[NT][K], wC[NT], dB[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const bool okn = uin[i] && ok_plane(t + 1), ok2 = uin[i] && ok_plane(t + 2);
+      dB[i] = ld_c(dg, t + 1, ucol[i], okn);
+      ld_f(t + 2, ucol[i], ok2, fC[i]);
+      wC[i] = ld_c(dw, t + 2, ucol[i], ok2);
+    }
+    lds_barrier();
     restrict_plane(t - 2, sr2[(t - 1) & 1]);
     // u2(t) on the 19 x 19 region: the second sweep, as the LDS-tiled sweep
     // forms it (0 outside the grid)
@@ -1349,13 +1386,19 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
       for (int k = 0; k < K; ++k) {
         fR[i][k] = fA[i][k];
         fA[i][k] = fB[i][k];
+        fB[i][k] = fC[i][k];
       }
       dR[i] = dA[i];
+      dA[i] = dB[i];
       wA[i] = wB[i];
+      wB[i] = wC[i];
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) frA[k] = frB[k];
+    wrA = wrB;
   }
   // the residual of the last plane, written before the loop ended
-  __syncthreads();
+  lds_barrier();
   restrict_plane(te - 1, sr2[te & 1]);
 }
 
