@@ -1141,11 +1141,15 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   const int sl = threadIdx.x & 3;                  // the same slot for all of a lane's tasks
   const int c = cgi * CG + sl * K;
   const int64_t plane = (int64_t)gf.nx * gf.ny;
+  // Addresses split into a plane part, the same for the whole workgroup (held
+  // in scalar registers), and a lane part fixed for the whole march: the
+  // element offsets of the lane's columns within a plane
+  const int64_t planeP = plane * gf.P, cplaneP = (int64_t)gc.nx * gc.ny * gc.P;
   // u2 tasks of this lane: point (ux, uy) of the 19 x 19 region (fine
   // (fx0 - 1 + ux, fy0 - 1 + uy)); the inner 17 x 17 are residual points
   int ux[NT], uy[NT];
   bool uon[NT], uin[NT], res[NT], own[NT];
-  int64_t ucol[NT];
+  int64_t ucol[NT], ucolP[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     const int task = threadIdx.x + PRR_L * i;
@@ -1159,6 +1163,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     // the u2 points this tile writes: its 16 x 16 core (every fine point once)
     own[i] = uin[i] && ux[i] >= 1 && ux[i] <= 2 * RT && uy[i] >= 1 && uy[i] <= 2 * RT;
     ucol[i] = uin[i] ? (int64_t)gy * gf.nx + gx : 0;
+    ucolP[i] = ucol[i] * gf.P + c;
   }
   // ring task of this lane (lanes 0 .. 4*NRV-1): u1-region coordinates (hx, hy)
   const int rp = threadIdx.x >> 2;
@@ -1180,11 +1185,13 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   const int gxr = fx0 - 2 + hx, gyr = fy0 - 2 + hy;
   const bool ringin = ring && gxr >= 0 && gxr < gf.nx && gyr >= 0 && gyr < gf.ny;
   const int64_t ringcol = ringin ? (int64_t)gyr * gf.nx + gxr : 0;
+  const int64_t ringcolP = ringcol * gf.P + c;
   // accumulation task (lanes 0..255): coarse node (ax, ay) of the tile
   const int aq = threadIdx.x >> 2;
   const int ax = aq % RT, ay = aq / RT;
   const int X = RT * xb + ax, Y = RT * yb + ay;
   const bool acc_on = threadIdx.x < 4 * RT * RT && X < gc.nx && Y < gc.ny;
+  const int64_t xyP = ((int64_t)Y * gc.nx + X) * gc.P + c;
   // per task: f at t - 1 (residual), t, t + 1; w/D at t, t + 1; D at t - 1
   // (residual) and t; the ring's f and w/D at t
   cx<T> fR[NT][K], fA[NT][K], fB[NT][K];
@@ -1197,9 +1204,9 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   // zeroed where it lies outside the grid or the lane has no such task: with
   // no load behind a branch, a wait for one plane's operands leaves the next
   // plane's loads in flight.
-  auto ld_f = [&](int z, int64_t col, bool ok, cx<T>* o) {
+  auto ld_f = [&](int z, int64_t colP, bool ok, cx<T>* o) {
     const int zc = z < 0 ? 0 : (z >= gf.nz ? gf.nz - 1 : z);
-    ldK<K, S, T>(f + ((int64_t)zc * plane + col) * gf.P + c, o);
+    ldK<K, S, T>(f + (int64_t)zc * planeP + colP, o);
 #pragma unroll
     for (int k = 0; k < K; ++k) o[k] = ok ? o[k] : cx<T>{};
   };
@@ -1215,7 +1222,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   for (int i = 0; i < NT; ++i) {
     const bool okm = uin[i] && ok_plane(tb - 1), okc = uin[i] && ok_plane(tb), okn = uin[i] && ok_plane(tb + 1);
     cx<T> fm[K];
-    ld_f(tb - 1, ucol[i], okm, fm);
+    ld_f(tb - 1, ucolP[i], okm, fm);
     const cx<T> wm = ld_c(dw, tb - 1, ucol[i], okm);
     if (uon[i]) {
       const int o = ((uy[i] + 1) * RV + ux[i] + 1) * CG + sl * K;
@@ -1224,16 +1231,16 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) fR[i][k] = cx<T>{};
-    ld_f(tb, ucol[i], okc, fA[i]);
+    ld_f(tb, ucolP[i], okc, fA[i]);
     wA[i] = ld_c(dw, tb, ucol[i], okc);
-    ld_f(tb + 1, ucol[i], okn, fB[i]);
+    ld_f(tb + 1, ucolP[i], okn, fB[i]);
     wB[i] = ld_c(dw, tb + 1, ucol[i], okn);
     dA[i] = ld_c(dg, tb, ucol[i], okc);
     dR[i] = cx<T>{};
   }
   {
     const bool ok = ringin && ok_plane(tb);
-    ld_f(tb, ringcol, ok, frA);
+    ld_f(tb, ringcolP, ok, frA);
     wrA = ld_c(dw, tb, ringcol, ok);
   }
   cx<T> accA[K], accB[K];
@@ -1265,8 +1272,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
         cx<T> outv[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) outv[k] = (T)0.125 * accA[k];
-        const int64_t I = ((int64_t)Zc * gc.ny + Y) * gc.nx + X;
-        st_own<K, SO, T>(rc + I * gc.P + c, outv);
+        st_own<K, SO, T>(rc + (int64_t)Zc * cplaneP + xyP, outv);
       }
     }
     if (!odd) {  // the plane opened on accB continues on accA
@@ -1305,7 +1311,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     cx<T> frB[K], wrB{};
     {
       const bool ok = ringin && ok_plane(t + 1);
-      ld_f(t + 1, ringcol, ok, frB);
+      ld_f(t + 1, ringcolP, ok, frB);
       wrB = ld_c(dw, t + 1, ringcol, ok);
     }
     cx<T> fC[NT][K], wC[NT], dB[NT];
@@ -1313,7 +1319,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     for (int i = 0; i < NT; ++i) {
       const bool okn = uin[i] && ok_plane(t + 1), ok2 = uin[i] && ok_plane(t + 2);
       dB[i] = ld_c(dg, t + 1, ucol[i], okn);
-      ld_f(t + 2, ucol[i], ok2, fC[i]);
+      ld_f(t + 2, ucolP[i], ok2, fC[i]);
       wC[i] = ld_c(dw, t + 2, ucol[i], ok2);
     }
     lds_barrier();
@@ -1340,7 +1346,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
         acc = acc - sum;
         u2c[i][k] = us + wA[i] * (fA[i][k] - acc);
       }
-      if (own[i] && t_own) stK<K, S, T>(u2o + ((int64_t)t * plane + ucol[i]) * gf.P + c, u2c[i]);
+      if (own[i] && t_own) stK<K, S, T>(u2o + (int64_t)t * planeP + ucolP[i], u2c[i]);
     }
     // the residual of plane t - 1 (u2 of t - 1 in LDS, of t - 2 and t in
     // registers), as k_resid_restrict forms it, into sr
