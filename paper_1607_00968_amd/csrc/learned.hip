@@ -22,6 +22,7 @@
 // of voxels and are summed in a fixed order (deterministic).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <vector>
@@ -67,6 +68,14 @@ struct ConvArgs {
   int flip, relu;
   const bf16* mask;  // out *= (mask[v][offm + n] > 0) when set
   int ldm, offm;
+  // A second input (the 16- and 32-channel kernels only): when in2 is set,
+  // input channels [C1, Cin) are channels [0, Cin - C1) of in2 (row stride
+  // ldi2), and channels [0, C1) come from in; with up1, in holds a grid of
+  // half the edge and voxel (x, y, z) reads its voxel (x/2, y/2, z/2), the
+  // nearest upsampling. A decoder layer thus reads its skip input and the
+  // upsampled coarser activations where they are, with no concatenated copy.
+  const bf16* in2;
+  int ldi2, C1, up1;
 };
 
 template <int NT>
@@ -302,15 +311,27 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
   for (int z = 0; z < CT_Z; ++z)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[z][nt] = float4_{0.f, 0.f, 0.f, 0.f};
+  const int dh = D / 2;  // edge of a half-resolution first input
+  const int64_t sbase_h = b * (int64_t)dh * dh * dh;
   for (int c0 = 0; c0 < a.Cin; c0 += CCH) {
     __syncthreads();
+    // the chunk's source: the second input, the half-resolution first input,
+    // or the first input
+    const bool second = a.in2 && c0 >= a.C1, half_res = !second && a.up1;
     for (int e = threadIdx.x; e < CH_V * 2; e += 256) {
       const int hv = e >> 1, half = e & 1;
       const int gx = x0 + hv % CH_X - 1, gy = y0 + (hv / CH_X) % CH_Y - 1, gz = z0 + hv / (CH_X * CH_Y) - 1;
       uint4 val{0u, 0u, 0u, 0u};
-      if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D)
-        val = *reinterpret_cast<const uint4*>(a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi +
-                                              a.offi + c0 + half * 8);
+      if (gx >= 0 && gx < D && gy >= 0 && gy < D && gz >= 0 && gz < D) {
+        const bf16* src;
+        if (second)
+          src = a.in2 + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi2 + (c0 - a.C1);
+        else if (half_res)
+          src = a.in + (sbase_h + (gx >> 1) + (int64_t)dh * ((gy >> 1) + (int64_t)dh * (gz >> 1))) * a.ldi + a.offi + c0;
+        else
+          src = a.in + (sbase + gx + (int64_t)D * (gy + (int64_t)D * gz)) * a.ldi + a.offi + c0;
+        val = *reinterpret_cast<const uint4*>(src + half * 8);
+      }
       lds_u4[halo_u4(hv) + half] = val;
     }
     if (WLDS)
@@ -320,12 +341,10 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
             *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
       }
     __syncthreads();
-#pragma unroll 1
-    for (int txy = 0; txy < 9; ++txy) {
-      const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
-      const int hoff = SG * dxt + CH_X * (SG * dyt);
-      const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
-      short4_ Bt[3][NT];  // z taps dz = -1, 0, 1
+    // B fragments of in-plane tap txy for the z taps dz = -1, 0, 1; read from
+    // the caches (16 output channels), those of the next tap are issued
+    // before this tap's MFMAs
+    auto load_b = [&](int txy, short4_ (&Bt)[3][NT]) {
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -333,6 +352,23 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
           Bt[k][nt] = WLDS ? *reinterpret_cast<const short4_*>(ws + wrow_el((txy + 9 * k) * N + nt * 16 + ml, kg))
                            : *reinterpret_cast<const short4_*>(
                                  a.W + (int64_t)((txy + 9 * k) * N + nt * 16 + ml) * a.Cin + c0 + kg * 4);
+    };
+    short4_ Bt[3][NT], Bn[3][NT];
+    if (!WLDS) load_b(0, Bn);
+#pragma unroll 1
+    for (int txy = 0; txy < 9; ++txy) {
+      const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
+      const int hoff = SG * dxt + CH_X * (SG * dyt);
+      const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
+      if (WLDS) {
+        load_b(txy, Bt);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) Bt[k][nt] = Bn[k][nt];
+        if (txy + 1 < 9) load_b(txy + 1, Bn);
+      }
 #pragma unroll
       for (int p = 0; p < CH_Z; ++p) {
         const short4_ A = *reinterpret_cast<const short4_*>(
@@ -468,6 +504,16 @@ static void conv3_lds_launch(const ConvArgs& a, hipStream_t s) {
 }
 
 static void conv3(const ConvArgs& a, hipStream_t s) {
+  if (a.in2 || a.up1) {
+    // two inputs: the z-reuse kernels only
+    if (a.Cin % CCH != 0 || (a.in2 && (a.C1 % CCH != 0 || a.C1 <= 0 || a.C1 >= a.Cin)) || (a.up1 && a.D % 2 != 0))
+      fatal_combo("conv3 second input");
+    switch (a.N / 16) {
+      case 1: a.flip ? conv3_zr_launch<1, 1>(a, s) : conv3_zr_launch<1, 0>(a, s); return;
+      case 2: a.flip ? conv3_zr_launch<2, 1>(a, s) : conv3_zr_launch<2, 0>(a, s); return;
+      default: fatal_combo("conv3 second input: output channels");
+    }
+  }
   if (a.Cin == 4 && a.N == 16 && a.ldi == 4 && a.offi == 0) {
     const int ntx = (a.D + CT_X - 1) / CT_X, nty = (a.D + CT_Y - 1) / CT_Y, ntz = (a.D + CT_Z - 1) / CT_Z;
     const int64_t ntiles = (int64_t)a.B * ntx * nty * ntz;
@@ -1262,9 +1308,60 @@ static void conv_bwd_weight(Net* n, int l, int B, int D, const bf16* x, int ldx,
   hipLaunchKernelGGL(k_bias_grad, dim3(Cout), dim3(256), 0, s, total, Cout, dy, Cout, 0, gW + nw);
 }
 
-static void run_forward(Net* n, int B, hipStream_t s) {
+// Decoder layer l reading the upsampled coarser activations `up` (C1
+// channels, row stride ldu, grid edge D / 2) and the skip activations `skip`
+// (row stride lds) as one input of C1 + (Cin - C1) channels, in that order.
+static void conv_fwd_up(Net* n, int l, int B, int D, const bf16* up, int ldu, int C1, const bf16* skip, int lds,
+                        bf16* out, int ldo, hipStream_t s) {
+  ConvArgs a{};
+  a.B = B;
+  a.D = D;
+  a.Cin = L_CIN[l];
+  a.N = L_COUT[l];
+  a.in = up;
+  a.ldi = ldu;
+  a.offi = 0;
+  a.up1 = 1;
+  a.in2 = skip;
+  a.ldi2 = lds;
+  a.C1 = C1;
+  a.W = n->Wf[l];
+  a.bias = n->p + layer_off(l) + 27LL * L_CIN[l] * L_COUT[l];
+  a.out = out;
+  a.ldo = ldo;
+  a.offo = 0;
+  a.flip = 0;
+  a.relu = 1;
+  conv3(a, s);
+}
+
+// The forward pass. With `concat` (training, whose backward pass reads the
+// decoder inputs as stored activations) the skip outputs s1, s2 go into
+// slices of c1, c2 and the upsampled activations are copied beside them;
+// without it (inference) s1 and s2 are stored densely in c1, c2 and the two
+// decoder layers that take them read the coarser activations and the skip
+// outputs directly. Both forms give every convolution the same values in
+// the same channel order, so their outputs are equal bit for bit.
+static void run_forward(Net* n, int B, hipStream_t s, bool concat) {
   const int D = n->D, d2 = D / 2, d4 = D / 4;
   const int64_t BV = (int64_t)B * n->V;
+  if (!concat) {
+    conv_fwd(n, 0, B, D, n->x0, 4, 0, n->a1, 16, 0, s);
+    conv_fwd(n, 1, B, D, n->a1, 16, 0, n->c1, 16, 0, s);  // s1, dense
+    hipLaunchKernelGGL(k_pool2, g1(BV / 8 * 2), dim3(256), 0, s, B, D, 16, (const bf16*)n->c1, 16, 0, n->p1, 16);
+    conv_fwd(n, 2, B, d2, n->p1, 16, 0, n->a2, 32, 0, s);
+    conv_fwd(n, 3, B, d2, n->a2, 32, 0, n->c2, 32, 0, s);  // s2, dense
+    hipLaunchKernelGGL(k_pool2, g1(BV / 64 * 4), dim3(256), 0, s, B, d2, 32, (const bf16*)n->c2, 32, 0, n->p2, 32);
+    conv_fwd(n, 4, B, d4, n->p2, 32, 0, n->a4, 64, 0, s);
+    conv_fwd(n, 5, B, d4, n->a4, 64, 0, n->a5, 64, 0, s);
+    conv_fwd_up(n, 6, B, d2, n->a5, 64, 64, n->c2, 32, n->a6, 32, s);
+    conv_fwd(n, 7, B, d2, n->a6, 32, 0, n->a7, 32, 0, s);
+    conv_fwd_up(n, 8, B, D, n->a7, 32, 32, n->c1, 16, n->a8, 16, s);
+    conv_fwd(n, 9, B, D, n->a8, 16, 0, n->a9, 16, 0, s);
+    hipLaunchKernelGGL(k_head_fwd, g1(BV), dim3(256), 0, s, BV, (const bf16*)n->a9,
+                       (const float*)(n->p + n->np - 34), (const float*)(n->p + n->np - 2), n->out);
+    return;
+  }
   conv_fwd(n, 0, B, D, n->x0, 4, 0, n->a1, 16, 0, s);
   conv_fwd(n, 1, B, D, n->a1, 16, 0, n->c1, 48, 32, s);  // s1 -> second slice of c1
   hipLaunchKernelGGL(k_pool2, g1(BV / 8 * 2), dim3(256), 0, s, B, D, 16, (const bf16*)n->c1, 48, 32, n->p1, 16);
@@ -1363,12 +1460,19 @@ static void run_loss_backward(Net* n, int B, const uint8_t* mask, float* loss_ds
   conv_bwd_weight(n, 0, B, D, n->x0, 4, 0, n->g0, s);
 }
 
+// HELM_NET_CONCAT=1 makes the inference passes take the training form of the
+// forward pass (the check that both forms agree)
+static bool concat_forward() {
+  const char* e = std::getenv("HELM_NET_CONCAT");
+  return e && e[0] == '1';
+}
+
 helm_status forward(Net* n, int B, const float* x, float* out, hipStream_t s) {
   if (B < 1 || B > n->Bmax) return fail(HELM_ERR_INVALID_ARG, "batch %d outside 1..%d", B, n->Bmax);
   if (!x || !out) return fail(HELM_ERR_INVALID_ARG, "null buffer");
   const int64_t BV = (int64_t)B * n->V;
   hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
-  run_forward(n, B, s);
+  run_forward(n, B, s, concat_forward());
   LCHECK(hipMemcpyAsync(out, n->out, 8 * BV, hipMemcpyDeviceToDevice, s));
   LCHECK(hipStreamSynchronize(s));
   LCHECK(hipGetLastError());
@@ -1384,7 +1488,7 @@ helm_status loss_grad(Net* n, int B, const float* x, const float* target, const 
   const int64_t BV = (int64_t)B * n->V;
   hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
   LCHECK(hipMemcpyAsync(n->tgt, target, 8 * BV, hipMemcpyDeviceToDevice, s));
-  run_forward(n, B, s);
+  run_forward(n, B, s, true);
   run_loss_backward(n, B, mask, n->lossd, s);
   LCHECK(hipMemcpyAsync(grad, n->g, 4 * n->np, hipMemcpyDeviceToDevice, s));
   float lf = 0.f;
@@ -1450,7 +1554,7 @@ static void apply_t(Net* n, int P, const S* f, S* out, hipStream_t s) {
     const int nb = std::min(n->Bmax, P - c0);
     hipLaunchKernelGGL(k_net_input<S>, g1((int64_t)nb * n->V), dim3(256), 0, s, P, c0, nb, n->D, n->box, f,
                        (const double*)n->sc, (const float*)n->dgn, n->x0);
-    run_forward(n, nb, s);
+    run_forward(n, nb, s, concat_forward());
     hipLaunchKernelGGL(k_net_output<S>, g1(n->Nc * nb), dim3(256), 0, s, P, c0, nb, n->D, n->box,
                        (const float*)n->out, (const double*)n->os, out, n->bad);
   }
@@ -1574,7 +1678,7 @@ helm_status train_step(Net* n, int B, const float* x, const float* target, const
   const int64_t BV = (int64_t)B * n->V;
   hipLaunchKernelGGL(k_f32_to_bf16, g1(BV * 4), dim3(256), 0, s, BV * 4, x, n->x0);
   LCHECK(hipMemcpyAsync(n->tgt, target, 8 * BV, hipMemcpyDeviceToDevice, s));
-  run_forward(n, B, s);
+  run_forward(n, B, s, true);
   run_loss_backward(n, B, mask, n->lossd, s);
   adam_update(n, lr, s);
   float lf = 0.f;
@@ -1618,7 +1722,7 @@ helm_status train(Net* n, int steps, int batch, double lr, uint64_t seed, double
     hipLaunchKernelGGL(k_gather_samples, g1(BV), dim3(256), 0, s, batch, (const int*)(n->idx + (size_t)k * batch),
                        (const float*)(n->rot + (size_t)2 * k * batch), n->V, (const bf16*)n->xs, (const float*)n->ts,
                        n->x0, n->tgt);
-    run_forward(n, batch, s);
+    run_forward(n, batch, s, true);
     run_loss_backward(n, batch, n->mask, n->hist + k, s);
     adam_update(n, lr, s);
   }

@@ -16,6 +16,8 @@ Parity against the FP64 CPU oracle of the network (oracle/conv_oracle.c):
 Solver-level tests: training lowers the loss, a trained network gives a
 convergent outer solve, and a non-finite network output falls back to GMRES.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -147,6 +149,59 @@ def test_loss_grad_matches_oracle(D, B):
     for l, e, c in prof:
         assert e <= 0.1 and c >= 0.995, (l, e, c)
     assert cosine(gg, gref) >= 0.999
+
+
+class ConcatForward:
+    """HELM_NET_CONCAT=1: the inference passes take the training form of the
+    forward pass (skip outputs stored in slices of concatenated buffers, the
+    upsampled activations copied beside them)."""
+
+    def __enter__(self):
+        os.environ["HELM_NET_CONCAT"] = "1"
+
+    def __exit__(self, *exc):
+        os.environ.pop("HELM_NET_CONCAT", None)
+
+
+@pytest.mark.parametrize("D,B", [(16, 3), (48, 2)])
+def test_inference_forward_equals_training_form(D, B):
+    """The inference forward feeds the two decoder layers from the skip
+    outputs and the coarser activations where they are (no concatenated
+    copy, no upsampled copy). Every convolution sees the same values in the
+    same channel order, so the output must not change by a bit. D = 48 is
+    the network edge at the 192^3 benchmark's coarsest grid."""
+    net = pk.helm_net_create(D, B, seed=7)
+    net.set_params(he_params())
+    x = cuda(RNG.standard_normal((B, D ** 3, 4)).astype(np.float32))
+    a = torch.empty((B, D ** 3, 2), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    net.forward(x, a)
+    with ConcatForward():
+        net.forward(x, b)
+    c = torch.empty_like(a)  # the default form again, after the other
+    net.forward(x, c)
+    torch.cuda.synchronize()
+    assert torch.isfinite(a).all()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_learned_coarse_solve_same_in_both_forward_forms():
+    """The in-cycle learned coarsest solve (network guess + GMRES) gives
+    bitwise the same correction with either form of the forward pass."""
+    p, hd = coarse_problem(32, 3)
+    nu = pk.helm_level_dims(hd, 2)
+    blob = pk.helm_net_create((max(nu) + 3) // 4 * 4, 4, seed=6).save()
+    hl = pk.helm_setup(p.dim, p.n, p.h, p.m, p.gamma, p.omega, shift=p.shift, levels=3,
+                       precision="mixed", coarse="learned", net=blob, coarse_iters=4)
+    nc = int(np.prod(nu))
+    R = cuda(RNG.standard_normal((4, nc)) + 1j * RNG.standard_normal((4, nc)), torch.complex128)
+    E1 = torch.empty_like(R)
+    E2 = torch.empty_like(R)
+    pk.helm_coarse_solve(hl, R, E1)
+    with ConcatForward():
+        pk.helm_coarse_solve(hl, R, E2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(E1).all() and torch.equal(E1, E2)
 
 
 def coarse_problem(n=32, levels=3, precision="fp64", seed_src=(2, 2)):
