@@ -36,6 +36,7 @@ namespace learned {
 typedef uint16_t bf16;
 typedef short short4_ __attribute__((ext_vector_type(4)));
 typedef float float4_ __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int NLAYER = 10;
 constexpr int L_CIN[NLAYER] = {4, 16, 16, 32, 32, 64, 96, 32, 48, 16};
@@ -280,13 +281,16 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty,
 // the 8x8 block) through all 4 output planes. For each in-plane tap offset it
 // walks the 6 halo planes once: every input fragment it reads from LDS feeds
 // the MFMAs of up to 3 output planes (one per z tap), which halves the LDS
-// reads of the plain form.
+// reads of the plain form. With 32 output channels each MFMA is gfx950's
+// K = 32 form and takes two in-plane taps at once (16 channels each), twice
+// the rate of the K = 16 one.
 template <int NT, int FLIP>
 __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
                                                   int64_t per) {
   extern __shared__ uint4 lds_u4[];
-  bf16* xs = reinterpret_cast<bf16*>(lds_u4);  // [CH_V][CCH], rows padded
-  bf16* ws = xs + CH_PAD_U4 * 8;               // [27][N][CCH] when staged
+  // LDS: the halo [CH_V][CCH] (rows padded) in CH_PAD_U4 16-byte units, then
+  // the weights [27][N][CCH] when staged
+  const bf16* xs = reinterpret_cast<const bf16*>(lds_u4);
   constexpr int N = NT * 16;
   constexpr int SG = FLIP ? -1 : 1;
   constexpr bool WLDS = NT >= 2;  // weights staged in LDS
@@ -341,67 +345,131 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
             *reinterpret_cast<const uint4*>(a.W + (int64_t)row * a.Cin + c0 + half * 8);
       }
     __syncthreads();
-    // B fragments of in-plane tap txy for the z taps dz = -1, 0, 1; read from
-    // the caches (16 output channels), those of the next tap are issued
-    // before this tap's MFMAs
-    auto load_b = [&](int txy, short4_ (&Bt)[3][NT]) {
+    if constexpr (NT == 1) {
+      // 16 output channels: one in-plane tap per MFMA (K = 16), the B
+      // fragments read from the caches, those of the next tap issued before
+      // this tap's MFMAs. This form keeps about 40 VGPRs (eight waves per
+      // SIMD); the K = 32 form below needs 80 and was slower here (254 -> 278
+      // us at Cin = 16), faster with 32 output channels.
+      auto load_b = [&](int txy, short4_ (&Bt)[3]) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          Bt[k][nt] = WLDS ? *reinterpret_cast<const short4_*>(ws + wrow_el((txy + 9 * k) * N + nt * 16 + ml, kg))
-                           : *reinterpret_cast<const short4_*>(
-                                 a.W + (int64_t)((txy + 9 * k) * N + nt * 16 + ml) * a.Cin + c0 + kg * 4);
-    };
-    short4_ Bt[3][NT], Bn[3][NT];
-    if (!WLDS) load_b(0, Bn);
+        for (int k = 0; k < 3; ++k)
+          Bt[k] = *reinterpret_cast<const short4_*>(a.W + (int64_t)((txy + 9 * k) * N + ml) * a.Cin + c0 + kg * 4);
+      };
+      short4_ Bt[3], Bn[3];  // z taps dz = -1, 0, 1
+      load_b(0, Bn);
 #pragma unroll 1
-    for (int txy = 0; txy < 9; ++txy) {
-      const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
-      const int hoff = SG * dxt + CH_X * (SG * dyt);
-      const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
-      if (WLDS) {
-        load_b(txy, Bt);
-      } else {
+      for (int txy = 0; txy < 9; ++txy) {
+        const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
+        const int hoff = SG * dxt + CH_X * (SG * dyt);
+        const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Bt[k] = Bn[k];
+        if (txy + 1 < 9) load_b(txy + 1, Bn);
+#pragma unroll
+        for (int p = 0; p < CH_Z; ++p) {
+          const short4_ A = *reinterpret_cast<const short4_*>(
+              xs + halo_el(hxy + hoff + CH_X * CH_Y * p, rxy + CH_Y * p) + kg * 4);
+#pragma unroll
+          for (int z = 0; z < CT_Z; ++z) {
+            const int dzin = p - 1 - z;  // input plane offset seen from output plane z
+            if (dzin < -1 || dzin > 1) continue;
+            acc[z][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Bt[SG * dzin + 1], A, acc[z][0], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      // Two in-plane taps per MFMA (v_mfma_f32_16x16x32_bf16, K = 32): in step j
+      // lane groups kg = 0, 1 take tap 2 j and kg = 2, 3 tap 2 j + 1 (none for
+      // j = 4: zeros), channels 8 (kg & 1) .. 8 (kg & 1) + 7 of the chunk, in the
+      // A and the B fragment alike. B rows come from LDS; those of step j + 1
+      // are read before step j's MFMAs, and step j's six A fragments (one per
+      // halo plane) before its first MFMA. Every load is issued by every lane
+      // (lanes without a tap read tap 8's and zero it), so none sits behind a
+      // branch.
+      const int hsel = kg & 1;
+      auto load_b = [&](int j, bf16x8 (&Bt)[3][NT]) {
+        const int tl = 2 * j + (kg >> 1);
+        const bool tv = tl < 9;
+        const int tc = tv ? tl : 8;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) Bt[k][nt] = Bn[k][nt];
-        if (txy + 1 < 9) load_b(txy + 1, Bn);
-      }
+          for (int nt = 0; nt < NT; ++nt) {
+            const int row = (tc + 9 * k) * N + nt * 16 + ml;
+            uint4 w = lds_u4[CH_PAD_U4 + wrow_u4(row, hsel)];
+            if (!tv) w = uint4{0u, 0u, 0u, 0u};
+            Bt[k][nt] = __builtin_bit_cast(bf16x8, w);
+          }
+      };
+      bf16x8 B2[2][3][NT];  // steps j and j + 1 by parity; z taps dz = -1, 0, 1
+      load_b(0, B2[0]);
 #pragma unroll
-      for (int p = 0; p < CH_Z; ++p) {
-        const short4_ A = *reinterpret_cast<const short4_*>(
-            xs + halo_el(hxy + hoff + CH_X * CH_Y * p, rxy + CH_Y * p) + kg * 4);
+      for (int j = 0; j < 5; ++j) {
+        bf16x8 (&Bt)[3][NT] = B2[j & 1];
+        if (j + 1 < 5) load_b(j + 1, B2[(j + 1) & 1]);
+        const int tl = 2 * j + (kg >> 1);  // this lane group's in-plane tap
+        const bool tv = tl < 9;
+        const int tc = tv ? tl : 8;
+        const int dxt = tc % 3 - 1, dyt = tc / 3 - 1;
+        const int v0 = hxy + SG * dxt + CH_X * (SG * dyt);  // halo voxel of the tap, plane 0
+        // plane p of voxel v0 is voxel v0 + CH_X CH_Y p, in halo row v0 / CH_X + CH_Y p
+        const uint4* ap = lds_u4 + halo_u4(v0) + hsel;
+        constexpr int PSTEP = 2 * CH_X * CH_Y + CH_Y;  // 16-byte units per halo plane
+        bf16x8 Av[CH_Z];
 #pragma unroll
-        for (int z = 0; z < CT_Z; ++z) {
-          const int dzin = p - 1 - z;  // input plane offset seen from output plane z
-          if (dzin < -1 || dzin > 1) continue;
-          const int k = SG * dzin + 1;
+        for (int p = 0; p < CH_Z; ++p) {
+          uint4 av = ap[PSTEP * p];
+          if (!tv) av = uint4{0u, 0u, 0u, 0u};
+          Av[p] = __builtin_bit_cast(bf16x8, av);
+        }
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-            acc[z][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bt[k][nt], acc[z][nt], 0, 0, 0);
+        for (int p = 0; p < CH_Z; ++p) {
+#pragma unroll
+          for (int z = 0; z < CT_Z; ++z) {
+            const int dzin = p - 1 - z;  // input plane offset seen from output plane z
+            if (dzin < -1 || dzin > 1) continue;
+            const int k = SG * dzin + 1;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[z][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bt[k][nt], Av[p], acc[z][nt], 0, 0, 0);
+          }
         }
       }
     }
   }
+  // The weights are the MFMA's A operand and the voxels its B operand, so
+  // lane (ml, kg) holds output channels 4 kg .. 4 kg + 3 (of each 16-channel
+  // tile) of voxel qa: one 8-byte store per output plane and tile.
+  const int gx = x0 + qa % CT_X, gy = y0 + qa / CT_X;
 #pragma unroll
-  for (int z = 0; z < CT_Z; ++z)
+  for (int z = 0; z < CT_Z; ++z) {
+    const int gz = z0 + z;
+    if (gx >= D || gy >= D || gz >= D) continue;
+    const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = wave * 16 + 4 * kg + j;
-      const int gx = x0 + q % CT_X, gy = y0 + q / CT_X, gz = z0 + z;
-      if (gx >= D || gy >= D || gz >= D) continue;
-      const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n0 = nt * 16 + 4 * kg;
+      uint2 mk{0xffffffffu, 0xffffffffu};  // BF16 pairs; all positive where no mask
+      if (a.mask) mk = *reinterpret_cast<const uint2*>(a.mask + v * a.ldm + a.offm + n0);
+      uint32_t o[2];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int n = nt * 16 + ml;
-        float rv = acc[z][nt][j] + (a.bias ? a.bias[n] : 0.f);
-        if (a.relu && !(rv > 0.f)) rv = 0.f;
-        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) rv = 0.f;
-        a.out[v * a.ldo + a.offo + n] = f2bf(rv);
+      for (int h = 0; h < 2; ++h) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int j = 2 * h + e;
+          float rv = acc[z][nt][j] + (a.bias ? a.bias[n0 + j] : 0.f);
+          if (a.relu && !(rv > 0.f)) rv = 0.f;
+          const uint32_t mw = h ? mk.y : mk.x;
+          if (a.mask && !(b2f((bf16)(e ? mw >> 16 : mw & 0xffffu)) > 0.f)) rv = 0.f;
+          packed |= (uint32_t)f2bf(rv) << (16 * e);
+        }
+        o[h] = packed;
       }
+      *reinterpret_cast<uint2*>(a.out + v * a.ldo + a.offo + n0) = uint2{o[0], o[1]};
     }
+  }
 }
 
 template <int NT, int FLIP>
