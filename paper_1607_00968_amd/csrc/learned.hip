@@ -540,26 +540,41 @@ __global__ __launch_bounds__(256) void k_conv3_c4(ConvArgs a, int ntx, int nty, 
       const short4_ A = ok ? __builtin_bit_cast(short4_, xs4[hb[mt] + toff]) : short4_{0, 0, 0, 0};
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv[nt], acc[mt][nt], 0, 0, 0);
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Bv[nt], A, acc[mt][nt], 0, 0, 0);
     }
   }
+  // weights as the MFMA's A operand, voxels as its B: lane (ml, kg) holds
+  // output channels 4 kg .. 4 kg + 3 of voxel (4 wave + mt) 16 + ml, one
+  // 8-byte store per M tile
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int mt = 0; mt < 4; ++mt) {
+    const int q = (wave * 4 + mt) * 16 + ml;
+    const int gx = x0 + q % CT_X, gy = y0 + (q / CT_X) % CT_Y, gz = z0 + q / (CT_X * CT_Y);
+    if (gx >= D || gy >= D || gz >= D) continue;
+    const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = (wave * 4 + mt) * 16 + 4 * kg + j;
-      const int gx = x0 + q % CT_X, gy = y0 + (q / CT_X) % CT_Y, gz = z0 + q / (CT_X * CT_Y);
-      if (gx >= D || gy >= D || gz >= D) continue;
-      const int64_t v = sbase + gx + (int64_t)D * (gy + (int64_t)D * gz);
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n0 = nt * 16 + 4 * kg;
+      uint2 mk{0xffffffffu, 0xffffffffu};  // BF16 pairs; all positive where no mask
+      if (a.mask) mk = *reinterpret_cast<const uint2*>(a.mask + v * a.ldm + a.offm + n0);
+      uint32_t o[2];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int n = nt * 16 + ml;
-        float rv = acc[mt][nt][j] + (a.bias ? a.bias[n] : 0.f);
-        if (a.relu && !(rv > 0.f)) rv = 0.f;
-        if (a.mask && !(b2f(a.mask[v * a.ldm + a.offm + n]) > 0.f)) rv = 0.f;
-        a.out[v * a.ldo + a.offo + n] = f2bf(rv);
+      for (int h = 0; h < 2; ++h) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int j = 2 * h + e;
+          float rv = acc[mt][nt][j] + (a.bias ? a.bias[n0 + j] : 0.f);
+          if (a.relu && !(rv > 0.f)) rv = 0.f;
+          const uint32_t mw = h ? mk.y : mk.x;
+          if (a.mask && !(b2f((bf16)(e ? mw >> 16 : mw & 0xffffu)) > 0.f)) rv = 0.f;
+          packed |= (uint32_t)f2bf(rv) << (16 * e);
+        }
+        o[h] = packed;
       }
+      *reinterpret_cast<uint2*>(a.out + v * a.ldo + a.offo + n0) = uint2{o[0], o[1]};
     }
+  }
 }
 
 template <int NT>
