@@ -37,6 +37,11 @@
  *    filled with 0xFF bytes (NaN in FP64, FP32 and BF16) instead of whatever
  *    the allocator returns, so a read of memory no kernel has written shows
  *    as a non-finite result. Results are otherwise unchanged.
+ *  - Check aid: with HELM_NET_CONCAT=1 (read at every network forward pass of
+ *    helm_net_forward and of the learned coarsest solve) the network's
+ *    inference pass takes the form its training pass uses, with the decoder
+ *    inputs copied into concatenated buffers; the outputs are bitwise equal
+ *    to the default form, which reads those inputs in place.
  */
 #ifndef HELM_H
 #define HELM_H
