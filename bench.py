@@ -73,6 +73,28 @@ def fine_kernel_bytes(prec, N, Nc, P):
     }
 
 
+# Algorithmic flops of the fused pre-smoothing per fine point and column:
+# u1 = (w/D) f (one complex product, 6), the second sweep (D u1, the six
+# neighbours scaled by 1/h^2, the update: 36), the residual f - M u2 (28) and
+# the restriction (27 weighted terms and a scaling per coarse node, 110 / 8).
+PRE_RR_FLOPS = 6 + 36 + 28 + 110 / 8
+
+
+def pre_rr_alu(prec, N, P, avg_s):
+    """The fused pre-smoothing against the vector ALU: its algorithmic flops
+    per launch over the measured time, against the published vector peak
+    (FP32 157.3, FP64 78.6 TFLOP/s, FMA counted twice, FP32 packed) and
+    against the 39.3 T lane operations per second (256 CUs x 4 SIMDs x 16
+    lanes x 2.4 GHz) that its instruction mix can issue: it runs without FMA
+    contraction (so that fused and unfused kernels round alike) and without
+    packed FP32, one flop per VALU lane operation."""
+    f = N * P * PRE_RR_FLOPS
+    tf = f / avg_s / 1e12
+    pub = 78.6 if prec == "fp64" else 157.3
+    return {"flops_per_launch": int(f), "achieved": round(tf, 2), "unit": "TFLOP/s", "peak_published": pub,
+            "frac_published": round(tf / pub, 4), "peak_lane_ops": 39.3, "frac_lane_ops": round(tf / 39.3, 4)}
+
+
 def committed_traffic(precision, n, nrhs, tile, kernel="fine_sweep"):
     """HBM bytes per launch of a finest-level kernel class from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summaries (scaled by the copy-kernel
@@ -561,6 +583,8 @@ def main():
             fine[k] = {"launches": launches, "avg_launch_ms": round(avg_s * 1e3, 4), "bytes_per_launch": int(byts),
                        "achieved": round(byts / avg_s / 1e9, 1), "frac": round(byts / avg_s / 1e9 / 8000.0, 4),
                        "total_ms": round(ms, 1)}
+    if "fine_pre_rr" in fine:
+        fine["fine_pre_rr"]["alu"] = pre_rr_alu(args.precision, N, P, fine["fine_pre_rr"]["avg_launch_ms"] / 1e3)
     dom = max(fine, key=lambda k: fine[k]["total_ms"])
     d = fine[dom]
     roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved"], "peak": 8000.0, "unit": "GB/s",

@@ -173,3 +173,16 @@ def test_kernel_classes_follow_the_header():
     names = [t.strip().split("=")[0].strip() for t in m.group(1).split(",") if t.strip()]
     assert names[-1] == "HELM_K_NCLASS"
     assert [n[len("HELM_K_"):].lower() for n in names[:-1]] == list(pk.KERNEL_CLASSES)
+
+
+def test_pre_rr_alu_figure():
+    """The fused pre-smoothing's ALU figure: 83.75 flops per fine point and
+    column (6 + 36 + 28 + 110/8), against 157.3 TFLOP/s published and 39.3 T
+    lane operations per second."""
+    import bench
+    assert bench.PRE_RR_FLOPS == 83.75
+    a = bench.pre_rr_alu("mixed", 1000, 64, 1e-3)
+    assert a["flops_per_launch"] == 1000 * 64 * 83.75
+    assert abs(a["achieved"] - 1000 * 64 * 83.75 / 1e-3 / 1e12) < 0.01
+    assert a["peak_published"] == 157.3 and a["peak_lane_ops"] == 39.3
+    assert bench.pre_rr_alu("fp64", 1000, 64, 1e-3)["peak_published"] == 78.6
