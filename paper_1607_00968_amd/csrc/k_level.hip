@@ -1100,15 +1100,18 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
 // 17 x 17 fine points, and u2 there needs u1 on 21 x 21. Marching through the
 // fine planes t, a workgroup forms u1(t) (LDS, with its ring), then u2(t) on
 // 19 x 19 (kept one plane in LDS for the residual's in-plane neighbours),
-// writes the u2 points the tile owns, and forms the residual of plane t - 1
-// with the restriction of k_resid_restrict. Every value is formed with the
-// operations, and in the order, of the sweep kernels and of
-// k_resid_restrict, so u2 and r_c are bitwise those of the unfused path;
-// u2 is written but never re-read, and f is read once.
+// writes the u2 points the tile owns, and forms the residual of plane t - 1,
+// which the restriction of k_resid_restrict takes up one plane later. Every
+// value is formed with the operations, and in the order, of the sweep
+// kernels and of k_resid_restrict, so u2 and r_c are bitwise those of the
+// unfused path; u2 is written but never re-read, and f is read once. Each
+// LDS plane is double-buffered, so one barrier per plane (ordering LDS only)
+// suffices, and every global load is issued one plane ahead of its use.
 // ---------------------------------------------------------------------------
 constexpr int RV = RU + 2;  // fine u1 points per axis (the ring of the u2 region)
-// Lanes per workgroup: 1024 for FP32 fields (two u2 tasks per lane, within
-// 128 VGPRs); FP64 fields need more registers per task and run 512 lanes.
+// Lanes per workgroup: 768 for FP32 fields (two u2 tasks per lane, about 140
+// VGPRs with the next plane's loads in flight; 1024 lanes, at 128 VGPRs,
+// spilled); FP64 fields need more registers per task and run 512 lanes.
 template <class T> constexpr int prr_lanes() { return sizeof(T) == 4 ? 768 : 512; }
 
 template <class S, class SO, class T, int PRR_L = prr_lanes<T>()>
