@@ -273,17 +273,19 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs a, int ntx, int nty,
 }
 
 // Same tiling with plane reuse, for NT <= 2. The halo is staged in LDS. With
-// 16 output channels the B fragments of the weights (27 x 16 rows of 32 B per
-// chunk, read by every workgroup) come from the caches, so that the LDS holds
+// 16 output channels the weight fragments (27 x 16 rows of 32 B per chunk,
+// read by every workgroup) come from the caches, so that the LDS holds
 // only the halo (20 KB: eight workgroups per CU; 463 -> 385 us per launch at
 // 48^3 x 64); with 32 they are staged in LDS next to it (reading them from
 // the caches was slower there, 130 -> 159 us). Wave w owns a 16-voxel xy patch (rows 2w, 2w+1 of
 // the 8x8 block) through all 4 output planes. For each in-plane tap offset it
 // walks the 6 halo planes once: every input fragment it reads from LDS feeds
 // the MFMAs of up to 3 output planes (one per z tap), which halves the LDS
-// reads of the plain form. With 32 output channels each MFMA is gfx950's
-// K = 32 form and takes two in-plane taps at once (16 channels each), twice
-// the rate of the K = 16 one.
+// reads of the plain form. The weights are each MFMA's A operand and the
+// voxels its B operand (so that a lane's results are four channels of one
+// voxel). With 32 output channels each MFMA is gfx950's K = 32 form and
+// takes two in-plane taps at once (16 channels each), twice the rate of the
+// K = 16 one.
 template <int NT, int FLIP>
 __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, int ntz, int64_t ntiles,
                                                   int64_t per) {
@@ -346,35 +348,35 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
       }
     __syncthreads();
     if constexpr (NT == 1) {
-      // 16 output channels: one in-plane tap per MFMA (K = 16), the B
+      // 16 output channels: one in-plane tap per MFMA (K = 16), the weight
       // fragments read from the caches, those of the next tap issued before
       // this tap's MFMAs. This form keeps about 40 VGPRs (eight waves per
       // SIMD); the K = 32 form below needs 80 and was slower here (254 -> 278
       // us at Cin = 16), faster with 32 output channels.
-      auto load_b = [&](int txy, short4_ (&Bt)[3]) {
+      auto load_w = [&](int txy, short4_ (&Wt)[3]) {
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          Bt[k] = *reinterpret_cast<const short4_*>(a.W + (int64_t)((txy + 9 * k) * N + ml) * a.Cin + c0 + kg * 4);
+          Wt[k] = *reinterpret_cast<const short4_*>(a.W + (int64_t)((txy + 9 * k) * N + ml) * a.Cin + c0 + kg * 4);
       };
-      short4_ Bt[3], Bn[3];  // z taps dz = -1, 0, 1
-      load_b(0, Bn);
+      short4_ Wt[3], Wn[3];  // z taps dz = -1, 0, 1
+      load_w(0, Wn);
 #pragma unroll 1
       for (int txy = 0; txy < 9; ++txy) {
         const int dxt = txy % 3 - 1, dyt = txy / 3 - 1;  // the tap's in-plane offsets
         const int hoff = SG * dxt + CH_X * (SG * dyt);
         const int rxy = (hxy + hoff) / CH_X;  // halo row of the tap's voxel in plane 0
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Bt[k] = Bn[k];
-        if (txy + 1 < 9) load_b(txy + 1, Bn);
+        for (int k = 0; k < 3; ++k) Wt[k] = Wn[k];
+        if (txy + 1 < 9) load_w(txy + 1, Wn);
 #pragma unroll
         for (int p = 0; p < CH_Z; ++p) {
-          const short4_ A = *reinterpret_cast<const short4_*>(
+          const short4_ Xf = *reinterpret_cast<const short4_*>(
               xs + halo_el(hxy + hoff + CH_X * CH_Y * p, rxy + CH_Y * p) + kg * 4);
 #pragma unroll
           for (int z = 0; z < CT_Z; ++z) {
             const int dzin = p - 1 - z;  // input plane offset seen from output plane z
             if (dzin < -1 || dzin > 1) continue;
-            acc[z][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Bt[SG * dzin + 1], A, acc[z][0], 0, 0, 0);
+            acc[z][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Wt[SG * dzin + 1], Xf, acc[z][0], 0, 0, 0);
           }
         }
       }
@@ -382,13 +384,13 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
       // Two in-plane taps per MFMA (v_mfma_f32_16x16x32_bf16, K = 32): in step j
       // lane groups kg = 0, 1 take tap 2 j and kg = 2, 3 tap 2 j + 1 (none for
       // j = 4: zeros), channels 8 (kg & 1) .. 8 (kg & 1) + 7 of the chunk, in the
-      // A and the B fragment alike. B rows come from LDS; those of step j + 1
-      // are read before step j's MFMAs, and step j's six A fragments (one per
-      // halo plane) before its first MFMA. Every load is issued by every lane
+      // weight and the voxel fragment alike. Weight rows come from LDS; those
+      // of step j + 1 are read before step j's MFMAs, and step j's six voxel
+      // fragments (one per halo plane) before its first MFMA. Every load is issued by every lane
       // (lanes without a tap read tap 8's and zero it), so none sits behind a
       // branch.
       const int hsel = kg & 1;
-      auto load_b = [&](int j, bf16x8 (&Bt)[3][NT]) {
+      auto load_w = [&](int j, bf16x8 (&Wt)[3][NT]) {
         const int tl = 2 * j + (kg >> 1);
         const bool tv = tl < 9;
         const int tc = tv ? tl : 8;
@@ -399,15 +401,15 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
             const int row = (tc + 9 * k) * N + nt * 16 + ml;
             uint4 w = lds_u4[CH_PAD_U4 + wrow_u4(row, hsel)];
             if (!tv) w = uint4{0u, 0u, 0u, 0u};
-            Bt[k][nt] = __builtin_bit_cast(bf16x8, w);
+            Wt[k][nt] = __builtin_bit_cast(bf16x8, w);
           }
       };
-      bf16x8 B2[2][3][NT];  // steps j and j + 1 by parity; z taps dz = -1, 0, 1
-      load_b(0, B2[0]);
+      bf16x8 W2[2][3][NT];  // steps j and j + 1 by parity; z taps dz = -1, 0, 1
+      load_w(0, W2[0]);
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        bf16x8 (&Bt)[3][NT] = B2[j & 1];
-        if (j + 1 < 5) load_b(j + 1, B2[(j + 1) & 1]);
+        bf16x8 (&Wt)[3][NT] = W2[j & 1];
+        if (j + 1 < 5) load_w(j + 1, W2[(j + 1) & 1]);
         const int tl = 2 * j + (kg >> 1);  // this lane group's in-plane tap
         const bool tv = tl < 9;
         const int tc = tv ? tl : 8;
@@ -416,12 +418,12 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
         // plane p of voxel v0 is voxel v0 + CH_X CH_Y p, in halo row v0 / CH_X + CH_Y p
         const uint4* ap = lds_u4 + halo_u4(v0) + hsel;
         constexpr int PSTEP = 2 * CH_X * CH_Y + CH_Y;  // 16-byte units per halo plane
-        bf16x8 Av[CH_Z];
+        bf16x8 Xv[CH_Z];
 #pragma unroll
         for (int p = 0; p < CH_Z; ++p) {
           uint4 av = ap[PSTEP * p];
           if (!tv) av = uint4{0u, 0u, 0u, 0u};
-          Av[p] = __builtin_bit_cast(bf16x8, av);
+          Xv[p] = __builtin_bit_cast(bf16x8, av);
         }
 #pragma unroll
         for (int p = 0; p < CH_Z; ++p) {
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(256) void k_conv3_zr(ConvArgs a, int ntx, int nty, 
             const int k = SG * dzin + 1;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-              acc[z][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bt[k][nt], Av[p], acc[z][nt], 0, 0, 0);
+              acc[z][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wt[k][nt], Xv[p], acc[z][nt], 0, 0, 0);
           }
         }
       }
