@@ -46,15 +46,6 @@ template <int K, class S, class T> __device__ inline void ldKz(const S* p, bool 
     for (int k = 0; k < K; ++k) o[k] = {(T)0, (T)0};
   }
 }
-// A workgroup barrier that orders LDS accesses only. __syncthreads() also
-// waits for every outstanding global load of the lane; this one lets loads
-// issued before it (operands of a later step that no other lane writes) stay
-// in flight across it.
-__device__ inline void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 template <int K, class S, class T> __device__ inline void stK(S* p, const cx<T>* o) {
 #pragma unroll
   for (int k = 0; k < K; k += St<S>::R) st16<T>(p + k, o + k);
@@ -1105,8 +1096,8 @@ static void resid_restrict_launch(const Geo& gf, const Geo& gc, const void* u, c
 // value is formed with the operations, and in the order, of the sweep
 // kernels and of k_resid_restrict, so u2 and r_c are bitwise those of the
 // unfused path; u2 is written but never re-read, and f is read once. Each
-// LDS plane is double-buffered, so one barrier per plane (ordering LDS only)
-// suffices, and every global load is issued one plane ahead of its use.
+// LDS plane is double-buffered, so one barrier per plane suffices, and every
+// global load is issued one plane ahead of its use.
 // ---------------------------------------------------------------------------
 constexpr int RV = RU + 2;  // fine u1 points per axis (the ring of the u2 region)
 // Lanes per workgroup: 768 for FP32 fields (two u2 tasks per lane, about 140
@@ -1290,8 +1281,8 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
   // and so are u2(t - 1) and the residual of plane t - 2 (written during the
   // previous plane), which is restricted first. Each buffer alternates by
   // plane parity, so what one plane writes is read after the next barrier.
-  // The barrier orders LDS only: every global load is issued one plane before
-  // its use and stays in flight across it.
+  // Every global load is issued one plane before its use and stays in flight
+  // across the barrier, which waits for the workgroup's LDS operations only.
   for (int t = tb; t <= te; ++t) {
     cx<T>* const sv = sv2[t & 1];        // u1(t)
     const cx<T>* const svm = sv2[(t - 1) & 1];  // u1(t - 1)
@@ -1325,7 +1316,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
       ld_f(t + 2, ucolP[i], ok2, fC[i]);
       wC[i] = ld_c(dw, t + 2, ucol[i], ok2);
     }
-    lds_barrier();
+    __syncthreads();
     restrict_plane(t - 2, sr2[(t - 1) & 1]);
     // u2(t) on the 19 x 19 region: the second sweep, as the LDS-tiled sweep
     // forms it (0 outside the grid)
@@ -1407,7 +1398,7 @@ __global__ __launch_bounds__(PRR_L) void k_pre_rr(Geo gf, Geo gc, int ncg, int n
     wrA = wrB;
   }
   // the residual of the last plane, written before the loop ended
-  lds_barrier();
+  __syncthreads();
   restrict_plane(te - 1, sr2[te & 1]);
 }
 
